@@ -1,0 +1,167 @@
+"""Dense definitions of the paper's objects for tiny graphs (oracle).
+
+TEST INFRASTRUCTURE ONLY.  Every matrix is formed explicitly from its
+definition, in FP64 numpy, so that a reader can check it against the paper:
+
+  * L_G = B^T W B (Sec. 2.1);
+  * P_{k}^{k+1}(i, j) = 1 iff node i is in aggregate j; P^k = P_1^2 ... P_{k-1}^k
+    (Eq. def:P); P(mu) = [I, -mu P^2, mu^2 P^3, ...] (Sec. 2.2);
+  * L_G~ = P(mu)^T L_G P(mu) (Eq. def:L_ell);
+  * H~: the positively weighted edges of G~, i.e. the negative off-diagonal
+    entries of L_G~, with the diagonal recomputed as a Laplacian (Sec. 3.2);
+  * T~ (MSP): from H~ keep the top-level edges, the links between a node and
+    its own aggregate on the next level, and the edges inside aggregates
+    (Sec. 3.3; reading stated in the design notes);
+  * kappa(pinv(B) A): largest over smallest nonzero eigenvalue (Sec. 3.2).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def laplacian(n, u, v, w):
+    """L_G = B^T W B from the incidence matrix B (one row per edge)."""
+    m = len(u)
+    B = np.zeros((m, n))
+    B[np.arange(m), u] = 1.0
+    B[np.arange(m), v] = -1.0
+    return B.T @ np.diag(np.asarray(w, dtype=np.float64)) @ B
+
+
+def prolongation(agg, nc):
+    """P_{k}^{k+1}(i, j) = 1 if node i is in aggregate j."""
+    P = np.zeros((len(agg), nc))
+    P[np.arange(len(agg)), agg] = 1.0
+    return P
+
+
+def composite(aggs, n):
+    """[P^1 = I, P^2, ..., P^l] with P^(k+1) = P^k P_k^(k+1)."""
+    Ps = [np.eye(n)]
+    for a in aggs:
+        nc = int(np.max(a)) + 1
+        Ps.append(Ps[-1] @ prolongation(a, nc))
+    return Ps
+
+
+def p_mu(aggs, n, mu):
+    """P(mu) = [I, (-mu) P^2, (-mu)^2 P^3, ..., (-mu)^(l-1) P^l]."""
+    Ps = composite(aggs, n)
+    return np.hstack([(-mu) ** k * P for k, P in enumerate(Ps)])
+
+
+def level_sizes(aggs, n):
+    return [n] + [int(np.max(a)) + 1 for a in aggs]
+
+
+def expanded(L, Pmu):
+    """L_G~ = P(mu)^T L_G P(mu)."""
+    return Pmu.T @ L @ Pmu
+
+
+def positive_subgraph(Gt):
+    """H~: keep the off-diagonal entries < 0 (positive edges); diagonal =
+    minus the sum of the kept off-diagonals of the row."""
+    off = Gt - np.diag(np.diag(Gt))
+    H = np.where(off < 0.0, off, 0.0)
+    H[np.diag_indices_from(H)] = -H.sum(axis=1)
+    return H
+
+
+def negative_part(Gt):
+    """L_mu^-: Laplacian of the dropped (negatively weighted) edges, so that
+    L_G~ = L_H~ - L_mu^- (Lemma lem:upper)."""
+    off = Gt - np.diag(np.diag(Gt))
+    N = np.where(off > 0.0, -off, 0.0)
+    N[np.diag_indices_from(N)] = -N.sum(axis=1)
+    return N
+
+
+def level_of(sizes):
+    return np.concatenate([np.full(s, k) for k, s in enumerate(sizes)])
+
+
+def msp_from_h(H, aggs, sizes):
+    """T~ extracted from H~: edges inside an aggregate on every level below
+    the top, links (i, agg(i)) between adjacent levels, all top-level edges."""
+    nt = sum(sizes)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    lev = level_of(sizes)
+    local = np.arange(nt) - offs[lev]
+    top = len(sizes) - 1
+    keep = np.zeros((nt, nt), dtype=bool)
+    for i in range(nt):
+        for j in range(nt):
+            if i == j or H[i, j] == 0.0:
+                continue
+            ki, kj = lev[i], lev[j]
+            if ki == kj:
+                if ki == top or aggs[ki][local[i]] == aggs[ki][local[j]]:
+                    keep[i, j] = True
+            elif kj == ki + 1 and aggs[ki][local[i]] == local[j]:
+                keep[i, j] = keep[j, i] = True
+    T = np.where(keep, H, 0.0)
+    T[np.diag_indices_from(T)] = 0.0
+    T[np.diag_indices_from(T)] = -T.sum(axis=1)
+    return T
+
+
+def edges_to_dense(nt, u, v, w):
+    """Laplacian of an edge list (used for oracle-built T~)."""
+    A = np.zeros((nt, nt))
+    for a, b, c in zip(u, v, w):
+        A[a, b] -= c
+        A[b, a] -= c
+        A[a, a] += c
+        A[b, b] += c
+    return A
+
+
+def pencil_eigs(A, B):
+    """Eigenvalues of pinv(B) A for Laplacians A, B with null(B) = span{1}
+    and A 1 = 0.
+
+    With D = diag(B)^(-1/2), the pencil (D A D, D B D + u u^T), u = D^-1 1,
+    has eigenvalue 0 on u and, on the D B D-orthogonal complement of u,
+    exactly the eigenvalues of B v = lambda^-1 A v restricted to 1-perp,
+    i.e. those of pinv(B) A.  The congruence by D changes no eigenvalue; it
+    only keeps the entries O(1) when the levels are scaled by mu^(2k)."""
+    d = 1.0 / np.sqrt(np.diag(B))
+    u = 1.0 / d
+    u /= np.linalg.norm(u)
+    As = d[:, None] * A * d[None, :]
+    Bs = d[:, None] * B * d[None, :]
+    return sla.eigh(As, Bs + np.outer(u, u), eigvals_only=True)
+
+
+def kappa(A, B, rel=1e-9):
+    """kappa(pinv(B) A) = lambda_max / smallest nonzero lambda."""
+    ev = np.abs(pencil_eigs(A, B))
+    nz = ev[ev > rel * ev.max()]
+    return nz.max() / nz.min()
+
+
+def pinv_solve_operator(T, Pmu):
+    """P(mu) pinv(L_T~) P(mu)^T with the mean removed on both sides."""
+    n = Pmu.shape[0]
+    M = Pmu @ np.linalg.pinv(T) @ Pmu.T
+    J = np.eye(n) - np.ones((n, n)) / n
+    return J @ M @ J
+
+
+def stretch(T, H):
+    """Total stretch of H's edges in T (Eqs. def:stretch-edge/graph), with
+    the tree distance taken as the effective resistance through T (for a
+    tree it is the path sum of 1/w; for the sparsifier it is a lower bound
+    of the lightest path sum used by the paper)."""
+    Tp = np.linalg.pinv(T)
+    nt = T.shape[0]
+    total = 0.0
+    for i in range(nt):
+        for j in range(i + 1, nt):
+            if H[i, j] < 0.0:
+                e = np.zeros(nt)
+                e[i], e[j] = 1.0, -1.0
+                total += -H[i, j] * (e @ Tp @ e)
+    return total
