@@ -1,0 +1,193 @@
+/*
+ * lap.h - C ABI of the MI355X (gfx950) Laplacian solver: preconditioned
+ * conjugate gradients on a weighted graph Laplacian L_G, preconditioned by
+ * the multilevel sparsifier preconditioner (MSP) of Hu & Lin, "Solving Graph
+ * Laplacians via Multilevel Sparsifiers" (arXiv 2207.07847), Sec. 3.3, or
+ * left unpreconditioned.
+ *
+ * Problem (Sec. 1, Sec. 2.1): G = (E, V, w) simply connected with positive
+ * weights, L_G = B^T W B symmetric positive semidefinite with null space
+ * span{1}.  lap_solve returns the mean-free x with L_G x = b - mean(b).
+ *
+ * Conventions
+ *   - Every function returns a lap_status (0 = LAP_OK); nothing throws or
+ *     aborts across this boundary.  lap_status_str names a code.
+ *   - Host pointers are read only during the call and stay owned by the
+ *     caller.  Device pointers are hipMalloc'ed (or torch) memory on the
+ *     current device; the library reads/writes them on the given stream.
+ *   - "stream" is a hipStream_t passed as void* (NULL = default stream).
+ *   - A hierarchy owns its device memory until lap_free.  It holds one solve
+ *     workspace: calls that use the same hierarchy must not overlap in time
+ *     (issue them from one host thread; any stream is fine).
+ */
+#ifndef LAP_H
+#define LAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LAP_OK = 0,
+    LAP_EINVAL = 1,         /* invalid argument or graph */
+    LAP_EDISCONNECTED = 2,  /* graph has more than one component */
+    LAP_ENOMEM = 3,         /* host or device allocation failed */
+    LAP_EDEVICE = 4,        /* HIP runtime error, or no device */
+    LAP_ENOCONV = 5,        /* max_iter reached; x and info still written */
+    LAP_EBREAKDOWN = 6,     /* p^T L p <= 0 or a non-finite value */
+    LAP_EUNSUPPORTED = 7    /* valid but not supported by this build */
+} lap_status;
+
+typedef enum {
+    LAP_PREC_MSP = 0,       /* multilevel sparsifier preconditioner, Sec. 3.3 */
+    LAP_PREC_PEGP = 1,      /* positive expanded graph, Sec. 3.2 (reserved) */
+    LAP_PREC_NONE = 2       /* plain conjugate gradients */
+} lap_precond;
+
+typedef enum {
+    LAP_FP64 = 0            /* all arithmetic in double precision */
+} lap_precision;
+
+/* Flags for lap_params.flags */
+#define LAP_FLAG_HOST_ONLY 1u  /* lap_setup builds the host hierarchy only:
+                                  export/info calls work, solves return
+                                  LAP_EUNSUPPORTED; no device is touched. */
+
+/* Undirected weighted graph, host memory, edges (u[e], v[e], w[e]).
+ * Requirements: n >= 2; 0 <= u, v < n; u != v; w finite and > 0.
+ * Parallel edges are merged by summing their weights. */
+typedef struct {
+    int64_t n;
+    int64_t m;
+    const int64_t *u;
+    const int64_t *v;
+    const double *w;
+} lap_graph;
+
+typedef struct {
+    double mu;            /* level weight 0 < mu < 1 of P(mu) (Sec. 2.2) */
+    int32_t max_levels;   /* 0 = level max (Sec. 3.2); else at most this many */
+    int32_t n_top;        /* coarsen while a level has more nodes (default 2) */
+    uint64_t mwm_seed;    /* 0 = natural visit order; else seeded random order */
+    int32_t precond;      /* lap_precond */
+    int32_t precision;    /* lap_precision */
+    int32_t max_iter;     /* iteration cap of lap_solve (default 1000) */
+    uint32_t flags;       /* LAP_FLAG_* */
+} lap_params;
+
+typedef struct {
+    int32_t iterations;        /* products with L_G performed */
+    int32_t refinements;       /* outer refinement steps (0 for FP64) */
+    double relres_true;        /* ||b^ - L_G x|| / ||b^|| in FP64, b^ = b - mean(b) */
+    double relres_recursive;   /* ||r_k|| / ||b^|| of the PCG recurrence */
+    double seconds;            /* host wall time of the call */
+    int32_t status;            /* lap_status of this right-hand side */
+    int32_t pad;
+} lap_solve_info;
+
+#define LAP_MAX_LEVELS 64
+typedef struct {
+    int32_t nlev;                 /* levels, fine (0) to top (nlev-1) */
+    int32_t tail_level;           /* first level handled by the one-block tail */
+    int64_t sizes[LAP_MAX_LEVELS];/* nodes per level */
+    int64_t ntilde;               /* sum of sizes: nodes of the expanded graph */
+    int64_t nnz;                  /* stored adjacency entries of L_G (2m) */
+    int64_t device_bytes;         /* device memory held by the hierarchy */
+    double setup_seconds;         /* host time spent in lap_setup */
+} lap_hierarchy_desc;
+
+typedef struct lap_hierarchy lap_hierarchy;
+
+/* Defaults: mu 0.8, level max, n_top 2, natural order, MSP, FP64,
+ * max_iter 1000, no flags.  Errors: LAP_EINVAL if p is NULL. */
+lap_status lap_default_params(lap_params *p);
+
+/* Host setup (Sec. 2.2, Sec. 3.3) then upload on `stream`.
+ *   1. validate and build the symmetric adjacency (parallel edges summed in
+ *      input order); reject a disconnected graph (LAP_EDISCONNECTED);
+ *   2. aggregate each level by maximal weighted matching (visit order per
+ *      mwm_seed; an unaggregated vertex pairs with its heaviest unaggregated
+ *      neighbour, ties to the smaller id; leftovers join their heaviest
+ *      neighbour's aggregate) and form the coarse graph P^T L P;
+ *   3. derive the MSP coefficients: per aggregate the local solve of its
+ *      sparsifier block, per level the weight theta_j, the top-level
+ *      pseudo-inverse; renumber the levels so aggregates are contiguous;
+ *   4. copy everything to the device.
+ * On success *out owns the hierarchy.  Errors: LAP_EINVAL (bad graph or
+ * params: mu outside (0,1), n_top < 2, unknown precond/precision),
+ * LAP_EDISCONNECTED, LAP_ENOMEM, LAP_EDEVICE, LAP_EUNSUPPORTED (top level
+ * larger than the on-chip coarse solve allows, or PEGP requested). */
+lap_status lap_setup(const lap_graph *g, const lap_params *p, void *stream,
+                     lap_hierarchy **out);
+
+/* Preconditioned CG on L_G x = b (Sec. 4 solves the equivalent expanded
+ * system; the Theorem of Sec. 3.1 maps it back).  b, x: device arrays of
+ * nrhs columns with leading dimension ld >= n (column c at b + c*ld),
+ * original vertex order.  x is overwritten with the mean-free solution.
+ * Stops when ||r_k|| <= tol ||b^||.  info: host array of nrhs entries (may
+ * be NULL).  Returns the worst per-column status: LAP_ENOCONV when
+ * max_iter is reached, LAP_EBREAKDOWN, LAP_EINVAL (tol <= 0, nrhs < 1,
+ * ld < n, non-finite b), LAP_EDEVICE. */
+lap_status lap_solve(lap_hierarchy *h, const double *b, double *x,
+                     int32_t nrhs, int64_t ld, double tol,
+                     lap_solve_info *info, void *stream);
+
+/* y = L_G x on the device (original order).  Errors: LAP_EINVAL,
+ * LAP_EDEVICE, LAP_EUNSUPPORTED for a host-only hierarchy. */
+lap_status lap_apply_laplacian(lap_hierarchy *h, const double *x, double *y,
+                               void *stream);
+
+/* z = M r - mean, the MSP preconditioner of Sec. 3.3 applied through the
+ * lifting of Sec. 3.1: M = P(mu) L_T~^+ P(mu)^T.  r must be mean-free (a
+ * residual).  Device arrays, original order. */
+lap_status lap_apply_precond(lap_hierarchy *h, const double *r, double *z,
+                             void *stream);
+
+/* Kernel timing for roofline reports.  Launches the chosen part of one PCG
+ * iteration `reps` times on `stream` between two HIP events, on the
+ * hierarchy's own workspace (its contents are overwritten; the next
+ * lap_solve reinitialises it), and returns the average milliseconds per
+ * launch and the algorithmic HBM bytes one launch must move:
+ *   LAP_KERNEL_SPMV     p update + q = L p + p^T q   (32 n + 12 nnz bytes)
+ *   LAP_KERNEL_UPDATE   x, r update + level-0 restriction and pair solves
+ *   LAP_KERNEL_DOWN0    level-0 prolongation + z, r^T z reductions
+ *   LAP_KERNEL_PRECOND  the whole preconditioner sequence (all levels)
+ *   LAP_KERNEL_ITER     one whole PCG iteration
+ * Errors: LAP_EINVAL (bad id, reps < 1), LAP_EUNSUPPORTED (host-only or a
+ * kernel the hierarchy does not use), LAP_EDEVICE. */
+enum { LAP_KERNEL_SPMV = 0, LAP_KERNEL_UPDATE = 1, LAP_KERNEL_DOWN0 = 2,
+       LAP_KERNEL_PRECOND = 3, LAP_KERNEL_ITER = 4 };
+lap_status lap_profile_kernel(lap_hierarchy *h, int32_t kernel, int32_t reps,
+                              void *stream, double *avg_ms, double *alg_bytes);
+
+/* Sizes and memory of a hierarchy.  Errors: LAP_EINVAL on NULL. */
+lap_status lap_hierarchy_info(const lap_hierarchy *h, lap_hierarchy_desc *d);
+
+/* Integer outputs of level `level` (0 = fine) for 0 <= level < nlev-1, in
+ * the level's own numbering (aggregate ids in pair-creation order):
+ * agg[i] = aggregate of node i on level+1, matched[i] = 1 if i was paired
+ * by the matching, 0 if it joined as a leftover.  Host arrays of
+ * sizes[level] entries; either may be NULL.  Errors: LAP_EINVAL. */
+lap_status lap_export_level(const lap_hierarchy *h, int32_t level,
+                            int64_t *agg, int8_t *matched);
+
+/* Graph of level `level` (0 <= level < nlev) as symmetric CSR in that
+ * level's numbering, neighbours ascending: ptr (sizes[level]+1), col and w
+ * (ptr[last] entries).  Pass col = w = NULL to query ptr only.  Host
+ * arrays.  Errors: LAP_EINVAL. */
+lap_status lap_export_graph(const lap_hierarchy *h, int32_t level,
+                            int64_t *ptr, int64_t *col, double *w);
+
+/* Release the hierarchy and its device memory (NULL is a no-op). */
+void lap_free(lap_hierarchy *h);
+
+/* Static string naming a status. */
+const char *lap_status_str(lap_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

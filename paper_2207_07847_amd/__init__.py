@@ -1,0 +1,185 @@
+"""Python binding of liblapgpu.so, the MI355X MSP-preconditioned Laplacian
+solver (Hu & Lin, arXiv 2207.07847).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  Functions carry the C names of include/lap.h.  Device
+buffers are passed as integer addresses (``tensor.data_ptr()``) and streams
+as integer handles (``torch.cuda.current_stream().cuda_stream``); PyTorch is
+used by callers for device memory and streams only.
+
+Importing this module raises if the compiled library is missing: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblapgpu.so")
+
+LAP_OK, LAP_EINVAL, LAP_EDISCONNECTED, LAP_ENOMEM, LAP_EDEVICE, LAP_ENOCONV, \
+    LAP_EBREAKDOWN, LAP_EUNSUPPORTED = range(8)
+LAP_PREC_MSP, LAP_PREC_PEGP, LAP_PREC_NONE = 0, 1, 2
+LAP_FP64 = 0
+LAP_FLAG_HOST_ONLY = 1
+LAP_MAX_LEVELS = 64
+LAP_KERNEL_SPMV, LAP_KERNEL_UPDATE, LAP_KERNEL_DOWN0, LAP_KERNEL_PRECOND, LAP_KERNEL_ITER = range(5)
+
+
+class lap_graph(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("u", C.POINTER(C.c_int64)),
+                ("v", C.POINTER(C.c_int64)), ("w", C.POINTER(C.c_double))]
+
+
+class lap_params(C.Structure):
+    _fields_ = [("mu", C.c_double), ("max_levels", C.c_int32), ("n_top", C.c_int32),
+                ("mwm_seed", C.c_uint64), ("precond", C.c_int32), ("precision", C.c_int32),
+                ("max_iter", C.c_int32), ("flags", C.c_uint32)]
+
+
+class lap_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("refinements", C.c_int32),
+                ("relres_true", C.c_double), ("relres_recursive", C.c_double),
+                ("seconds", C.c_double), ("status", C.c_int32), ("pad", C.c_int32)]
+
+
+class lap_hierarchy_desc(C.Structure):
+    _fields_ = [("nlev", C.c_int32), ("tail_level", C.c_int32),
+                ("sizes", C.c_int64 * LAP_MAX_LEVELS), ("ntilde", C.c_int64),
+                ("nnz", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2207_07847_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.lap_default_params.argtypes = [C.POINTER(lap_params)]
+    L.lap_setup.argtypes = [C.POINTER(lap_graph), C.POINTER(lap_params), vp, C.POINTER(vp)]
+    L.lap_solve.argtypes = [vp, vp, vp, C.c_int32, C.c_int64, C.c_double,
+                            C.POINTER(lap_solve_info), vp]
+    L.lap_apply_laplacian.argtypes = [vp, vp, vp, vp]
+    L.lap_apply_precond.argtypes = [vp, vp, vp, vp]
+    L.lap_hierarchy_info.argtypes = [vp, C.POINTER(lap_hierarchy_desc)]
+    L.lap_export_level.argtypes = [vp, C.c_int32, vp, vp]
+    L.lap_export_graph.argtypes = [vp, C.c_int32, vp, vp, vp]
+    L.lap_profile_kernel.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
+    L.lap_free.argtypes = [vp]
+    L.lap_free.restype = None
+    L.lap_status_str.argtypes = [C.c_int]
+    L.lap_status_str.restype = C.c_char_p
+    for f in ("lap_default_params", "lap_setup", "lap_solve", "lap_apply_laplacian",
+              "lap_apply_precond", "lap_hierarchy_info", "lap_export_level", "lap_export_graph",
+              "lap_profile_kernel"):
+        getattr(L, f).restype = C.c_int
+    return L
+
+
+_lib = _load()
+
+
+class LapError(RuntimeError):
+    def __init__(self, status, what=""):
+        super().__init__(f"{what}: {lap_status_str(status)}")
+        self.status = status
+
+
+def lap_status_str(status: int) -> str:
+    return _lib.lap_status_str(int(status)).decode()
+
+
+def lap_default_params(**overrides) -> lap_params:
+    p = lap_params()
+    _lib.lap_default_params(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def lap_setup(n, u, v, w, params: lap_params | None = None, stream=0):
+    """Host setup + upload.  u, v, w: host arrays (copied during the call).
+    Returns an opaque handle (int); raises LapError on a non-OK status."""
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    g = lap_graph(int(n), len(u), u.ctypes.data_as(C.POINTER(C.c_int64)),
+                  v.ctypes.data_as(C.POINTER(C.c_int64)), w.ctypes.data_as(C.POINTER(C.c_double)))
+    p = params if params is not None else lap_default_params()
+    h = C.c_void_p()
+    st = _lib.lap_setup(C.byref(g), C.byref(p), C.c_void_p(stream or 0), C.byref(h))
+    if st != LAP_OK:
+        raise LapError(st, "lap_setup")
+    return h.value
+
+
+def lap_solve(h, b_ptr: int, x_ptr: int, n: int, tol: float, nrhs: int = 1, ld: int | None = None,
+              stream=0):
+    """Returns (status, [info dict per column])."""
+    info = (lap_solve_info * nrhs)()
+    st = _lib.lap_solve(C.c_void_p(h), C.c_void_p(b_ptr), C.c_void_p(x_ptr), int(nrhs),
+                        int(ld if ld is not None else n), float(tol), info, C.c_void_p(stream or 0))
+    out = [dict(iterations=i.iterations, refinements=i.refinements, relres_true=i.relres_true,
+                relres_recursive=i.relres_recursive, seconds=i.seconds, status=i.status)
+           for i in info]
+    return st, out
+
+
+def lap_apply_laplacian(h, x_ptr: int, y_ptr: int, stream=0) -> int:
+    return _lib.lap_apply_laplacian(C.c_void_p(h), C.c_void_p(x_ptr), C.c_void_p(y_ptr),
+                                    C.c_void_p(stream or 0))
+
+
+def lap_apply_precond(h, r_ptr: int, z_ptr: int, stream=0) -> int:
+    return _lib.lap_apply_precond(C.c_void_p(h), C.c_void_p(r_ptr), C.c_void_p(z_ptr),
+                                  C.c_void_p(stream or 0))
+
+
+def lap_hierarchy_info(h) -> dict:
+    d = lap_hierarchy_desc()
+    st = _lib.lap_hierarchy_info(C.c_void_p(h), C.byref(d))
+    if st != LAP_OK:
+        raise LapError(st, "lap_hierarchy_info")
+    return dict(nlev=d.nlev, tail_level=d.tail_level, sizes=list(d.sizes[:d.nlev]),
+                ntilde=d.ntilde, nnz=d.nnz, device_bytes=d.device_bytes,
+                setup_seconds=d.setup_seconds)
+
+
+def lap_export_level(h, level: int, size: int):
+    agg = np.empty(size, dtype=np.int64)
+    mt = np.empty(size, dtype=np.int8)
+    st = _lib.lap_export_level(C.c_void_p(h), int(level), agg.ctypes.data, mt.ctypes.data)
+    if st != LAP_OK:
+        raise LapError(st, "lap_export_level")
+    return agg, mt.astype(bool)
+
+
+def lap_export_graph(h, level: int, size: int):
+    ptr = np.empty(size + 1, dtype=np.int64)
+    st = _lib.lap_export_graph(C.c_void_p(h), int(level), ptr.ctypes.data, None, None)
+    if st != LAP_OK:
+        raise LapError(st, "lap_export_graph")
+    col = np.empty(int(ptr[-1]), dtype=np.int64)
+    w = np.empty(int(ptr[-1]), dtype=np.float64)
+    _lib.lap_export_graph(C.c_void_p(h), int(level), ptr.ctypes.data, col.ctypes.data,
+                          w.ctypes.data)
+    return ptr, col, w
+
+
+def lap_profile_kernel(h, kernel: int, reps: int, stream=0):
+    """Returns (avg_ms per launch, algorithmic bytes per launch)."""
+    ms = C.c_double()
+    by = C.c_double()
+    st = _lib.lap_profile_kernel(C.c_void_p(h), int(kernel), int(reps), C.c_void_p(stream or 0),
+                                 C.byref(ms), C.byref(by))
+    if st != LAP_OK:
+        raise LapError(st, "lap_profile_kernel")
+    return ms.value, by.value
+
+
+def lap_free(h) -> None:
+    if h:
+        _lib.lap_free(C.c_void_p(h))

@@ -1,0 +1,990 @@
+// MI355X (gfx950) solve path of the MSP-preconditioned Laplacian solver and
+// its C ABI (include/lap.h).
+//
+// One PCG iteration is this kernel sequence (all on one stream):
+//   spmv_p      p = z - zbar + beta p_old;  q = L p;  p^T q  -> alpha
+//   update_up0  x += alpha p;  r -= alpha q;  ||r||^2 -> convergence flag;
+//               restriction of r onto level 1 fused with the local solves of
+//               the level-0 aggregates
+//   up(k)       restriction + local solves, levels 1 .. kt-1
+//   tail        one workgroup: levels kt .. top-1 up, top pseudo-inverse,
+//               levels top-1 .. kt down
+//   down(k)     prolongation + local corrections, levels kt-1 .. 1
+//   down0       z on the fine level; sum z, r^T z, sum r -> zbar, rho, beta
+// Reductions finish in the last block to arrive (fixed summation order, so
+// results are bitwise reproducible).  Every kernel returns at once when the
+// device flag `done` is set, so chunks of iterations captured in a hipGraph
+// can be replayed without host round trips per iteration.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lap.h"
+#include "setup.hpp"
+
+namespace lapgpu {
+
+// ------------------------------------------------------------ reductions
+
+template <int N>
+__device__ inline void wave_sum(double (&v)[N]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off, 64);
+}
+
+// Block sum in a fixed order; the result is valid in thread 0.
+template <int N, int NT>
+__device__ inline void block_sum(double (&v)[N], double* lds) {
+    constexpr int NW = NT / 64;
+    wave_sum<N>(v);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) lds[i * NW + wid] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double s = 0.0;
+            for (int w = 0; w < NW; ++w) s += lds[i * NW + w];
+            v[i] = s;
+        }
+}
+
+// Each block stores its partial sums; the last block to arrive adds all
+// partials in block order and returns true (totals in tot, thread 0).
+template <int N>
+__device__ inline bool last_block_sum(double (&v)[N], double* part, uint32_t* counter,
+                                      double (&tot)[N]) {
+    __shared__ double lds[N * (kBlock / 64)];
+    __shared__ int is_last;
+    block_sum<N, kBlock>(v, lds);
+    const int G = gridDim.x;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) part[i * G + blockIdx.x] = v[i];
+        __threadfence();
+        const uint32_t t = atomicAdd(counter, 1u);
+        is_last = (t == (uint32_t)(G - 1));
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double s[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock)
+#pragma unroll
+        for (int i = 0; i < N; ++i) s[i] += part[i * G + b];
+    __syncthreads();
+    block_sum<N, kBlock>(s, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) tot[i] = s[i];
+        *counter = 0u;
+    }
+    return true;
+}
+
+// --------------------------------------------------- aggregate primitives
+
+// Restriction of level-k values onto aggregate J plus the pair solve of the
+// aggregate's sparsifier block: g = C^T r, eta = theta S^-1 g.
+__device__ inline void agg_up(const LevelDev& s, const double* __restrict__ rk,
+                              double* __restrict__ rk1, int J) {
+    const int b0 = s.cptr[J], b1 = s.cptr[J + 1];
+    const double ra = rk[b0], rb = rk[b0 + 1];
+    double sum = ra + rb, ga = ra, gb = rb;
+    for (int t = b0 + 2; t < b1; ++t) {
+        const int li = t - 2 * J - 2;
+        const double rv = rk[t];
+        sum += rv;
+        ga += s.l1[li] * rv;
+        gb += s.l2[li] * rv;
+    }
+    const double saa = s.saa[J], sab = s.sab[J], sbb = s.sbb[J];
+    s.ea[J] = saa * ga + sab * gb;
+    s.eb[J] = sab * ga + sbb * gb;
+    rk1[J] = sum;
+}
+
+// Prolongation from aggregate J plus the local corrections of its members.
+__device__ inline void agg_down(const LevelDev& s, const double* __restrict__ rk,
+                                double* __restrict__ yk, const double* __restrict__ yk1, int J) {
+    const int b0 = s.cptr[J], b1 = s.cptr[J + 1];
+    const double yJ = yk1[J], ea = s.ea[J], eb = s.eb[J];
+    yk[b0] = ea + yJ;
+    yk[b0 + 1] = eb + yJ;
+    for (int t = b0 + 2; t < b1; ++t) {
+        const int li = t - 2 * J - 2;
+        yk[t] = s.l0[li] * rk[t] + s.l1[li] * ea + s.l2[li] * eb + yJ;
+    }
+}
+
+// ----------------------------------------------------------------- kernels
+
+// p = z - zbar + beta p_old; q = L p with (L p)_i = sum_j w_ij (p_i - p_j);
+// partial p^T q.  Last block: alpha = rho / p^T q, iteration count.
+__global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* __restrict__ z,
+                                                   const double* __restrict__ pold,
+                                                   double* __restrict__ pnew,
+                                                   double* __restrict__ q, Scal* S,
+                                                   double* part) {
+    if (S->done) return;
+    const double beta = S->beta, zbar = S->zbar;
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    double pi = 0.0, acc = 0.0;
+    if (row < n) {
+        const double zi = z[row], poi = pold[row];
+        pi = (zi - zbar) + beta * poi;
+        const int sl = row >> 6;
+        const int base = A.off[sl] + (row & 63);
+        const int W = A.width[sl];
+        for (int k = 0; k < W; ++k) {
+            const int j = A.col[base + k * 64];
+            const double w = A.w[base + k * 64];
+            acc += w * ((zi - z[j]) + beta * (poi - pold[j]));
+        }
+        pnew[row] = pi;
+        q[row] = acc;
+    }
+    double v[1] = {pi * acc}, tot[1];
+    if (last_block_sum<1>(v, part, &S->cnt[kCntSpmv], tot) && threadIdx.x == 0) {
+        const double pq = tot[0];
+        S->pq = pq;
+        S->iter += 1;
+        if (!(pq > 0.0) || !isfinite(pq)) S->done = 3;
+        else S->alpha = S->rho / pq;
+    }
+}
+
+// x += alpha p; r -= alpha q; ||r||^2; fused restriction of r to level 1.
+__global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev s0, double* __restrict__ x,
+                                                       double* __restrict__ r,
+                                                       const double* __restrict__ p,
+                                                       const double* __restrict__ q,
+                                                       double* __restrict__ r1, Scal* S,
+                                                       double* part, int do_update) {
+    if (S->done) return;
+    const double alpha = S->alpha;
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    double rr = 0.0;
+    if (J < s0.nc) {
+        const int b0 = s0.cptr[J], b1 = s0.cptr[J + 1];
+        if (do_update) {
+            for (int t = b0; t < b1; ++t) {
+                const double xt = x[t] + alpha * p[t];
+                const double rt = r[t] - alpha * q[t];
+                x[t] = xt;
+                r[t] = rt;
+                rr += rt * rt;
+            }
+        }
+        agg_up(s0, r, r1, J);
+    }
+    if (!do_update) return;
+    double v[1] = {rr}, tot[1];
+    if (last_block_sum<1>(v, part, &S->cnt[kCntUpd], tot) && threadIdx.x == 0) {
+        S->rr = tot[0];
+        if (!isfinite(tot[0])) S->done = 3;
+        else if (tot[0] <= S->tol2 * S->bn2) S->done = 1;
+        else if (S->iter >= S->maxit) S->done = 2;
+    }
+}
+
+// Plain CG variant of update_up0 (no preconditioner).
+__global__ __launch_bounds__(kBlock) void k_update_none(int n, double* __restrict__ x,
+                                                        double* __restrict__ r,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ q, Scal* S,
+                                                        double* part) {
+    if (S->done) return;
+    const double alpha = S->alpha;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double rr = 0.0;
+    if (t < n) {
+        x[t] += alpha * p[t];
+        const double rt = r[t] - alpha * q[t];
+        r[t] = rt;
+        rr = rt * rt;
+    }
+    double v[1] = {rr}, tot[1];
+    if (last_block_sum<1>(v, part, &S->cnt[kCntUpd], tot) && threadIdx.x == 0) {
+        S->rr = tot[0];
+        if (!isfinite(tot[0])) S->done = 3;
+        else if (tot[0] <= S->tol2 * S->bn2) S->done = 1;
+        else if (S->iter >= S->maxit) S->done = 2;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_up(LevelDev s, const double* __restrict__ rk,
+                                               double* __restrict__ rk1, const Scal* S) {
+    if (S->done) return;
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    if (J < s.nc) agg_up(s, rk, rk1, J);
+}
+
+__global__ __launch_bounds__(kBlock) void k_down(LevelDev s, const double* __restrict__ rk,
+                                                 double* __restrict__ yk,
+                                                 const double* __restrict__ yk1, const Scal* S) {
+    if (S->done) return;
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    if (J < s.nc) agg_down(s, rk, yk, yk1, J);
+}
+
+// Levels kt .. top in one workgroup: restriction and local solves upwards,
+// theta_top * pinv(L_top) on the top, prolongation and corrections back.
+__global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDev* __restrict__ tab, int kt,
+                                                       int top, const double* __restrict__ tp,
+                                                       const Scal* S) {
+    if (S->done) return;
+    for (int k = kt; k < top; ++k) {
+        const LevelDev s = tab[k];
+        double* rk1 = tab[k + 1].r;
+        for (int J = threadIdx.x; J < s.nc; J += blockDim.x) agg_up(s, s.r, rk1, J);
+        __syncthreads();
+    }
+    {
+        const int nt = tab[top].n;
+        const double* rT = tab[top].r;
+        double* yT = tab[top].y;
+        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+            double acc = 0.0;
+            for (int j = 0; j < nt; ++j) acc += tp[i * nt + j] * rT[j];
+            yT[i] = acc;
+        }
+        __syncthreads();
+    }
+    for (int k = top - 1; k >= kt; --k) {
+        const LevelDev s = tab[k];
+        const double* yk1 = tab[k + 1].y;
+        for (int J = threadIdx.x; J < s.nc; J += blockDim.x) agg_down(s, s.r, s.y, yk1, J);
+        __syncthreads();
+    }
+}
+
+// z on the fine level; sums of z, r*z and r.  Last block: zbar, rho, beta.
+__global__ __launch_bounds__(kBlock) void k_down0(LevelDev s0, int n, const double* __restrict__ r,
+                                                  double* __restrict__ z,
+                                                  const double* __restrict__ y1, Scal* S,
+                                                  double* part) {
+    if (S->done) return;
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (J < s0.nc) {
+        const int b0 = s0.cptr[J], b1 = s0.cptr[J + 1];
+        agg_down(s0, r, z, y1, J);
+        for (int t = b0; t < b1; ++t) {
+            const double zt = z[t], rt = r[t];
+            v[0] += zt;
+            v[1] += rt * zt;
+            v[2] += rt;
+        }
+    }
+    double tot[3];
+    if (last_block_sum<3>(v, part, &S->cnt[kCntDown], tot) && threadIdx.x == 0) {
+        const double zbar = tot[0] / (double)n;
+        const double rho = tot[1] - zbar * tot[2];
+        S->zbar = zbar;
+        if (!isfinite(rho)) S->done = 3;
+        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->first = 0;
+        S->rho = rho;
+    }
+}
+
+// One-level hierarchy (top = fine level, at most kTopMax nodes): the MSP is
+// theta_0 pinv(L) = pinv(L); one workgroup applies it and does the k_down0
+// reductions itself.
+__global__ __launch_bounds__(kBlock) void k_top_only(int n, const double* __restrict__ tp,
+                                                     const double* __restrict__ r,
+                                                     double* __restrict__ z, Scal* S) {
+    if (S->done) return;
+    __shared__ double lds[3 * (kBlock / 64)];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += tp[i * n + j] * r[j];
+        z[i] = acc;
+        v[0] += acc;
+        v[1] += r[i] * acc;
+        v[2] += r[i];
+    }
+    block_sum<3, kBlock>(v, lds);
+    if (threadIdx.x == 0) {
+        const double zbar = v[0] / (double)n;
+        const double rho = v[1] - zbar * v[2];
+        S->zbar = zbar;
+        if (!isfinite(rho)) S->done = 3;
+        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->first = 0;
+        S->rho = rho;
+    }
+}
+
+// Plain CG: z = r, same reductions as k_down0.
+__global__ __launch_bounds__(kBlock) void k_prec_none(int n, const double* __restrict__ r,
+                                                      double* __restrict__ z, Scal* S,
+                                                      double* part) {
+    if (S->done) return;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (t < n) {
+        const double rt = r[t];
+        z[t] = rt;
+        v[0] = rt;
+        v[1] = rt * rt;
+        v[2] = rt;
+    }
+    double tot[3];
+    if (last_block_sum<3>(v, part, &S->cnt[kCntDown], tot) && threadIdx.x == 0) {
+        const double zbar = tot[0] / (double)n;
+        const double rho = tot[1] - zbar * tot[2];
+        S->zbar = zbar;
+        if (!isfinite(rho)) S->done = 3;
+        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->first = 0;
+        S->rho = rho;
+    }
+}
+
+// dst[t] = src[perm[t]] (gather into tree order) and sum -> S->bsum.
+__global__ __launch_bounds__(kBlock) void k_gather_sum(int n, const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ src,
+                                                       double* __restrict__ dst, Scal* S,
+                                                       double* part) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0}, tot[1];
+    if (t < n) {
+        const double b = src[perm[t]];
+        dst[t] = b;
+        v[0] = b;
+    }
+    if (last_block_sum<1>(v, part, &S->cnt[kCntInit], tot) && threadIdx.x == 0) S->bsum = tot[0];
+}
+
+// b^ = b - mean; r = b^; x = p0 = p1 = 0; ||b^||^2 -> bn2, run flags.
+__global__ __launch_bounds__(kBlock) void k_init(int n, double* __restrict__ b, double* __restrict__ r,
+                                                 double* __restrict__ x, double* __restrict__ p0,
+                                                 double* __restrict__ p1, Scal* S, double* part) {
+    const double mean = S->bsum / (double)n;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0}, tot[1];
+    if (t < n) {
+        const double bh = b[t] - mean;
+        b[t] = bh;
+        r[t] = bh;
+        x[t] = 0.0;
+        p0[t] = 0.0;
+        p1[t] = 0.0;
+        v[0] = bh * bh;
+    }
+    if (last_block_sum<1>(v, part, &S->cnt[kCntInit], tot) && threadIdx.x == 0) {
+        S->bn2 = tot[0];
+        S->iter = 0;
+        S->first = 1;
+        S->alpha = 0.0;
+        S->beta = 0.0;
+        S->zbar = 0.0;
+        S->rr = tot[0];
+        if (!isfinite(tot[0])) S->done = 4;
+        else if (tot[0] == 0.0) S->done = 1;
+        else if (S->maxit <= 0) S->done = 2;
+        else S->done = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum(int n, const double* __restrict__ a, Scal* S,
+                                                double* part) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {t < n ? a[t] : 0.0}, tot[1];
+    if (last_block_sum<1>(v, part, &S->cnt[kCntFin], tot) && threadIdx.x == 0) S->xsum = tot[0];
+}
+
+// xc = x - mean(x) in tree order and dst[perm[t]] = xc[t].
+__global__ __launch_bounds__(kBlock) void k_center_scatter(int n, const int32_t* __restrict__ perm,
+                                                           const double* __restrict__ x,
+                                                           double* __restrict__ xc,
+                                                           double* __restrict__ dst,
+                                                           const Scal* S) {
+    const double mean = S->xsum / (double)n;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) {
+        const double v = x[t] - mean;
+        xc[t] = v;
+        dst[perm[t]] = v;
+    }
+}
+
+// ||b^ - L x||^2 -> S->res2.
+__global__ __launch_bounds__(kBlock) void k_resid(int n, Sell A, const double* __restrict__ x,
+                                                  const double* __restrict__ bh, Scal* S,
+                                                  double* part) {
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0}, tot[1];
+    if (row < n) {
+        const double xi = x[row];
+        const int sl = row >> 6;
+        const int base = A.off[sl] + (row & 63);
+        double acc = 0.0;
+        for (int k = 0; k < A.width[sl]; ++k)
+            acc += A.w[base + k * 64] * (xi - x[A.col[base + k * 64]]);
+        const double d = bh[row] - acc;
+        v[0] = d * d;
+    }
+    if (last_block_sum<1>(v, part, &S->cnt[kCntFin], tot) && threadIdx.x == 0) S->res2 = tot[0];
+}
+
+// y[perm[t]] = (L x~)_t with x~[t] = x[perm[t]] (original order in and out).
+__global__ __launch_bounds__(kBlock) void k_spmv_orig(int n, Sell A, const int32_t* __restrict__ perm,
+                                                      const double* __restrict__ xt,
+                                                      double* __restrict__ y) {
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row >= n) return;
+    const double xi = xt[row];
+    const int sl = row >> 6;
+    const int base = A.off[sl] + (row & 63);
+    double acc = 0.0;
+    for (int k = 0; k < A.width[sl]; ++k)
+        acc += A.w[base + k * 64] * (xi - xt[A.col[base + k * 64]]);
+    y[perm[row]] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(int n, const int32_t* __restrict__ perm,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ dst) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) dst[t] = src[perm[t]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_center(int n, const int32_t* __restrict__ perm,
+                                                           const double* __restrict__ z,
+                                                           double* __restrict__ dst,
+                                                           const Scal* S) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) dst[perm[t]] = z[t] - S->zbar;
+}
+
+}  // namespace lapgpu
+
+// ====================================================================== host
+
+using namespace lapgpu;
+
+namespace {
+
+inline int nblk(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+struct HipErr {};
+#define HIPCHK(expr)                                  \
+    do {                                              \
+        if ((expr) != hipSuccess) throw HipErr();     \
+    } while (0)
+
+int tail_max_default() {
+    const char* s = std::getenv("LAPGPU_TAIL_MAX");
+    if (s) {
+        const int v = std::atoi(s);
+        if (v > 0) return v;
+    }
+    return 8192;
+}
+
+int chunk_default() {
+    const char* s = std::getenv("LAPGPU_CHUNK");
+    if (s) {
+        const int v = std::atoi(s);
+        if (v >= 2) return v & ~1;
+    }
+    return 8;
+}
+
+}  // namespace
+
+struct lap_hierarchy {
+    HostPlan plan;
+    lap_params params{};
+    bool host_only = false;
+    bool with_msp = true;
+    int64_t n = 0;
+    int device = 0;
+    double setup_seconds = 0.0;
+    int64_t dev_bytes = 0;
+    std::vector<void*> allocs;
+    // device data
+    int32_t* perm0 = nullptr;
+    Sell A{};
+    std::vector<LevelDev> lv;    // host copy of the level table
+    LevelDev* d_lv = nullptr;
+    double* top_pinv = nullptr;
+    int kt = 1;
+    // workspace
+    double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr, *xc = nullptr;
+    double* p[2] = {nullptr, nullptr};
+    Scal* S = nullptr;
+    double* part = nullptr;
+    Scal* stage = nullptr;       // pinned host copy of S
+    hipStream_t cap = nullptr;   // private capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int chunk = 8;
+
+    template <class T>
+    T* dalloc(size_t count) {
+        void* ptr = nullptr;
+        const size_t bytes = (count ? count : 1) * sizeof(T);
+        if (hipMalloc(&ptr, bytes) != hipSuccess) throw std::bad_alloc();
+        allocs.push_back(ptr);
+        dev_bytes += (int64_t)bytes;
+        return static_cast<T*>(ptr);
+    }
+    template <class T>
+    T* upload(const std::vector<T>& v, hipStream_t s) {
+        T* d = dalloc<T>(v.size());
+        if (!v.empty())
+            HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        return d;
+    }
+    ~lap_hierarchy() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (void* ptr : allocs) (void)hipFree(ptr);
+        if (stage) (void)hipHostFree(stage);
+    }
+};
+
+namespace {
+
+// Enqueue the preconditioner (update_up0 with or without the x/r update,
+// then up, tail, down, down0) or the plain-CG equivalent.
+void enqueue_precond(lap_hierarchy* h, hipStream_t s, int do_update, const double* pcur) {
+    const int T = h->plan.nlev() - 1;
+    if (!h->with_msp) {
+        if (do_update)
+            hipLaunchKernelGGL(k_update_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n,
+                               h->x, h->r, pcur, h->q, h->S, h->part);
+        hipLaunchKernelGGL(k_prec_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n, h->r,
+                           h->z, h->S, h->part);
+        return;
+    }
+    if (T == 0) {
+        if (do_update)
+            hipLaunchKernelGGL(k_update_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n,
+                               h->x, h->r, pcur, h->q, h->S, h->part);
+        hipLaunchKernelGGL(k_top_only, dim3(1), dim3(kBlock), 0, s, (int)h->n, h->top_pinv, h->r,
+                           h->z, h->S);
+        return;
+    }
+    const LevelDev& s0 = h->lv[0];
+    hipLaunchKernelGGL(k_update_up0, dim3(nblk(s0.nc)), dim3(kBlock), 0, s, s0, h->x, h->r, pcur,
+                       h->q, h->lv[1].r, h->S, h->part, do_update);
+    for (int k = 1; k < h->kt; ++k)
+        hipLaunchKernelGGL(k_up, dim3(nblk(h->lv[k].nc)), dim3(kBlock), 0, s, h->lv[k], h->lv[k].r,
+                           h->lv[k + 1].r, h->S);
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), 0, s, h->d_lv, h->kt, T, h->top_pinv,
+                       h->S);
+    for (int k = h->kt - 1; k >= 1; --k)
+        hipLaunchKernelGGL(k_down, dim3(nblk(h->lv[k].nc)), dim3(kBlock), 0, s, h->lv[k],
+                           h->lv[k].r, h->lv[k].y, h->lv[k + 1].y, h->S);
+    hipLaunchKernelGGL(k_down0, dim3(nblk(s0.nc)), dim3(kBlock), 0, s, s0, (int)h->n, h->r, h->z,
+                       h->lv[1].y, h->S, h->part);
+}
+
+// One PCG iteration reading p[par] and writing p[1-par].
+void enqueue_iteration(lap_hierarchy* h, hipStream_t s, int par) {
+    hipLaunchKernelGGL(k_spmv_p, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n, h->A, h->z,
+                       h->p[par], h->p[1 - par], h->q, h->S, h->part);
+    enqueue_precond(h, s, 1, h->p[1 - par]);
+}
+
+void build_graph(lap_hierarchy* h) {
+    HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < h->chunk; ++i) enqueue_iteration(h, h->cap, i & 1);
+    HIPCHK(hipStreamEndCapture(h->cap, &h->graph));
+    HIPCHK(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+}
+
+void upload_plan(lap_hierarchy* h, hipStream_t s) {
+    const HostPlan& P = h->plan;
+    const int L = P.nlev();
+    const int T = L - 1;
+    h->perm0 = h->upload(P.perm[0], s);
+    h->A.off = h->upload(P.sell_off, s);
+    h->A.width = h->upload(P.sell_width, s);
+    h->A.col = h->upload(P.sell_col, s);
+    h->A.w = h->upload(P.sell_w, s);
+    h->with_msp = (h->params.precond == LAP_PREC_MSP);
+    h->lv.assign(L, LevelDev{});
+    const int tail_max = tail_max_default();
+    h->kt = T;
+    for (int k = 1; k <= T; ++k)
+        if (P.lv[k].g.n <= tail_max) { h->kt = k; break; }
+    for (int k = 0; k < L; ++k) {
+        LevelDev& d = h->lv[k];
+        d.n = (int32_t)P.lv[k].g.n;
+        d.nc = k < T ? (int32_t)P.lv[k + 1].g.n : 0;
+        if (k >= 1) {
+            d.r = h->dalloc<double>(d.n);
+            d.y = h->dalloc<double>(d.n);
+        }
+        if (k < T) {
+            const StepCoef& c = P.step[k];
+            d.cptr = h->upload(c.cptr, s);
+            d.saa = h->upload(c.saa, s);
+            d.sab = h->upload(c.sab, s);
+            d.sbb = h->upload(c.sbb, s);
+            d.l0 = h->upload(c.l0, s);
+            d.l1 = h->upload(c.l1, s);
+            d.l2 = h->upload(c.l2, s);
+            d.ea = h->dalloc<double>(d.nc);
+            d.eb = h->dalloc<double>(d.nc);
+        }
+    }
+    h->d_lv = h->upload(h->lv, s);
+    h->top_pinv = h->upload(P.top_pinv, s);
+    const int64_t n = h->n;
+    h->b = h->dalloc<double>(n);
+    h->x = h->dalloc<double>(n);
+    h->r = h->dalloc<double>(n);
+    h->z = h->dalloc<double>(n);
+    h->q = h->dalloc<double>(n);
+    h->xc = h->dalloc<double>(n);
+    h->p[0] = h->dalloc<double>(n);
+    h->p[1] = h->dalloc<double>(n);
+    h->S = h->dalloc<Scal>(1);
+    h->part = h->dalloc<double>((size_t)kMaxGridPart * nblk(n) + 64);
+    HIPCHK(hipHostMalloc((void**)&h->stage, sizeof(Scal), hipHostMallocDefault));
+    std::memset(h->stage, 0, sizeof(Scal));
+    HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->chunk = chunk_default();
+    build_graph(h);
+}
+
+lap_status to_status(int done) {
+    switch (done) {
+        case 1: return LAP_OK;
+        case 2: return LAP_ENOCONV;
+        case 3: return LAP_EBREAKDOWN;
+        case 4: return LAP_EINVAL;
+        default: return LAP_EDEVICE;
+    }
+}
+
+lap_status solve_one(lap_hierarchy* h, const double* b, double* x, double tol,
+                     lap_solve_info* info, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int n = (int)h->n;
+    // reset scalars (counters included) and set the run parameters
+    std::memset(h->stage, 0, sizeof(Scal));
+    h->stage->tol2 = tol * tol;
+    h->stage->maxit = h->params.max_iter;
+    HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_gather_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, b, h->b, h->S,
+                       h->part);
+    hipLaunchKernelGGL(k_init, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->b, h->r, h->x, h->p[0],
+                       h->p[1], h->S, h->part);
+    enqueue_precond(h, s, 0, h->p[0]);
+    HIPCHK(hipGetLastError());
+    // chunks of iterations; one chunk in flight beyond the one being checked
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    const int max_chunks = h->params.max_iter / h->chunk + 2;
+    HIPCHK(hipGraphLaunch(h->exec, s));
+    for (int c = 0; c < max_chunks; ++c) {
+        HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ev, s));
+        HIPCHK(hipGraphLaunch(h->exec, s));
+        HIPCHK(hipEventSynchronize(ev));
+        if (h->stage->done) break;
+    }
+    (void)hipEventDestroy(ev);
+    // mean-free x in original order, true residual
+    hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->x, h->S, h->part);
+    hipLaunchKernelGGL(k_center_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, h->x,
+                       h->xc, x, h->S);
+    hipLaunchKernelGGL(k_resid, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, h->xc, h->b, h->S,
+                       h->part);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Scal& S = *h->stage;
+    const lap_status st = S.done == 0 ? LAP_ENOCONV : to_status(S.done);
+    if (info) {
+        const double bn = std::sqrt(S.bn2);
+        info->iterations = S.iter;
+        info->refinements = 0;
+        info->relres_true = bn > 0 ? std::sqrt(S.res2) / bn : 0.0;
+        info->relres_recursive = bn > 0 ? std::sqrt(S.rr) / bn : 0.0;
+        info->status = st;
+        info->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+}
+
+int rank_status(lap_status s) {
+    switch (s) {
+        case LAP_OK: return 0;
+        case LAP_ENOCONV: return 1;
+        case LAP_EBREAKDOWN: return 2;
+        default: return 3;
+    }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+lap_status lap_default_params(lap_params* p) {
+    if (!p) return LAP_EINVAL;
+    p->mu = 0.8;
+    p->max_levels = 0;
+    p->n_top = 2;
+    p->mwm_seed = 0;
+    p->precond = LAP_PREC_MSP;
+    p->precision = LAP_FP64;
+    p->max_iter = 1000;
+    p->flags = 0;
+    return LAP_OK;
+}
+
+const char* lap_status_str(lap_status s) {
+    switch (s) {
+        case LAP_OK: return "LAP_OK";
+        case LAP_EINVAL: return "LAP_EINVAL";
+        case LAP_EDISCONNECTED: return "LAP_EDISCONNECTED";
+        case LAP_ENOMEM: return "LAP_ENOMEM";
+        case LAP_EDEVICE: return "LAP_EDEVICE";
+        case LAP_ENOCONV: return "LAP_ENOCONV";
+        case LAP_EBREAKDOWN: return "LAP_EBREAKDOWN";
+        case LAP_EUNSUPPORTED: return "LAP_EUNSUPPORTED";
+    }
+    return "LAP_UNKNOWN";
+}
+
+lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_hierarchy** out) {
+    if (!out) return LAP_EINVAL;
+    *out = nullptr;
+    if (!g || !p || !g->u || !g->v || !g->w) return LAP_EINVAL;
+    if (p->precond != LAP_PREC_MSP && p->precond != LAP_PREC_NONE) {
+        return p->precond == LAP_PREC_PEGP ? LAP_EUNSUPPORTED : LAP_EINVAL;
+    }
+    if (p->precision != LAP_FP64) return LAP_EINVAL;
+    if (p->max_iter < 0) return LAP_EINVAL;
+    const auto t0 = std::chrono::steady_clock::now();
+    lap_hierarchy* h = new (std::nothrow) lap_hierarchy();
+    if (!h) return LAP_ENOMEM;
+    h->params = *p;
+    h->host_only = (p->flags & LAP_FLAG_HOST_ONLY) != 0;
+    try {
+        const int rc = build_plan(g->n, g->m, g->u, g->v, g->w, p->mu, p->max_levels, p->n_top,
+                                  p->mwm_seed, h->host_only, h->plan);
+        if (rc != kOk) {
+            delete h;
+            return (lap_status)rc;
+        }
+        h->n = g->n;
+        if (!h->host_only) {
+            int ndev = 0;
+            if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+                delete h;
+                return LAP_EDEVICE;
+            }
+            HIPCHK(hipGetDevice(&h->device));
+            upload_plan(h, (hipStream_t)stream);
+        }
+    } catch (const std::bad_alloc&) {
+        delete h;
+        return LAP_ENOMEM;
+    } catch (const HipErr&) {
+        delete h;
+        return LAP_EDEVICE;
+    }
+    h->setup_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return LAP_OK;
+}
+
+lap_status lap_solve(lap_hierarchy* h, const double* b, double* x, int32_t nrhs, int64_t ld,
+                     double tol, lap_solve_info* info, void* stream) {
+    if (!h || !b || !x || nrhs < 1 || ld < h->n || !(tol > 0.0) || !std::isfinite(tol))
+        return LAP_EINVAL;
+    if (h->host_only) return LAP_EUNSUPPORTED;
+    lap_status worst = LAP_OK;
+    try {
+        for (int c = 0; c < nrhs; ++c) {
+            const lap_status st = solve_one(h, b + (int64_t)c * ld, x + (int64_t)c * ld, tol,
+                                            info ? info + c : nullptr, (hipStream_t)stream);
+            if (rank_status(st) > rank_status(worst)) worst = st;
+        }
+    } catch (const HipErr&) {
+        return LAP_EDEVICE;
+    }
+    return worst;
+}
+
+lap_status lap_apply_laplacian(lap_hierarchy* h, const double* x, double* y, void* stream) {
+    if (!h || !x || !y) return LAP_EINVAL;
+    if (h->host_only) return LAP_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)h->n;
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, x, h->xc);
+    hipLaunchKernelGGL(k_spmv_orig, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, h->perm0, h->xc,
+                       y);
+    return hipGetLastError() == hipSuccess ? LAP_OK : LAP_EDEVICE;
+}
+
+lap_status lap_apply_precond(lap_hierarchy* h, const double* r, double* z, void* stream) {
+    if (!h || !r || !z) return LAP_EINVAL;
+    if (h->host_only) return LAP_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)h->n;
+    try {
+        std::memset(h->stage, 0, sizeof(Scal));
+        h->stage->first = 1;
+        HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, r, h->r);
+        enqueue_precond(h, s, 0, h->p[0]);
+        hipLaunchKernelGGL(k_scatter_center, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, h->z,
+                           z, h->S);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (const HipErr&) {
+        return LAP_EDEVICE;
+    }
+    return LAP_OK;
+}
+
+lap_status lap_profile_kernel(lap_hierarchy* h, int32_t kernel, int32_t reps, void* stream,
+                              double* avg_ms, double* alg_bytes) {
+    if (!h || reps < 1 || kernel < 0 || kernel > LAP_KERNEL_ITER) return LAP_EINVAL;
+    if (h->host_only) return LAP_EUNSUPPORTED;
+    const int T = h->plan.nlev() - 1;
+    const bool levels = h->with_msp && T >= 1;
+    if ((kernel == LAP_KERNEL_UPDATE || kernel == LAP_KERNEL_DOWN0) && !levels)
+        return LAP_EUNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    // algorithmic bytes (FP64 values, int32 indices)
+    const double n = (double)h->n, nnz = (double)h->plan.lv[0].g.nnz();
+    auto step_bytes = [&](int k, bool up) {
+        const double nk = (double)h->plan.lv[k].g.n;
+        const double nc = k < T ? (double)h->plan.lv[k + 1].g.n : 0.0;
+        const double nl = nk - 2.0 * nc;
+        if (up)   // r_k; cptr, 3 pair coefficients; 2 leftover coefficients; eta_a, eta_b, r_k+1
+            return 8.0 * nk + 4.0 * nc + 24.0 * nc + 16.0 * nl + 24.0 * nc;
+        // r_k of leftovers; cptr, eta_a, eta_b, y_k+1; 3 leftover coefficients; y_k
+        return 8.0 * nl + 28.0 * nc + 24.0 * nl + 8.0 * nk;
+    };
+    const double spmv = 32.0 * n + 12.0 * nnz;
+    const double upd = levels ? 40.0 * n + step_bytes(0, true) : 48.0 * n;
+    const double down0 = levels ? step_bytes(0, false) + 8.0 * n : 16.0 * n;
+    double prec = down0 + (levels ? step_bytes(0, true) : 0.0);
+    for (int k = 1; levels && k < T; ++k) prec += step_bytes(k, true) + step_bytes(k, false);
+    double bytes = 0.0;
+    switch (kernel) {
+        case LAP_KERNEL_SPMV: bytes = spmv; break;
+        case LAP_KERNEL_UPDATE: bytes = upd; break;
+        case LAP_KERNEL_DOWN0: bytes = down0; break;
+        case LAP_KERNEL_PRECOND: bytes = prec; break;
+        default: bytes = spmv + upd + (prec - (levels ? step_bytes(0, true) : 0.0)); break;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        std::memset(h->stage, 0, sizeof(Scal));
+        h->stage->maxit = 0x7fffffff;
+        h->stage->rho = 1.0;
+        h->stage->bn2 = 1.0;
+        HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s));
+        for (int i = 0; i < reps; ++i) {
+            switch (kernel) {
+                case LAP_KERNEL_SPMV:
+                    hipLaunchKernelGGL(k_spmv_p, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n,
+                                       h->A, h->z, h->p[0], h->p[1], h->q, h->S, h->part);
+                    break;
+                case LAP_KERNEL_UPDATE:
+                    hipLaunchKernelGGL(k_update_up0, dim3(nblk(h->lv[0].nc)), dim3(kBlock), 0, s,
+                                       h->lv[0], h->x, h->r, h->p[1], h->q, h->lv[1].r, h->S,
+                                       h->part, 1);
+                    break;
+                case LAP_KERNEL_DOWN0:
+                    hipLaunchKernelGGL(k_down0, dim3(nblk(h->lv[0].nc)), dim3(kBlock), 0, s,
+                                       h->lv[0], (int)h->n, h->r, h->z, h->lv[1].y, h->S, h->part);
+                    break;
+                case LAP_KERNEL_PRECOND: enqueue_precond(h, s, 0, h->p[0]); break;
+                default: enqueue_iteration(h, s, 0); break;
+            }
+        }
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (avg_ms) *avg_ms = (double)ms / reps;
+        if (alg_bytes) *alg_bytes = bytes;
+        // the profiled kernels may have set flags; leave the workspace idle
+        HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const bool ran = h->stage->done == 0;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return ran ? LAP_OK : LAP_EBREAKDOWN;
+    } catch (const HipErr&) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return LAP_EDEVICE;
+    }
+}
+
+lap_status lap_hierarchy_info(const lap_hierarchy* h, lap_hierarchy_desc* d) {
+    if (!h || !d) return LAP_EINVAL;
+    std::memset(d, 0, sizeof(*d));
+    d->nlev = h->plan.nlev();
+    d->tail_level = h->kt;
+    for (int k = 0; k < d->nlev && k < LAP_MAX_LEVELS; ++k) {
+        d->sizes[k] = h->plan.lv[k].g.n;
+        d->ntilde += d->sizes[k];
+    }
+    d->nnz = h->plan.lv[0].g.nnz();
+    d->device_bytes = h->dev_bytes;
+    d->setup_seconds = h->setup_seconds;
+    return LAP_OK;
+}
+
+lap_status lap_export_level(const lap_hierarchy* h, int32_t level, int64_t* agg, int8_t* matched) {
+    if (!h || level < 0 || level >= h->plan.nlev() - 1) return LAP_EINVAL;
+    const Level& L = h->plan.lv[level];
+    if (agg) std::memcpy(agg, L.agg.data(), L.agg.size() * sizeof(int64_t));
+    if (matched) std::memcpy(matched, L.matched.data(), L.matched.size());
+    return LAP_OK;
+}
+
+lap_status lap_export_graph(const lap_hierarchy* h, int32_t level, int64_t* ptr, int64_t* col,
+                            double* w) {
+    if (!h || level < 0 || level >= h->plan.nlev() || !ptr) return LAP_EINVAL;
+    const Adjacency& g = h->plan.lv[level].g;
+    std::memcpy(ptr, g.ptr.data(), g.ptr.size() * sizeof(int64_t));
+    if (col)
+        for (int64_t k = 0; k < g.nnz(); ++k) col[k] = g.col[k];
+    if (w) std::memcpy(w, g.w.data(), g.w.size() * sizeof(double));
+    return LAP_OK;
+}
+
+void lap_free(lap_hierarchy* h) { delete h; }
+
+}  // extern "C"

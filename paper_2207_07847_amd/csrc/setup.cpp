@@ -1,0 +1,422 @@
+// Host-side setup of the MSP hierarchy; see setup.hpp.
+#include "setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace lapgpu {
+
+// ---------------------------------------------------------------- graph
+
+// Sec. 2.1: undirected, positively weighted.  Rows are filled by a
+// counting pass, then each row is ordered by (neighbour, edge position) and
+// parallel edges merged in edge-position order (same order in both rows, so
+// the merged weights are exactly symmetric).
+int build_adjacency(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+                    const double* w, Adjacency& out) {
+    if (n < 2 || m < 1 || n > INT32_MAX - 1) return kInval;
+    for (int64_t e = 0; e < m; ++e) {
+        if (u[e] < 0 || u[e] >= n || v[e] < 0 || v[e] >= n || u[e] == v[e]) return kInval;
+        if (!(w[e] > 0.0) || !std::isfinite(w[e])) return kInval;
+    }
+    std::vector<int64_t> start(n + 1, 0);
+    for (int64_t e = 0; e < m; ++e) { ++start[u[e] + 1]; ++start[v[e] + 1]; }
+    for (int64_t i = 0; i < n; ++i) start[i + 1] += start[i];
+    std::vector<std::pair<int32_t, int64_t>> slot(2 * m);   // (neighbour, edge)
+    std::vector<int64_t> fillp(start.begin(), start.end() - 1);
+    for (int64_t e = 0; e < m; ++e) {
+        slot[fillp[u[e]]++] = {(int32_t)v[e], e};
+        slot[fillp[v[e]]++] = {(int32_t)u[e], e};
+    }
+    out.n = n;
+    out.ptr.assign(n + 1, 0);
+    out.col.clear();
+    out.w.clear();
+    out.col.reserve(2 * m);
+    out.w.reserve(2 * m);
+    for (int64_t i = 0; i < n; ++i) {
+        auto b = slot.begin() + start[i], e = slot.begin() + start[i + 1];
+        std::sort(b, e);
+        for (auto it = b; it != e; ++it) {
+            if (it != b && it->first == (it - 1)->first) {
+                out.w.back() += w[it->second];
+            } else {
+                out.col.push_back(it->first);
+                out.w.push_back(w[it->second]);
+            }
+        }
+        out.ptr[i + 1] = (int64_t)out.col.size();
+    }
+    return kOk;
+}
+
+bool is_connected(const Adjacency& g) {
+    std::vector<char> seen(g.n, 0);
+    std::vector<int32_t> stack{0};
+    seen[0] = 1;
+    int64_t count = 1;
+    while (!stack.empty()) {
+        int32_t i = stack.back();
+        stack.pop_back();
+        for (int64_t k = g.ptr[i]; k < g.ptr[i + 1]; ++k) {
+            int32_t j = g.col[k];
+            if (!seen[j]) { seen[j] = 1; ++count; stack.push_back(j); }
+        }
+    }
+    return count == g.n;
+}
+
+// ---------------------------------------------------------- aggregation
+
+// Maximal weighted matching of Sec. 2.2.  First pass: in visit order, an
+// unaggregated vertex opens a new aggregate with its heaviest unaggregated
+// neighbour (ties: smaller id).  Second pass: each vertex still alone joins
+// the aggregate of its heaviest neighbour (ties: smaller id); all of its
+// neighbours were paired in the first pass.
+int64_t match_aggregate(const Adjacency& g, const std::vector<int64_t>* order,
+                        std::vector<int64_t>& agg, std::vector<int8_t>& matched) {
+    const int64_t n = g.n;
+    agg.assign(n, -1);
+    matched.assign(n, 0);
+    int64_t next = 0;
+    for (int64_t t = 0; t < n; ++t) {
+        const int64_t v = order ? (*order)[t] : t;
+        if (agg[v] >= 0) continue;
+        int64_t pick = -1;
+        double pw = -1.0;
+        for (int64_t k = g.ptr[v]; k < g.ptr[v + 1]; ++k) {
+            const int32_t nb = g.col[k];
+            if (agg[nb] >= 0) continue;
+            if (g.w[k] > pw) { pw = g.w[k]; pick = nb; }   // ascending nb: first max wins
+        }
+        if (pick >= 0) {
+            agg[v] = agg[pick] = next++;
+            matched[v] = matched[pick] = 1;
+        }
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        if (matched[v]) continue;
+        int64_t pick = -1;
+        double pw = -1.0;
+        for (int64_t k = g.ptr[v]; k < g.ptr[v + 1]; ++k)
+            if (g.w[k] > pw) { pw = g.w[k]; pick = g.col[k]; }
+        agg[v] = agg[pick];
+    }
+    return next;
+}
+
+// Coarse graph of P^T L P: edges between different aggregates, weights
+// accumulated per unordered aggregate pair in ascending fine (i, j), i < j.
+// Contributions are bucketed by the smaller aggregate id in scan order (a
+// stable counting sort), then merged per bucket with a position table.
+void coarse_graph(const Adjacency& f, const std::vector<int64_t>& agg, int64_t nc,
+                  Adjacency& c) {
+    std::vector<int64_t> bstart(nc + 1, 0);
+    for (int64_t i = 0; i < f.n; ++i)
+        for (int64_t k = f.ptr[i]; k < f.ptr[i + 1]; ++k) {
+            const int32_t j = f.col[k];
+            if (j > i && agg[j] != agg[i]) ++bstart[std::min(agg[i], agg[j]) + 1];
+        }
+    for (int64_t a = 0; a < nc; ++a) bstart[a + 1] += bstart[a];
+    std::vector<int32_t> bkey(bstart[nc]);
+    std::vector<double> bval(bstart[nc]);
+    std::vector<int64_t> fp(bstart.begin(), bstart.end() - 1);
+    for (int64_t i = 0; i < f.n; ++i)
+        for (int64_t k = f.ptr[i]; k < f.ptr[i + 1]; ++k) {
+            const int32_t j = f.col[k];
+            if (j <= i || agg[j] == agg[i]) continue;
+            const int64_t lo = std::min(agg[i], agg[j]), hi = std::max(agg[i], agg[j]);
+            bkey[fp[lo]] = (int32_t)hi;
+            bval[fp[lo]] = f.w[k];
+            ++fp[lo];
+        }
+    // unique upper-triangle edges per row, ascending
+    std::vector<int64_t> where(nc, -1);
+    std::vector<int64_t> ustart(nc + 1, 0);
+    std::vector<int32_t> ukey;
+    std::vector<double> uval;
+    ukey.reserve(bstart[nc]);
+    uval.reserve(bstart[nc]);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t a = 0; a < nc; ++a) {
+        row.clear();
+        for (int64_t e = bstart[a]; e < bstart[a + 1]; ++e) {
+            const int32_t b = bkey[e];
+            if (where[b] >= 0) {
+                row[where[b]].second += bval[e];
+            } else {
+                where[b] = (int64_t)row.size();
+                row.push_back({b, bval[e]});
+            }
+        }
+        for (auto& p : row) where[p.first] = -1;
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                      return x.first < y.first;
+                  });
+        for (auto& p : row) { ukey.push_back(p.first); uval.push_back(p.second); }
+        ustart[a + 1] = (int64_t)ukey.size();
+    }
+    // symmetric CSR: row x = (entries from rows a < x, ascending a) + own list
+    c.n = nc;
+    c.ptr.assign(nc + 1, 0);
+    for (int64_t a = 0; a < nc; ++a)
+        for (int64_t e = ustart[a]; e < ustart[a + 1]; ++e) {
+            ++c.ptr[a + 1];
+            ++c.ptr[ukey[e] + 1];
+        }
+    for (int64_t a = 0; a < nc; ++a) c.ptr[a + 1] += c.ptr[a];
+    c.col.assign(c.ptr[nc], 0);
+    c.w.assign(c.ptr[nc], 0.0);
+    std::vector<int64_t> lowfill(c.ptr.begin(), c.ptr.end() - 1);
+    std::vector<int64_t> nlow(nc, 0);
+    for (int64_t a = 0; a < nc; ++a)
+        for (int64_t e = ustart[a]; e < ustart[a + 1]; ++e) ++nlow[ukey[e]];
+    std::vector<int64_t> highfill(nc);
+    for (int64_t a = 0; a < nc; ++a) highfill[a] = c.ptr[a] + nlow[a];
+    for (int64_t a = 0; a < nc; ++a)
+        for (int64_t e = ustart[a]; e < ustart[a + 1]; ++e) {
+            const int32_t b = ukey[e];
+            c.col[highfill[a]] = b;
+            c.w[highfill[a]] = uval[e];
+            ++highfill[a];
+            c.col[lowfill[b]] = (int32_t)a;
+            c.w[lowfill[b]] = uval[e];
+            ++lowfill[b];
+        }
+}
+
+// ------------------------------------------------------------- helpers
+
+static uint64_t mix64(uint64_t& s) {      // SplitMix64 (Steele, Lea, Flood 2014)
+    uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Fisher-Yates shuffle driven by SplitMix64 seeded with seed + level index.
+static std::vector<int64_t> visit_order(int64_t n, uint64_t seed) {
+    std::vector<int64_t> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    uint64_t s = seed;
+    for (int64_t i = n - 1; i > 0; --i) {
+        const int64_t j = (int64_t)(mix64(s) % (uint64_t)(i + 1));
+        std::swap(ord[i], ord[j]);
+    }
+    return ord;
+}
+
+// Pseudo-inverse of a connected Laplacian: (L + J/t)^-1 - J/t, J = 1 1^T.
+static bool laplacian_pinv(const Adjacency& g, std::vector<double>& out) {
+    const int t = (int)g.n;
+    std::vector<double> A(t * t, 1.0 / t), I(t * t, 0.0);
+    for (int i = 0; i < t; ++i) {
+        for (int64_t k = g.ptr[i]; k < g.ptr[i + 1]; ++k) {
+            A[i * t + g.col[k]] -= g.w[k];
+            A[i * t + i] += g.w[k];
+        }
+        I[i * t + i] = 1.0;
+    }
+    // Gauss-Jordan with partial pivoting (A is SPD).
+    for (int c = 0; c < t; ++c) {
+        int p = c;
+        for (int r = c + 1; r < t; ++r)
+            if (std::fabs(A[r * t + c]) > std::fabs(A[p * t + c])) p = r;
+        if (A[p * t + c] == 0.0) return false;
+        if (p != c)
+            for (int k = 0; k < t; ++k) {
+                std::swap(A[p * t + k], A[c * t + k]);
+                std::swap(I[p * t + k], I[c * t + k]);
+            }
+        const double d = 1.0 / A[c * t + c];
+        for (int k = 0; k < t; ++k) { A[c * t + k] *= d; I[c * t + k] *= d; }
+        for (int r = 0; r < t; ++r) {
+            if (r == c || A[r * t + c] == 0.0) continue;
+            const double f = A[r * t + c];
+            for (int k = 0; k < t; ++k) {
+                A[r * t + k] -= f * A[c * t + k];
+                I[r * t + k] -= f * I[c * t + k];
+            }
+        }
+    }
+    out.resize(t * t);
+    for (int i = 0; i < t * t; ++i) out[i] = I[i] - 1.0 / t;
+    return true;
+}
+
+// Level weight of the additive form of P(mu) L_T~^+ P(mu)^T:
+//   theta_k = s_k^2 mu^(-2k),  s_k = sum_{i<=k} (-mu)^i = (1 - (-mu)^(k+1)) / (1 + mu).
+static double level_theta(double mu, int k) {
+    const double s = (1.0 - std::pow(-mu, k + 1)) / (1.0 + mu);
+    return s * s * std::pow(mu, -2.0 * k);
+}
+
+// ---------------------------------------------------------------- plan
+
+int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+               const double* w, double mu, int max_levels, int64_t n_top,
+               uint64_t seed, bool host_only, HostPlan& plan) {
+    if (!(mu > 0.0 && mu < 1.0) || n_top < 2 || max_levels < 0) return kInval;
+    plan = HostPlan();
+    plan.mu = mu;
+    plan.lv.emplace_back();
+    int rc = build_adjacency(n, m, u, v, w, plan.lv[0].g);
+    if (rc != kOk) return rc;
+    if (!is_connected(plan.lv[0].g)) return kDisconnected;
+
+    // 1. hierarchy
+    while ((max_levels == 0 || (int)plan.lv.size() < max_levels) &&
+           plan.lv.back().g.n > n_top && plan.lv.size() < 60) {
+        Level& f = plan.lv.back();
+        std::vector<int64_t> agg;
+        std::vector<int8_t> mt;
+        int64_t nc;
+        if (seed != 0) {
+            std::vector<int64_t> ord = visit_order(f.g.n, seed + (uint64_t)plan.lv.size());
+            nc = match_aggregate(f.g, &ord, agg, mt);
+        } else {
+            nc = match_aggregate(f.g, nullptr, agg, mt);
+        }
+        if (nc < 2 || nc >= f.g.n) break;
+        Level c;
+        coarse_graph(f.g, agg, nc, c.g);
+        f.agg.swap(agg);
+        f.matched.swap(mt);
+        plan.lv.push_back(std::move(c));
+    }
+    const int L = plan.nlev();
+    const int T = L - 1;
+    if (plan.lv[T].g.n > kTopMax && !host_only) return kUnsupported;
+
+    // 2. tree numbering, top level first
+    plan.perm.assign(L, {});
+    plan.inv.assign(L, {});
+    plan.step.assign(T, {});
+    {
+        const int64_t nt = plan.lv[T].g.n;
+        plan.perm[T].resize(nt);
+        plan.inv[T].resize(nt);
+        std::iota(plan.perm[T].begin(), plan.perm[T].end(), 0);
+        std::iota(plan.inv[T].begin(), plan.inv[T].end(), 0);
+    }
+    for (int k = T - 1; k >= 0; --k) {
+        const Level& f = plan.lv[k];
+        const int64_t nk = f.g.n, nc = plan.lv[k + 1].g.n;
+        StepCoef& sc = plan.step[k];
+        sc.cptr.assign(nc + 1, 0);
+        for (int64_t i = 0; i < nk; ++i) ++sc.cptr[plan.inv[k + 1][f.agg[i]] + 1];
+        for (int64_t J = 0; J < nc; ++J) sc.cptr[J + 1] += sc.cptr[J];
+        std::vector<int32_t> pos(sc.cptr.begin(), sc.cptr.end() - 1);
+        plan.perm[k].resize(nk);
+        plan.inv[k].resize(nk);
+        for (int pass = 1; pass >= 0; --pass)      // matched members, then leftovers
+            for (int64_t i = 0; i < nk; ++i) {
+                if (f.matched[i] != pass) continue;
+                const int32_t J = plan.inv[k + 1][f.agg[i]];
+                plan.perm[k][pos[J]] = (int32_t)i;
+                plan.inv[k][i] = pos[J]++;
+            }
+    }
+
+    // 3. MSP coefficients
+    plan.theta.resize(L);
+    for (int k = 0; k < L; ++k) plan.theta[k] = level_theta(mu, k);
+    for (int k = 0; k < T; ++k) {
+        const Level& f = plan.lv[k];
+        StepCoef& sc = plan.step[k];
+        const int64_t nc = plan.lv[k + 1].g.n;
+        const double th = plan.theta[k];
+        const int64_t nleft = f.g.n - 2 * nc;
+        sc.saa.resize(nc); sc.sab.resize(nc); sc.sbb.resize(nc);
+        sc.l0.resize(nleft); sc.l1.resize(nleft); sc.l2.resize(nleft);
+        for (int64_t J = 0; J < nc; ++J) {
+            const int32_t b0 = sc.cptr[J], b1 = sc.cptr[J + 1];
+            if (b1 - b0 < 2) return kInval;   // cannot happen: every aggregate has a pair
+            const int32_t a = plan.perm[k][b0], b = plan.perm[k][b0 + 1];
+            const int64_t aggid = f.agg[a];
+            // pair block of L_B + mu diag(ext)
+            double wab = 0.0, ia = 0.0, ib = 0.0, ea = 0.0, eb = 0.0;
+            for (int64_t q = f.g.ptr[a]; q < f.g.ptr[a + 1]; ++q) {
+                if (f.agg[f.g.col[q]] == aggid) { ia += f.g.w[q]; if (f.g.col[q] == b) wab = f.g.w[q]; }
+                else ea += f.g.w[q];
+            }
+            for (int64_t q = f.g.ptr[b]; q < f.g.ptr[b + 1]; ++q) {
+                if (f.agg[f.g.col[q]] == aggid) ib += f.g.w[q];
+                else eb += f.g.w[q];
+            }
+            double Saa = ia + mu * ea, Sbb = ib + mu * eb, Sab = -wab;
+            for (int32_t t = b0 + 2; t < b1; ++t) {
+                const int32_t x = plan.perm[k][t];
+                double wa = 0.0, wb = 0.0, ex = 0.0;
+                for (int64_t q = f.g.ptr[x]; q < f.g.ptr[x + 1]; ++q) {
+                    const int32_t y = f.g.col[q];
+                    if (f.agg[y] != aggid) ex += f.g.w[q];
+                    else if (y == a) wa += f.g.w[q];
+                    else if (y == b) wb += f.g.w[q];
+                    else return kInval;     // leftovers are never adjacent
+                }
+                const double dxx = wa + wb + mu * ex;
+                Saa -= wa * wa / dxx;
+                Sbb -= wb * wb / dxx;
+                Sab -= wa * wb / dxx;
+                const int64_t li = t - 2 * (int64_t)(J + 1);
+                sc.l0[li] = th / dxx;
+                sc.l1[li] = wa / dxx;
+                sc.l2[li] = wb / dxx;
+            }
+            const double det = Saa * Sbb - Sab * Sab;
+            if (!(det > 0.0)) return kInval;
+            sc.saa[J] = th * Sbb / det;
+            sc.sbb[J] = th * Saa / det;
+            sc.sab[J] = -th * Sab / det;
+        }
+    }
+    if (plan.lv[T].g.n <= kTopMax) {
+        if (!laplacian_pinv(plan.lv[T].g, plan.top_pinv)) return kInval;
+        for (double& x : plan.top_pinv) x *= plan.theta[T];
+    }
+
+    // 4. fine Laplacian in tree order, sliced ELL
+    const Adjacency& g0 = plan.lv[0].g;
+    const int64_t nslice = (n + kSlice - 1) / kSlice;
+    plan.sell_off.assign(nslice + 1, 0);
+    plan.sell_width.assign(nslice, 0);
+    for (int64_t s = 0; s < nslice; ++s) {
+        int64_t wmax = 0;
+        for (int64_t t = s * kSlice; t < std::min<int64_t>(n, (s + 1) * kSlice); ++t) {
+            const int32_t o = plan.perm[0][t];
+            wmax = std::max<int64_t>(wmax, g0.ptr[o + 1] - g0.ptr[o]);
+        }
+        plan.sell_width[s] = (int32_t)wmax;
+        plan.sell_off[s + 1] = plan.sell_off[s] + (int32_t)(wmax * kSlice);
+    }
+    plan.sell_col.assign(plan.sell_off[nslice], 0);
+    plan.sell_w.assign(plan.sell_off[nslice], 0.0);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t t = 0; t < n; ++t) {
+        const int64_t s = t / kSlice, lane = t % kSlice;
+        const int32_t o = plan.perm[0][t];
+        row.clear();
+        for (int64_t q = g0.ptr[o]; q < g0.ptr[o + 1]; ++q)
+            row.push_back({plan.inv[0][g0.col[q]], g0.w[q]});
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                      return x.first < y.first;
+                  });
+        for (int64_t k = 0; k < plan.sell_width[s]; ++k) {
+            const int64_t slot = plan.sell_off[s] + k * kSlice + lane;
+            if (k < (int64_t)row.size()) {
+                plan.sell_col[slot] = row[k].first;
+                plan.sell_w[slot] = row[k].second;
+            } else {
+                plan.sell_col[slot] = (int32_t)t;   // padding: w = 0 on the row itself
+                plan.sell_w[slot] = 0.0;
+            }
+        }
+    }
+    return kOk;
+}
+
+}  // namespace lapgpu

@@ -1,0 +1,78 @@
+// Host-side setup of the MSP hierarchy (Hu & Lin, arXiv 2207.07847).
+//
+// Builds, on the CPU, everything the device solve reads:
+//   * the aggregation hierarchy by maximal weighted matching (Sec. 2.2) and
+//     the coarse graphs P^T L P;
+//   * a renumbering of every level in which the children of each aggregate
+//     are contiguous (matched pair first), so restriction and prolongation
+//     are segmented sums and broadcasts over ranges;
+//   * the closed-form coefficients of the MSP solve (Sec. 3.3): per
+//     aggregate the inverse of the 2x2 Schur complement of its sparsifier
+//     block, per leftover member its elimination coefficients, per level the
+//     weight theta_j, and the pseudo-inverse of the top-level Laplacian;
+//   * the fine Laplacian in sliced-ELL form in the renumbered order.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace lapgpu {
+
+enum Status { kOk = 0, kInval = 1, kDisconnected = 2, kNoMem = 3, kDevice = 4,
+              kNoConv = 5, kBreakdown = 6, kUnsupported = 7 };
+
+constexpr int kSlice = 64;        // rows per sliced-ELL slice (one wave)
+constexpr int kTopMax = 64;       // largest top level solved on chip
+
+// Symmetric weighted adjacency, neighbours ascending, no diagonal.
+struct Adjacency {
+    int64_t n = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> w;
+    int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+struct Level {
+    Adjacency g;                   // graph of this level, own numbering
+    std::vector<int64_t> agg;      // node -> aggregate (next level); empty on top
+    std::vector<int8_t> matched;   // 1: paired by the matching, 0: leftover
+};
+
+// Per aggregation step k (level k -> level k+1), in tree numbering.
+struct StepCoef {
+    std::vector<int32_t> cptr;               // children of aggregate J: [cptr[J], cptr[J+1])
+    std::vector<double> saa, sab, sbb;       // theta_k * inverse Schur complement (pair)
+    std::vector<double> l0, l1, l2;          // leftover t: theta_k/D_tt, w_ta/D_tt, w_tb/D_tt
+};
+
+struct HostPlan {
+    double mu = 0.8;
+    std::vector<Level> lv;                   // original numbering per level
+    std::vector<std::vector<int32_t>> perm;  // perm[k][tree id] = level-k id
+    std::vector<std::vector<int32_t>> inv;   // inv[k][level-k id] = tree id
+    std::vector<StepCoef> step;              // nlev-1 entries
+    std::vector<double> theta;               // theta_k, k = 0..nlev-1
+    std::vector<double> top_pinv;            // theta_top * pinv(L_top), row-major
+    // fine Laplacian, tree order, sliced ELL (64 rows per slice, column-major)
+    std::vector<int32_t> sell_off;           // slice -> first slot
+    std::vector<int32_t> sell_width;         // slice -> slots per row
+    std::vector<int32_t> sell_col;
+    std::vector<double> sell_w;
+    int nlev() const { return (int)lv.size(); }
+};
+
+int build_adjacency(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+                    const double* w, Adjacency& out);
+bool is_connected(const Adjacency& g);
+int64_t match_aggregate(const Adjacency& g, const std::vector<int64_t>* order,
+                        std::vector<int64_t>& agg, std::vector<int8_t>& matched);
+void coarse_graph(const Adjacency& f, const std::vector<int64_t>& agg, int64_t nc,
+                  Adjacency& c);
+// Full host setup; returns a Status.  host_only skips nothing here (the
+// device upload happens elsewhere) but allows tops larger than kTopMax.
+int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+               const double* w, double mu, int max_levels, int64_t n_top,
+               uint64_t seed, bool host_only, HostPlan& plan);
+
+}  // namespace lapgpu
