@@ -187,6 +187,11 @@ void lap_free(lap_hierarchy *h);
 /* Static string naming a status. */
 const char *lap_status_str(lap_status s);
 
+/* Description of the last HIP runtime failure seen by this thread (the
+ * failing call and HIP's error string), "" if none.  Valid until the next
+ * library call on the thread. */
+const char *lap_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -96,6 +96,9 @@ def lib():
     L.lr_pcg.argtypes = [vp, vp, vp, _f64p, C.c_double, C.c_int32, _f64p,
                          C.POINTER(_PcgInfo), vp]
     L.lr_pcg.restype = C.c_int
+    L.lr_pcg_noisy.argtypes = [vp, vp, vp, _f64p, C.c_double, C.c_int32, _f64p,
+                               C.POINTER(_PcgInfo), vp, C.c_double, C.c_uint64]
+    L.lr_pcg_noisy.restype = C.c_int
     _lib = L
     return L
 
@@ -252,6 +255,15 @@ class MSP:
         return z
 
 
+def iteration_band(g: Graph, b, tol, maxit, precond, seeds=8, noise=4e-16):
+    """(min, max) iteration count over the unperturbed run and `seeds` runs of
+    the rounding model (relative noise `noise` on L p and M r)."""
+    its = [pcg(g, b, tol, maxit, precond).iterations]
+    its += [pcg(g, b, tol, maxit, precond, noise=noise, seed=s + 1).iterations
+            for s in range(seeds)]
+    return min(its), max(its)
+
+
 class PcgResult:
     def __init__(self, x, info, hist):
         self.x = x
@@ -262,9 +274,10 @@ class PcgResult:
         self.hist = hist[: self.iterations + 1]
 
 
-def pcg(g: Graph, b, tol=1e-8, maxit=1000, precond=None):
+def pcg(g: Graph, b, tol=1e-8, maxit=1000, precond=None, noise=0.0, seed=0):
     """PCG on L_G x = b.  precond: None (plain CG), an MSP, or a callable
-    r -> z on numpy arrays (e.g. the PEGP of oracle.pegp)."""
+    r -> z on numpy arrays (e.g. the PEGP of oracle.pegp).  noise > 0 runs
+    the rounding model of lr_pcg_noisy."""
     L = lib()
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.empty(g.n)
@@ -285,7 +298,7 @@ def pcg(g: Graph, b, tol=1e-8, maxit=1000, precond=None):
 
         keep = PRECOND_FN(_cb)
         fn, ctx = C.cast(keep, C.c_void_p), None
-    L.lr_pcg(g.handle, fn, ctx, b, float(tol), int(maxit), x, C.byref(info),
-             hist.ctypes.data)
+    L.lr_pcg_noisy(g.handle, fn, ctx, b, float(tol), int(maxit), x, C.byref(info),
+                   hist.ctypes.data, float(noise), int(seed))
     del keep
     return PcgResult(x, info, hist)

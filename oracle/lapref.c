@@ -699,10 +699,32 @@ static void remove_mean(int64_t n, double *a)
  *           z = M r - mean; rho' = r.z; beta = rho'/rho; p = z + beta p.
  *   x -= mean(x); report ||b^ - L x|| / ||b^||.
  * relres_hist (optional, maxit+1 entries) receives ||r_k||/||b^||. */
+/* Rounding model for parity bands: with noise > 0 every product L p and
+ * every preconditioner output M r is multiplied entrywise by (1 + noise*u),
+ * u uniform in [-1, 1) from SplitMix64 seeded with `seed`.  A noise of a few
+ * units of round-off models a different summation order; the spread of the
+ * iteration count over seeds is the band an independent FP64 implementation
+ * of the same method can be expected to fall in. */
+static void perturb(int64_t n, double *a, double noise, uint64_t *s)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double u = (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0);
+        a[i] *= 1.0 + noise * (2.0 * u - 1.0);
+    }
+}
+
 int lr_pcg(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
            double tol, int32_t maxit, double *x, lr_pcg_info *info,
            double *relres_hist)
 {
+    return lr_pcg_noisy(g, M, ctx, b, tol, maxit, x, info, relres_hist, 0.0, 0);
+}
+
+int lr_pcg_noisy(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
+                 double tol, int32_t maxit, double *x, lr_pcg_info *info,
+                 double *relres_hist, double noise, uint64_t seed)
+{
+    uint64_t st = seed;
     int64_t n = g->n;
     double *bh = (double *)malloc(sizeof(double) * (size_t)n);
     double *r = (double *)malloc(sizeof(double) * (size_t)n);
@@ -725,11 +747,13 @@ int lr_pcg(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
     } else {
         if (M) M(ctx, r, z);
         else memcpy(z, r, sizeof(double) * (size_t)n);
+        if (noise > 0.0) perturb(n, z, noise, &st);
         remove_mean(n, z);
         memcpy(p, z, sizeof(double) * (size_t)n);
         double rho = dot(n, r, z);
         while (it < maxit) {
             lr_lap_apply(g, p, q);
+            if (noise > 0.0) perturb(n, q, noise, &st);
             ++it;
             double pq = dot(n, p, q);
             if (!(pq > 0.0) || !isfinite(pq)) {
@@ -749,6 +773,7 @@ int lr_pcg(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
             }
             if (M) M(ctx, r, z);
             else memcpy(z, r, sizeof(double) * (size_t)n);
+            if (noise > 0.0) perturb(n, z, noise, &st);
             remove_mean(n, z);
             double rho2 = dot(n, r, z);
             double beta = rho2 / rho;

@@ -105,6 +105,12 @@ typedef struct {
 int lr_pcg(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
            double tol, int32_t maxit, double *x, lr_pcg_info *info,
            double *relres_hist);
+/* Same, with L p and M r perturbed entrywise by relative noise in
+ * [-noise, noise) (SplitMix64 stream from seed): a rounding model used to
+ * measure how far iteration counts move under reordered FP64 arithmetic. */
+int lr_pcg_noisy(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
+                 double tol, int32_t maxit, double *x, lr_pcg_info *info,
+                 double *relres_hist, double noise, uint64_t seed);
 
 #ifdef __cplusplus
 }

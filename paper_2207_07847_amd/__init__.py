@@ -53,6 +53,11 @@ class lap_hierarchy_desc(C.Structure):
 
 
 def _load():
+    # Device buffers come from torch, so the library must run on the same HIP
+    # runtime instance: torch ships its own libamdhip64.so.7; importing torch
+    # first makes the dynamic loader resolve the library's libamdhip64.so.7 to
+    # that copy instead of mapping a second runtime into the process.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2207_07847_amd.build")
     L = C.CDLL(LIB_PATH)
@@ -70,6 +75,8 @@ def _load():
                                      C.POINTER(C.c_double)]
     L.lap_free.argtypes = [vp]
     L.lap_free.restype = None
+    L.lap_last_error.argtypes = []
+    L.lap_last_error.restype = C.c_char_p
     L.lap_status_str.argtypes = [C.c_int]
     L.lap_status_str.restype = C.c_char_p
     for f in ("lap_default_params", "lap_setup", "lap_solve", "lap_apply_laplacian",
@@ -84,8 +91,13 @@ _lib = _load()
 
 class LapError(RuntimeError):
     def __init__(self, status, what=""):
-        super().__init__(f"{what}: {lap_status_str(status)}")
+        extra = lap_last_error() if status == LAP_EDEVICE else ""
+        super().__init__(f"{what}: {lap_status_str(status)} {extra}".rstrip())
         self.status = status
+
+
+def lap_last_error() -> str:
+    return _lib.lap_last_error().decode()
 
 
 def lap_status_str(status: int) -> str:

@@ -33,10 +33,7 @@ struct Scal {
     int32_t maxit;
     int32_t done;   // 0 running, 1 converged, 2 max_iter, 3 breakdown, 4 bad input
     int32_t first;  // next preconditioner result starts a new direction (beta = 0)
-    uint32_t cnt[8];// arrival counters of the last-block reductions
 };
-
-enum { kCntSpmv = 0, kCntUpd = 1, kCntDown = 2, kCntInit = 3, kCntFin = 4, kCntMisc = 5 };
 
 // Level table entry (device copy of per-level pointers).
 struct LevelDev {
@@ -53,6 +50,27 @@ struct LevelDev {
     const double* l2;   //             w(t, b) / D_tt
     double* ea;         // eta of the pair member a (theta-scaled)
     double* eb;
+};
+
+// Layout of the coarse tail in LDS (offsets in doubles from the start of the
+// dynamic shared buffer).  The read-only part [0, pack) is a byte copy of a
+// device buffer built by the host; the rest is work space.
+struct TailStep {
+    int32_t nk, nc, nl;                // children, aggregates, leftovers
+    int32_t cptr;                      // int32[nc+1], stored in double slots
+    int32_t saa, sab, sbb, l0, l1, l2; // coefficients
+    int32_t ea, eb;                    // work: pair corrections
+};
+constexpr int kMaxTailSteps = 62;
+struct TailDesc {
+    int32_t nsteps;                    // levels kt .. top-1
+    int32_t nt;                        // nodes on the top level
+    int32_t pack;                      // doubles copied from the device pack
+    int32_t total;                     // doubles of LDS used
+    int32_t pinv;                      // theta_top * pinv(L_top), nt*nt
+    int32_t r[kMaxTailSteps + 1];      // work: r of level kt+s (s = 0..nsteps)
+    int32_t y[kMaxTailSteps + 1];      // work: y of level kt+s
+    TailStep st[kMaxTailSteps];
 };
 
 struct Sell {

@@ -19,6 +19,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -59,39 +60,78 @@ __device__ inline void block_sum(double (&v)[N], double* lds) {
         }
 }
 
-// Each block stores its partial sums; the last block to arrive adds all
-// partials in block order and returns true (totals in tot, thread 0).
+// Each block stores its partial sums (value i of block b at part[i*G + b]);
+// a one-block finish kernel adds them in block order after the producing
+// kernel has completed.  No device-scope fence is needed inside the
+// producer: the kernel boundary orders the partials before the finish.
 template <int N>
-__device__ inline bool last_block_sum(double (&v)[N], double* part, uint32_t* counter,
-                                      double (&tot)[N]) {
+__device__ inline void block_partial(double (&v)[N], double* part) {
     __shared__ double lds[N * (kBlock / 64)];
-    __shared__ int is_last;
     block_sum<N, kBlock>(v, lds);
-    const int G = gridDim.x;
     if (threadIdx.x == 0) {
+        const int G = gridDim.x;
 #pragma unroll
         for (int i = 0; i < N; ++i) part[i * G + blockIdx.x] = v[i];
-        __threadfence();
-        const uint32_t t = atomicAdd(counter, 1u);
-        is_last = (t == (uint32_t)(G - 1));
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double s[N];
+}
+
+enum FinOp { kFinPq, kFinRr, kFinRho, kFinBsum, kFinBn2, kFinXsum, kFinRes2 };
+
+// Sums the partials of a producer grid of G blocks in a fixed order and
+// applies the scalar step of the solver that needs the total.
+template <int OP>
+__global__ __launch_bounds__(kBlock) void k_finish(int G, int n, const double* __restrict__ part,
+                                                   Scal* S) {
+    constexpr int N = (OP == kFinRho) ? 3 : 1;
+    const bool loop = OP == kFinPq || OP == kFinRr || OP == kFinRho;
+    if (loop && S->done) return;
+    __shared__ double lds[N * (kBlock / 64)];
+    double v[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) s[i] = 0.0;
+    for (int i = 0; i < N; ++i) v[i] = 0.0;
     for (int b = threadIdx.x; b < G; b += kBlock)
 #pragma unroll
-        for (int i = 0; i < N; ++i) s[i] += part[i * G + b];
-    __syncthreads();
-    block_sum<N, kBlock>(s, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) tot[i] = s[i];
-        *counter = 0u;
+        for (int i = 0; i < N; ++i) v[i] += part[i * G + b];
+    block_sum<N, kBlock>(v, lds);
+    if (threadIdx.x != 0) return;
+    if (OP == kFinPq) {
+        const double pq = v[0];
+        S->pq = pq;
+        S->iter += 1;
+        if (!(pq > 0.0) || !isfinite(pq)) S->done = 3;
+        else S->alpha = S->rho / pq;
+    } else if (OP == kFinRr) {
+        S->rr = v[0];
+        if (!isfinite(v[0])) S->done = 3;
+        else if (v[0] <= S->tol2 * S->bn2) S->done = 1;
+        else if (S->iter >= S->maxit) S->done = 2;
+    } else if (OP == kFinRho) {
+        const double zbar = v[0] / (double)n;
+        const double rho = v[1] - zbar * v[N - 1];
+        S->zbar = zbar;
+        if (!isfinite(rho)) S->done = 3;
+        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->first = 0;
+        S->rho = rho;
+    } else if (OP == kFinBsum) {
+        S->bsum = v[0];
+    } else if (OP == kFinBn2) {
+        S->bn2 = v[0];
+        S->iter = 0;
+        S->first = 1;
+        S->alpha = 0.0;
+        S->beta = 0.0;
+        S->zbar = 0.0;
+        S->rr = v[0];
+        if (!isfinite(v[0])) S->done = 4;
+        else if (v[0] == 0.0) S->done = 1;
+        else if (S->maxit <= 0) S->done = 2;
+        else S->done = 0;
+    } else if (OP == kFinXsum) {
+        S->xsum = v[0];
+    } else if (OP == kFinRes2) {
+        S->res2 = v[0];
     }
-    return true;
 }
 
 // --------------------------------------------------- aggregate primitives
@@ -156,14 +196,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* 
         pnew[row] = pi;
         q[row] = acc;
     }
-    double v[1] = {pi * acc}, tot[1];
-    if (last_block_sum<1>(v, part, &S->cnt[kCntSpmv], tot) && threadIdx.x == 0) {
-        const double pq = tot[0];
-        S->pq = pq;
-        S->iter += 1;
-        if (!(pq > 0.0) || !isfinite(pq)) S->done = 3;
-        else S->alpha = S->rho / pq;
-    }
+    double v[1] = {pi * acc};
+    block_partial<1>(v, part);
 }
 
 // x += alpha p; r -= alpha q; ||r||^2; fused restriction of r to level 1.
@@ -191,13 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev s0, double* __re
         agg_up(s0, r, r1, J);
     }
     if (!do_update) return;
-    double v[1] = {rr}, tot[1];
-    if (last_block_sum<1>(v, part, &S->cnt[kCntUpd], tot) && threadIdx.x == 0) {
-        S->rr = tot[0];
-        if (!isfinite(tot[0])) S->done = 3;
-        else if (tot[0] <= S->tol2 * S->bn2) S->done = 1;
-        else if (S->iter >= S->maxit) S->done = 2;
-    }
+    double v[1] = {rr};
+    block_partial<1>(v, part);
 }
 
 // Plain CG variant of update_up0 (no preconditioner).
@@ -216,13 +245,8 @@ __global__ __launch_bounds__(kBlock) void k_update_none(int n, double* __restric
         r[t] = rt;
         rr = rt * rt;
     }
-    double v[1] = {rr}, tot[1];
-    if (last_block_sum<1>(v, part, &S->cnt[kCntUpd], tot) && threadIdx.x == 0) {
-        S->rr = tot[0];
-        if (!isfinite(tot[0])) S->done = 3;
-        else if (tot[0] <= S->tol2 * S->bn2) S->done = 1;
-        else if (S->iter >= S->maxit) S->done = 2;
-    }
+    double v[1] = {rr};
+    block_partial<1>(v, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_up(LevelDev s, const double* __restrict__ rk,
@@ -240,34 +264,82 @@ __global__ __launch_bounds__(kBlock) void k_down(LevelDev s, const double* __res
     if (J < s.nc) agg_down(s, rk, yk, yk1, J);
 }
 
-// Levels kt .. top in one workgroup: restriction and local solves upwards,
-// theta_top * pinv(L_top) on the top, prolongation and corrections back.
-__global__ __launch_bounds__(kTailThreads) void k_tail(const LevelDev* __restrict__ tab, int kt,
-                                                       int top, const double* __restrict__ tp,
-                                                       const Scal* S) {
+// Levels kt .. top in one workgroup, entirely in LDS: the coefficients of
+// those levels are staged from one packed device buffer with a coalesced
+// copy, then restriction + local solves run upwards, theta_top pinv(L_top)
+// on the top, prolongation + corrections back down to level kt.
+__global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restrict__ D,
+                                                       const double* __restrict__ pack,
+                                                       const double* __restrict__ r_kt,
+                                                       double* __restrict__ y_kt, const Scal* S) {
     if (S->done) return;
-    for (int k = kt; k < top; ++k) {
-        const LevelDev s = tab[k];
-        double* rk1 = tab[k + 1].r;
-        for (int J = threadIdx.x; J < s.nc; J += blockDim.x) agg_up(s, s.r, rk1, J);
+    extern __shared__ double sm[];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int npack = D->pack, nsteps = D->nsteps;
+    for (int i = tid; i < npack; i += nth) sm[i] = pack[i];
+    {
+        const int n0 = nsteps > 0 ? D->st[0].nk : D->nt;
+        double* r0 = sm + D->r[0];
+        for (int i = tid; i < n0; i += nth) r0[i] = r_kt[i];
+    }
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        const TailStep t = D->st[s];
+        const int* cp = reinterpret_cast<const int*>(sm + t.cptr);
+        const double* rk = sm + D->r[s];
+        double* rk1 = sm + D->r[s + 1];
+        for (int J = tid; J < t.nc; J += nth) {
+            const int b0 = cp[J], b1 = cp[J + 1];
+            const double ra = rk[b0], rb = rk[b0 + 1];
+            double sum = ra + rb, ga = ra, gb = rb;
+            for (int c = b0 + 2; c < b1; ++c) {
+                const int li = c - 2 * J - 2;
+                const double rv = rk[c];
+                sum += rv;
+                ga += sm[t.l1 + li] * rv;
+                gb += sm[t.l2 + li] * rv;
+            }
+            const double saa = sm[t.saa + J], sab = sm[t.sab + J], sbb = sm[t.sbb + J];
+            sm[t.ea + J] = saa * ga + sab * gb;
+            sm[t.eb + J] = sab * ga + sbb * gb;
+            rk1[J] = sum;
+        }
         __syncthreads();
     }
     {
-        const int nt = tab[top].n;
-        const double* rT = tab[top].r;
-        double* yT = tab[top].y;
-        for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+        const int nt = D->nt;
+        const double* rT = sm + D->r[nsteps];
+        double* yT = sm + D->y[nsteps];
+        const double* tp = sm + D->pinv;
+        for (int i = tid; i < nt; i += nth) {
             double acc = 0.0;
             for (int j = 0; j < nt; ++j) acc += tp[i * nt + j] * rT[j];
             yT[i] = acc;
         }
         __syncthreads();
     }
-    for (int k = top - 1; k >= kt; --k) {
-        const LevelDev s = tab[k];
-        const double* yk1 = tab[k + 1].y;
-        for (int J = threadIdx.x; J < s.nc; J += blockDim.x) agg_down(s, s.r, s.y, yk1, J);
+    for (int s = nsteps - 1; s >= 0; --s) {
+        const TailStep t = D->st[s];
+        const int* cp = reinterpret_cast<const int*>(sm + t.cptr);
+        const double* rk = sm + D->r[s];
+        double* yk = sm + D->y[s];
+        const double* yk1 = sm + D->y[s + 1];
+        for (int J = tid; J < t.nc; J += nth) {
+            const int b0 = cp[J], b1 = cp[J + 1];
+            const double yJ = yk1[J], ea = sm[t.ea + J], eb = sm[t.eb + J];
+            yk[b0] = ea + yJ;
+            yk[b0 + 1] = eb + yJ;
+            for (int c = b0 + 2; c < b1; ++c) {
+                const int li = c - 2 * J - 2;
+                yk[c] = sm[t.l0 + li] * rk[c] + sm[t.l1 + li] * ea + sm[t.l2 + li] * eb + yJ;
+            }
+        }
         __syncthreads();
+    }
+    {
+        const int n0 = nsteps > 0 ? D->st[0].nk : D->nt;
+        const double* y0 = sm + D->y[0];
+        for (int i = tid; i < n0; i += nth) y_kt[i] = y0[i];
     }
 }
 
@@ -289,16 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_down0(LevelDev s0, int n, const doub
             v[2] += rt;
         }
     }
-    double tot[3];
-    if (last_block_sum<3>(v, part, &S->cnt[kCntDown], tot) && threadIdx.x == 0) {
-        const double zbar = tot[0] / (double)n;
-        const double rho = tot[1] - zbar * tot[2];
-        S->zbar = zbar;
-        if (!isfinite(rho)) S->done = 3;
-        S->beta = S->first ? 0.0 : rho / S->rho;
-        S->first = 0;
-        S->rho = rho;
-    }
+    block_partial<3>(v, part);
 }
 
 // One-level hierarchy (top = fine level, at most kTopMax nodes): the MSP is
@@ -344,16 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_prec_none(int n, const double* __res
         v[1] = rt * rt;
         v[2] = rt;
     }
-    double tot[3];
-    if (last_block_sum<3>(v, part, &S->cnt[kCntDown], tot) && threadIdx.x == 0) {
-        const double zbar = tot[0] / (double)n;
-        const double rho = tot[1] - zbar * tot[2];
-        S->zbar = zbar;
-        if (!isfinite(rho)) S->done = 3;
-        S->beta = S->first ? 0.0 : rho / S->rho;
-        S->first = 0;
-        S->rho = rho;
-    }
+    block_partial<3>(v, part);
 }
 
 // dst[t] = src[perm[t]] (gather into tree order) and sum -> S->bsum.
@@ -362,13 +416,13 @@ __global__ __launch_bounds__(kBlock) void k_gather_sum(int n, const int32_t* __r
                                                        double* __restrict__ dst, Scal* S,
                                                        double* part) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    double v[1] = {0.0}, tot[1];
+    double v[1] = {0.0};
     if (t < n) {
         const double b = src[perm[t]];
         dst[t] = b;
         v[0] = b;
     }
-    if (last_block_sum<1>(v, part, &S->cnt[kCntInit], tot) && threadIdx.x == 0) S->bsum = tot[0];
+    block_partial<1>(v, part);
 }
 
 // b^ = b - mean; r = b^; x = p0 = p1 = 0; ||b^||^2 -> bn2, run flags.
@@ -377,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, double* __restrict__ b, 
                                                  double* __restrict__ p1, Scal* S, double* part) {
     const double mean = S->bsum / (double)n;
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    double v[1] = {0.0}, tot[1];
+    double v[1] = {0.0};
     if (t < n) {
         const double bh = b[t] - mean;
         b[t] = bh;
@@ -387,26 +441,14 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, double* __restrict__ b, 
         p1[t] = 0.0;
         v[0] = bh * bh;
     }
-    if (last_block_sum<1>(v, part, &S->cnt[kCntInit], tot) && threadIdx.x == 0) {
-        S->bn2 = tot[0];
-        S->iter = 0;
-        S->first = 1;
-        S->alpha = 0.0;
-        S->beta = 0.0;
-        S->zbar = 0.0;
-        S->rr = tot[0];
-        if (!isfinite(tot[0])) S->done = 4;
-        else if (tot[0] == 0.0) S->done = 1;
-        else if (S->maxit <= 0) S->done = 2;
-        else S->done = 0;
-    }
+    block_partial<1>(v, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum(int n, const double* __restrict__ a, Scal* S,
                                                 double* part) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    double v[1] = {t < n ? a[t] : 0.0}, tot[1];
-    if (last_block_sum<1>(v, part, &S->cnt[kCntFin], tot) && threadIdx.x == 0) S->xsum = tot[0];
+    double v[1] = {t < n ? a[t] : 0.0};
+    block_partial<1>(v, part);
 }
 
 // xc = x - mean(x) in tree order and dst[perm[t]] = xc[t].
@@ -429,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(int n, Sell A, const double* _
                                                   const double* __restrict__ bh, Scal* S,
                                                   double* part) {
     const int row = blockIdx.x * kBlock + threadIdx.x;
-    double v[1] = {0.0}, tot[1];
+    double v[1] = {0.0};
     if (row < n) {
         const double xi = x[row];
         const int sl = row >> 6;
@@ -440,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(int n, Sell A, const double* _
         const double d = bh[row] - acc;
         v[0] = d * d;
     }
-    if (last_block_sum<1>(v, part, &S->cnt[kCntFin], tot) && threadIdx.x == 0) S->res2 = tot[0];
+    block_partial<1>(v, part);
 }
 
 // y[perm[t]] = (L x~)_t with x~[t] = x[perm[t]] (original order in and out).
@@ -484,9 +526,21 @@ namespace {
 inline int nblk(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 struct HipErr {};
-#define HIPCHK(expr)                                  \
-    do {                                              \
-        if ((expr) != hipSuccess) throw HipErr();     \
+thread_local char g_last_error[256] = "";
+
+void record_error(const char* what, hipError_t e, int line) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "lap.hip:%d %s -> %s (%d)", line, what,
+                  hipGetErrorString(e), (int)e);
+    if (std::getenv("LAPGPU_DEBUG")) std::fprintf(stderr, "[lapgpu] %s\n", g_last_error);
+}
+
+#define HIPCHK(expr)                                      \
+    do {                                                  \
+        const hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) {                           \
+            record_error(#expr, e_, __LINE__);            \
+            throw HipErr();                               \
+        }                                                 \
     } while (0)
 
 int tail_max_default() {
@@ -495,7 +549,66 @@ int tail_max_default() {
         const int v = std::atoi(s);
         if (v > 0) return v;
     }
-    return 8192;
+    return 1 << 30;   // largest tail that fits in LDS
+}
+
+constexpr size_t kTailLdsBytes = 152 * 1024;
+
+// Doubles of LDS the tail needs when it starts at level kt.
+size_t tail_lds_doubles(const HostPlan& P, int kt) {
+    const int T = P.nlev() - 1;
+    size_t d = 0;
+    for (int k = kt; k < T; ++k) {
+        const size_t nk = P.lv[k].g.n, nc = P.lv[k + 1].g.n, nl = nk - 2 * nc;
+        d += (nc + 2) / 2 + 3 * nc + 3 * nl + 2 * nc;   // cptr, pair, leftover, eta
+    }
+    for (int k = kt; k <= T; ++k) d += 2 * P.lv[k].g.n;     // r, y
+    d += P.lv[T].g.n * P.lv[T].g.n;                        // top pseudo-inverse
+    return d;
+}
+
+// Pack the tail coefficients of levels kt..T into one buffer and lay out
+// the LDS work space after it.
+void build_tail(const HostPlan& P, int kt, TailDesc& D, std::vector<double>& pack) {
+    const int T = P.nlev() - 1;
+    D.nsteps = T - kt;
+    D.nt = (int32_t)P.lv[T].g.n;
+    auto put = [&](const double* src, size_t cnt) {
+        const int32_t off = (int32_t)pack.size();
+        pack.insert(pack.end(), src, src + cnt);
+        return off;
+    };
+    for (int s = 0; s < D.nsteps; ++s) {
+        const int k = kt + s;
+        const StepCoef& c = P.step[k];
+        TailStep& t = D.st[s];
+        t.nk = (int32_t)P.lv[k].g.n;
+        t.nc = (int32_t)P.lv[k + 1].g.n;
+        t.nl = t.nk - 2 * t.nc;
+        t.cptr = (int32_t)pack.size();
+        const size_t cslots = (c.cptr.size() + 1) / 2;
+        pack.resize(pack.size() + cslots, 0.0);
+        std::memcpy(pack.data() + t.cptr, c.cptr.data(), c.cptr.size() * sizeof(int32_t));
+        t.saa = put(c.saa.data(), c.saa.size());
+        t.sab = put(c.sab.data(), c.sab.size());
+        t.sbb = put(c.sbb.data(), c.sbb.size());
+        t.l0 = put(c.l0.data(), c.l0.size());
+        t.l1 = put(c.l1.data(), c.l1.size());
+        t.l2 = put(c.l2.data(), c.l2.size());
+    }
+    D.pinv = put(P.top_pinv.data(), P.top_pinv.size());
+    D.pack = (int32_t)pack.size();
+    int32_t w = D.pack;
+    for (int s = 0; s <= D.nsteps; ++s) {
+        const int32_t nk = (int32_t)P.lv[kt + s].g.n;
+        D.r[s] = w; w += nk;
+        D.y[s] = w; w += nk;
+    }
+    for (int s = 0; s < D.nsteps; ++s) {
+        D.st[s].ea = w; w += D.st[s].nc;
+        D.st[s].eb = w; w += D.st[s].nc;
+    }
+    D.total = w;
 }
 
 int chunk_default() {
@@ -526,6 +639,9 @@ struct lap_hierarchy {
     LevelDev* d_lv = nullptr;
     double* top_pinv = nullptr;
     int kt = 1;
+    TailDesc* d_tail = nullptr;
+    double* tail_pack = nullptr;
+    size_t tail_lds = 0;
     // workspace
     double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr, *xc = nullptr;
     double* p[2] = {nullptr, nullptr};
@@ -568,41 +684,44 @@ namespace {
 // then up, tail, down, down0) or the plain-CG equivalent.
 void enqueue_precond(lap_hierarchy* h, hipStream_t s, int do_update, const double* pcur) {
     const int T = h->plan.nlev() - 1;
-    if (!h->with_msp) {
-        if (do_update)
+    if (!h->with_msp || T == 0) {
+        if (do_update) {
             hipLaunchKernelGGL(k_update_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n,
                                h->x, h->r, pcur, h->q, h->S, h->part);
-        hipLaunchKernelGGL(k_prec_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n, h->r,
-                           h->z, h->S, h->part);
-        return;
-    }
-    if (T == 0) {
-        if (do_update)
-            hipLaunchKernelGGL(k_update_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n,
-                               h->x, h->r, pcur, h->q, h->S, h->part);
-        hipLaunchKernelGGL(k_top_only, dim3(1), dim3(kBlock), 0, s, (int)h->n, h->top_pinv, h->r,
-                           h->z, h->S);
+            hipLaunchKernelGGL(k_finish<kFinRr>, dim3(1), dim3(kBlock), 0, s, nblk(h->n), (int)h->n, h->part, h->S);
+        }
+        if (!h->with_msp) {
+            hipLaunchKernelGGL(k_prec_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n, h->r,
+                               h->z, h->S, h->part);
+            hipLaunchKernelGGL(k_finish<kFinRho>, dim3(1), dim3(kBlock), 0, s, nblk(h->n), (int)h->n, h->part, h->S);
+        } else {
+            hipLaunchKernelGGL(k_top_only, dim3(1), dim3(kBlock), 0, s, (int)h->n, h->top_pinv,
+                               h->r, h->z, h->S);
+        }
         return;
     }
     const LevelDev& s0 = h->lv[0];
     hipLaunchKernelGGL(k_update_up0, dim3(nblk(s0.nc)), dim3(kBlock), 0, s, s0, h->x, h->r, pcur,
                        h->q, h->lv[1].r, h->S, h->part, do_update);
+    if (do_update) hipLaunchKernelGGL(k_finish<kFinRr>, dim3(1), dim3(kBlock), 0, s, nblk(s0.nc), (int)h->n, h->part, h->S);
     for (int k = 1; k < h->kt; ++k)
         hipLaunchKernelGGL(k_up, dim3(nblk(h->lv[k].nc)), dim3(kBlock), 0, s, h->lv[k], h->lv[k].r,
                            h->lv[k + 1].r, h->S);
-    hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), 0, s, h->d_lv, h->kt, T, h->top_pinv,
-                       h->S);
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), h->tail_lds, s, h->d_tail,
+                       h->tail_pack, h->lv[h->kt].r, h->lv[h->kt].y, h->S);
     for (int k = h->kt - 1; k >= 1; --k)
         hipLaunchKernelGGL(k_down, dim3(nblk(h->lv[k].nc)), dim3(kBlock), 0, s, h->lv[k],
                            h->lv[k].r, h->lv[k].y, h->lv[k + 1].y, h->S);
     hipLaunchKernelGGL(k_down0, dim3(nblk(s0.nc)), dim3(kBlock), 0, s, s0, (int)h->n, h->r, h->z,
                        h->lv[1].y, h->S, h->part);
+    hipLaunchKernelGGL(k_finish<kFinRho>, dim3(1), dim3(kBlock), 0, s, nblk(s0.nc), (int)h->n, h->part, h->S);
 }
 
 // One PCG iteration reading p[par] and writing p[1-par].
 void enqueue_iteration(lap_hierarchy* h, hipStream_t s, int par) {
     hipLaunchKernelGGL(k_spmv_p, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n, h->A, h->z,
                        h->p[par], h->p[1 - par], h->q, h->S, h->part);
+    hipLaunchKernelGGL(k_finish<kFinPq>, dim3(1), dim3(kBlock), 0, s, nblk(h->n), (int)h->n, h->part, h->S);
     enqueue_precond(h, s, 1, h->p[1 - par]);
 }
 
@@ -610,6 +729,7 @@ void build_graph(lap_hierarchy* h) {
     HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < h->chunk; ++i) enqueue_iteration(h, h->cap, i & 1);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamEndCapture(h->cap, &h->graph));
     HIPCHK(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
 }
@@ -628,7 +748,11 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     const int tail_max = tail_max_default();
     h->kt = T;
     for (int k = 1; k <= T; ++k)
-        if (P.lv[k].g.n <= tail_max) { h->kt = k; break; }
+        if (P.lv[k].g.n <= tail_max && T - k <= kMaxTailSteps &&
+            tail_lds_doubles(P, k) * sizeof(double) <= kTailLdsBytes) {
+            h->kt = k;
+            break;
+        }
     for (int k = 0; k < L; ++k) {
         LevelDev& d = h->lv[k];
         d.n = (int32_t)P.lv[k].g.n;
@@ -652,6 +776,19 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     }
     h->d_lv = h->upload(h->lv, s);
     h->top_pinv = h->upload(P.top_pinv, s);
+    if (T >= 1) {
+        TailDesc desc{};
+        std::vector<double> pack;
+        build_tail(P, h->kt, desc, pack);
+        h->tail_pack = h->upload(pack, s);
+        h->d_tail = h->dalloc<TailDesc>(1);
+        HIPCHK(hipMemcpyAsync(h->d_tail, &desc, sizeof(desc), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        h->tail_lds = (size_t)desc.total * sizeof(double);
+        HIPCHK(hipFuncSetAttribute((const void*)k_tail,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kTailLdsBytes));
+    }
     const int64_t n = h->n;
     h->b = h->dalloc<double>(n);
     h->x = h->dalloc<double>(n);
@@ -667,6 +804,7 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     std::memset(h->stage, 0, sizeof(Scal));
     HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
     h->chunk = chunk_default();
     build_graph(h);
 }
@@ -692,8 +830,10 @@ lap_status solve_one(lap_hierarchy* h, const double* b, double* x, double tol,
     HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_gather_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, b, h->b, h->S,
                        h->part);
+    hipLaunchKernelGGL(k_finish<kFinBsum>, dim3(1), dim3(kBlock), 0, s, nblk(n), (int)h->n, h->part, h->S);
     hipLaunchKernelGGL(k_init, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->b, h->r, h->x, h->p[0],
                        h->p[1], h->S, h->part);
+    hipLaunchKernelGGL(k_finish<kFinBn2>, dim3(1), dim3(kBlock), 0, s, nblk(n), (int)h->n, h->part, h->S);
     enqueue_precond(h, s, 0, h->p[0]);
     HIPCHK(hipGetLastError());
     // chunks of iterations; one chunk in flight beyond the one being checked
@@ -711,10 +851,12 @@ lap_status solve_one(lap_hierarchy* h, const double* b, double* x, double tol,
     (void)hipEventDestroy(ev);
     // mean-free x in original order, true residual
     hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->x, h->S, h->part);
+    hipLaunchKernelGGL(k_finish<kFinXsum>, dim3(1), dim3(kBlock), 0, s, nblk(n), (int)h->n, h->part, h->S);
     hipLaunchKernelGGL(k_center_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, h->x,
                        h->xc, x, h->S);
     hipLaunchKernelGGL(k_resid, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, h->xc, h->b, h->S,
                        h->part);
+    hipLaunchKernelGGL(k_finish<kFinRes2>, dim3(1), dim3(kBlock), 0, s, nblk(n), (int)h->n, h->part, h->S);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -986,5 +1128,7 @@ lap_status lap_export_graph(const lap_hierarchy* h, int32_t level, int64_t* ptr,
 }
 
 void lap_free(lap_hierarchy* h) { delete h; }
+
+const char* lap_last_error(void) { return g_last_error; }
 
 }  // extern "C"
