@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-reps", type=int, default=100)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="cap per solve (profiling runs); a capped solve is not a valid step")
     args = ap.parse_args()
@@ -135,6 +137,14 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     iters = inf["iterations"]
+
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb * 131072, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # dominant kernel, timed live on the solve stream
     kern = {}

@@ -13,6 +13,7 @@ namespace lapgpu {
 
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kTailThreads = 1024; // threads of the one-block coarse tail
+constexpr int kFinThreads = 1024;  // threads of the one-block reduction finish
 constexpr int kMaxGridPart = 3;    // values reduced per block
 
 // Scalars of one PCG run, resident in device memory.
@@ -72,6 +73,66 @@ struct TailDesc {
     int32_t y[kMaxTailSteps + 1];      // work: y of level kt+s
     TailStep st[kMaxTailSteps];
 };
+
+// A group of consecutive levels [k0, k1) processed block-locally: block b
+// owns the level-k1 nodes [D[m][b], D[m][b+1]) (m = k1 - k0) and, on every
+// level j = k0 + i, their descendants [D[i][b], D[i][b+1]), contiguous in the
+// tree numbering.  Each block's coefficients are pre-packed contiguously in
+// the order of its LDS carve, so staging is one flat copy; the up-sweep
+// leaves its intermediate values in a per-block scratch chunk laid out for
+// the down-sweep's carve.
+constexpr int kGrpThreads = 256;
+constexpr int kMaxGroupLevels = 12;
+struct GroupDev {
+    int32_t k0, k1, nblocks;
+    const int32_t* D;        // (m+1) rows of nblocks+1 entries
+    const int32_t* uoff;     // up pack offset of each block (nblocks+1)
+    const int32_t* doff;     // down pack offset of each block
+    const int32_t* xoff;     // scratch offset of each block
+    const double* upack;     // per level: cp (local), pair coefficients, l1, l2
+    const double* dpack;     // per level: cp (local), l0, l1, l2
+    double* scr;             // per level: r (levels 1..m-1), then eta a, eta b
+    double* r_top;           // level k1 residual (output of the up-sweep)
+    const double* y_top;     // level k1 correction (input of the down-sweep)
+    const double* r_in;      // level k0 residual (input)
+    double* y_out;           // level k0 correction (output)
+};
+
+// Offsets (doubles) inside one block's up pack, down pack, scratch chunk
+// and LDS carves, from the block's per-level counts.  Shared by host and
+// device so the layouts agree exactly.
+struct GrpLayout {
+    int32_t ucp[kMaxGroupLevels], us[kMaxGroupLevels], ul[kMaxGroupLevels], ulen;
+    int32_t dcp[kMaxGroupLevels], dl[kMaxGroupLevels], dlen;
+    int32_t xr[kMaxGroupLevels], xe[kMaxGroupLevels], xlen;
+    int32_t ur[kMaxGroupLevels + 1], utotal;                 // up LDS: upack | r_0..r_m
+    int32_t dx, dr0, dy[kMaxGroupLevels + 1], dtotal;        // down LDS: dpack | scr | r_0 | y_0..y_m
+};
+
+__host__ __device__ inline void grp_layout(int m, const int32_t* cnt, GrpLayout& L) {
+    int32_t u = 0, d = 0, x = 0;
+    for (int j = 0; j < m; ++j) {
+        const int32_t na = cnt[j + 1], nl = cnt[j] - 2 * cnt[j + 1];
+        L.ucp[j] = u; u += (na + 2) / 2;
+        L.us[j] = u;  u += 3 * na;
+        L.ul[j] = u;  u += 2 * nl;
+        L.dcp[j] = d; d += (na + 2) / 2;
+        L.dl[j] = d;  d += 3 * nl;
+        L.xr[j] = x;  if (j >= 1) x += cnt[j];
+        L.xe[j] = x;  x += 2 * na;
+    }
+    L.ulen = u;
+    L.dlen = d;
+    L.xlen = x;
+    int32_t o = u;
+    for (int j = 0; j <= m; ++j) { L.ur[j] = o; o += cnt[j]; }
+    L.utotal = o;
+    o = d;
+    L.dx = o; o += x;
+    L.dr0 = o; o += cnt[0];
+    for (int j = 0; j <= m; ++j) { L.dy[j] = o; o += cnt[j]; }
+    L.dtotal = o;
+}
 
 struct Sell {
     const int32_t* off;

@@ -1,22 +1,32 @@
 // MI355X (gfx950) solve path of the MSP-preconditioned Laplacian solver and
 // its C ABI (include/lap.h).
 //
+// Vector orders.  The SpMV gathers neighbour values, so the vectors it reads
+// and writes (x, p, q and a copy of z) stay in the graph's own vertex order,
+// where neighbours of a mesh or grid row are contiguous across a wavefront.
+// The preconditioner works in the tree order of the hierarchy (children of
+// every aggregate contiguous), so r, z and all coarse-level vectors use it.
+// Level 0 converts between the two: the restriction reads q through the
+// permutation and the prolongation writes z back through it.
+//
 // One PCG iteration is this kernel sequence (all on one stream):
-//   spmv_p      p = z - zbar + beta p_old;  q = L p;  p^T q  -> alpha
-//   update_up0  x += alpha p;  r -= alpha q;  ||r||^2 -> convergence flag;
-//               restriction of r onto level 1 fused with the local solves of
-//               the level-0 aggregates
-//   up(k)       restriction + local solves, levels 1 .. kt-1
-//   tail        one workgroup: levels kt .. top-1 up, top pseudo-inverse,
-//               levels top-1 .. kt down
-//   down(k)     prolongation + local corrections, levels kt-1 .. 1
-//   down0       z on the fine level; sum z, r^T z, sum r -> zbar, rho, beta
-// Reductions finish in the last block to arrive (fixed summation order, so
-// results are bitwise reproducible).  Every kernel returns at once when the
-// device flag `done` is set, so chunks of iterations captured in a hipGraph
-// can be replayed without host round trips per iteration.
+//   spmv_p      p = z - zbar + beta p_old;  q = L p;  partial p^T q
+//   finish      alpha = rho / p^T q
+//   update_up0  x += alpha p;  r -= alpha q;  partial ||r||^2; restriction of
+//               r to level 1 fused with the local solves of level-0 aggregates
+//   finish      convergence flag
+//   up / group  restriction + local solves of the middle levels
+//   tail        one workgroup in LDS: the small levels and the top solve
+//   down/group  prolongation + local corrections of the middle levels
+//   down0       z on level 0 (both orders); partial sum z, r^T z, sum r
+//   finish      zbar, rho, beta
+// Every reduction ends in a one-block finish kernel that adds the per-block
+// partials in a fixed order (bitwise reproducible).  Every kernel returns at
+// once when the device flag `done` is set, so chunks of iterations captured
+// in a hipGraph are replayed without a host round trip per iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -62,8 +72,8 @@ __device__ inline void block_sum(double (&v)[N], double* lds) {
 
 // Each block stores its partial sums (value i of block b at part[i*G + b]);
 // a one-block finish kernel adds them in block order after the producing
-// kernel has completed.  No device-scope fence is needed inside the
-// producer: the kernel boundary orders the partials before the finish.
+// kernel has completed.  No device-scope fence is needed in the producer:
+// the kernel boundary orders the partials before the finish.
 template <int N>
 __device__ inline void block_partial(double (&v)[N], double* part) {
     __shared__ double lds[N * (kBlock / 64)];
@@ -78,21 +88,37 @@ __device__ inline void block_partial(double (&v)[N], double* part) {
 enum FinOp { kFinPq, kFinRr, kFinRho, kFinBsum, kFinBn2, kFinXsum, kFinRes2 };
 
 // Sums the partials of a producer grid of G blocks in a fixed order and
-// applies the scalar step of the solver that needs the total.
+// applies the scalar step of the solver that needs the total.  kFinRho also
+// receives the ||r||^2 partials of the update kernel (G2 blocks at part2)
+// when G2 > 0 and takes the convergence decision there: the preconditioner
+// pass between the update and this point is then wasted only on the final
+// iteration, and one launch per iteration is saved.
 template <int OP>
-__global__ __launch_bounds__(kBlock) void k_finish(int G, int n, const double* __restrict__ part,
-                                                   Scal* S) {
-    constexpr int N = (OP == kFinRho) ? 3 : 1;
-    const bool loop = OP == kFinPq || OP == kFinRr || OP == kFinRho;
+__global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
+                                                        const double* __restrict__ part, int G2,
+                                                        const double* __restrict__ part2,
+                                                        Scal* S) {
+    constexpr int N = (OP == kFinRho) ? 4 : 1;
+    constexpr bool loop = OP == kFinPq || OP == kFinRr || OP == kFinRho;
     if (loop && S->done) return;
-    __shared__ double lds[N * (kBlock / 64)];
+    __shared__ double lds[N * (kFinThreads / 64)];
     double v[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = 0.0;
-    for (int b = threadIdx.x; b < G; b += kBlock)
+    const int nv = (OP == kFinRho) ? 3 : 1;
+    for (int i = 0; i < nv; ++i) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        int b = threadIdx.x;
+        for (; b + 3 * kFinThreads < G; b += 4 * kFinThreads) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) v[i] += part[i * G + b];
-    block_sum<N, kBlock>(v, lds);
+            for (int u = 0; u < 4; ++u) a[u] += part[i * G + b + u * kFinThreads];
+        }
+        for (; b < G; b += kFinThreads) a[0] += part[i * G + b];
+        v[i] = (a[0] + a[1]) + (a[2] + a[3]);
+    }
+    if (OP == kFinRho)
+        for (int b = threadIdx.x; b < G2; b += kFinThreads) v[N - 1] += part2[b];
+    block_sum<N, kFinThreads>(v, lds);
     if (threadIdx.x != 0) return;
     if (OP == kFinPq) {
         const double pq = v[0];
@@ -107,12 +133,18 @@ __global__ __launch_bounds__(kBlock) void k_finish(int G, int n, const double* _
         else if (S->iter >= S->maxit) S->done = 2;
     } else if (OP == kFinRho) {
         const double zbar = v[0] / (double)n;
-        const double rho = v[1] - zbar * v[N - 1];
+        const double rho = v[1] - zbar * v[2];
         S->zbar = zbar;
         if (!isfinite(rho)) S->done = 3;
         S->beta = S->first ? 0.0 : rho / S->rho;
         S->first = 0;
         S->rho = rho;
+        if (G2 > 0) {
+            S->rr = v[3];
+            if (!isfinite(v[3])) S->done = 3;
+            else if (v[3] <= S->tol2 * S->bn2) S->done = 1;
+            else if (S->iter >= S->maxit) S->done = 2;
+        }
     } else if (OP == kFinBsum) {
         S->bsum = v[0];
     } else if (OP == kFinBn2) {
@@ -169,11 +201,11 @@ __device__ inline void agg_down(const LevelDev& s, const double* __restrict__ rk
     }
 }
 
-// ----------------------------------------------------------------- kernels
+// ------------------------------------------------------ fine-level kernels
 
-// p = z - zbar + beta p_old; q = L p with (L p)_i = sum_j w_ij (p_i - p_j);
-// partial p^T q.  Last block: alpha = rho / p^T q, iteration count.
-__global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* __restrict__ z,
+// Input order: p = zn - zbar + beta p_old; q = L p with
+// (L p)_i = sum_j w_ij (p_i - p_j); partial p^T q.
+__global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* __restrict__ zn,
                                                    const double* __restrict__ pold,
                                                    double* __restrict__ pnew,
                                                    double* __restrict__ q, Scal* S,
@@ -183,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* 
     const int row = blockIdx.x * kBlock + threadIdx.x;
     double pi = 0.0, acc = 0.0;
     if (row < n) {
-        const double zi = z[row], poi = pold[row];
+        const double zi = zn[row], poi = pold[row];
         pi = (zi - zbar) + beta * poi;
         const int sl = row >> 6;
         const int base = A.off[sl] + (row & 63);
@@ -191,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* 
         for (int k = 0; k < W; ++k) {
             const int j = A.col[base + k * 64];
             const double w = A.w[base + k * 64];
-            acc += w * ((zi - z[j]) + beta * (poi - pold[j]));
+            acc += w * ((zi - zn[j]) + beta * (poi - pold[j]));
         }
         pnew[row] = pi;
         q[row] = acc;
@@ -200,8 +232,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* 
     block_partial<1>(v, part);
 }
 
-// x += alpha p; r -= alpha q; ||r||^2; fused restriction of r to level 1.
-__global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev s0, double* __restrict__ x,
+// x += alpha p (input order); r -= alpha q (tree order, q read through the
+// permutation); partial ||r||^2; restriction of r to level 1 fused with the
+// local solves of the level-0 aggregates.  The children ranges of all
+// aggregates partition [0, n), so the same ranges index x and p.
+__global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev s0, const int32_t* __restrict__ perm,
+                                                       double* __restrict__ x,
                                                        double* __restrict__ r,
                                                        const double* __restrict__ p,
                                                        const double* __restrict__ q,
@@ -215,9 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev s0, double* __re
         const int b0 = s0.cptr[J], b1 = s0.cptr[J + 1];
         if (do_update) {
             for (int t = b0; t < b1; ++t) {
-                const double xt = x[t] + alpha * p[t];
-                const double rt = r[t] - alpha * q[t];
-                x[t] = xt;
+                x[t] += alpha * p[t];
+                const double rt = r[t] - alpha * q[perm[t]];
                 r[t] = rt;
                 rr += rt * rt;
             }
@@ -229,8 +264,40 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev s0, double* __re
     block_partial<1>(v, part);
 }
 
-// Plain CG variant of update_up0 (no preconditioner).
-__global__ __launch_bounds__(kBlock) void k_update_none(int n, double* __restrict__ x,
+// z on the fine level, written through the permutation in input order for
+// the next SpMV; partial sums of z, r z and r (tree order, in registers).
+__global__ __launch_bounds__(kBlock) void k_down0(LevelDev s0, const int32_t* __restrict__ perm,
+                                                  const double* __restrict__ r,
+                                                  double* __restrict__ zn,
+                                                  const double* __restrict__ y1, Scal* S,
+                                                  double* part) {
+    if (S->done) return;
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (J < s0.nc) {
+        const int b0 = s0.cptr[J], b1 = s0.cptr[J + 1];
+        const double yJ = y1[J], ea = s0.ea[J], eb = s0.eb[J];
+        for (int t = b0; t < b1; ++t) {
+            const double rt = r[t];
+            double zt;
+            if (t == b0) zt = ea + yJ;
+            else if (t == b0 + 1) zt = eb + yJ;
+            else {
+                const int li = t - 2 * J - 2;
+                zt = s0.l0[li] * rt + s0.l1[li] * ea + s0.l2[li] * eb + yJ;
+            }
+            zn[perm[t]] = zt;
+            v[0] += zt;
+            v[1] += rt * zt;
+            v[2] += rt;
+        }
+    }
+    block_partial<3>(v, part);
+}
+
+// Without a hierarchy below the fine level: x and r update only.
+__global__ __launch_bounds__(kBlock) void k_update_none(int n, const int32_t* __restrict__ perm,
+                                                        double* __restrict__ x,
                                                         double* __restrict__ r,
                                                         const double* __restrict__ p,
                                                         const double* __restrict__ q, Scal* S,
@@ -241,13 +308,67 @@ __global__ __launch_bounds__(kBlock) void k_update_none(int n, double* __restric
     double rr = 0.0;
     if (t < n) {
         x[t] += alpha * p[t];
-        const double rt = r[t] - alpha * q[t];
+        const double rt = r[t] - alpha * q[perm[t]];
         r[t] = rt;
         rr = rt * rt;
     }
     double v[1] = {rr};
     block_partial<1>(v, part);
 }
+
+// Plain CG: z = r (both orders) with the down0 reductions.
+__global__ __launch_bounds__(kBlock) void k_prec_none(int n, const int32_t* __restrict__ perm,
+                                                      const double* __restrict__ r,
+                                                      double* __restrict__ z,
+                                                      double* __restrict__ zn, Scal* S,
+                                                      double* part) {
+    if (S->done) return;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (t < n) {
+        const double rt = r[t];
+        z[t] = rt;
+        zn[perm[t]] = rt;
+        v[0] = rt;
+        v[1] = rt * rt;
+        v[2] = rt;
+    }
+    block_partial<3>(v, part);
+}
+
+// One-level hierarchy (the fine level is the top, at most kTopMax nodes):
+// the MSP is theta_0 pinv(L) = pinv(L), applied by one workgroup, which also
+// does the finish step of the down0 reductions itself.
+__global__ __launch_bounds__(kBlock) void k_top_only(int n, const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ tp,
+                                                     const double* __restrict__ r,
+                                                     double* __restrict__ z,
+                                                     double* __restrict__ zn, Scal* S) {
+    if (S->done) return;
+    __shared__ double lds[3 * (kBlock / 64)];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += tp[i * n + j] * r[j];
+        z[i] = acc;
+        zn[perm[i]] = acc;
+        v[0] += acc;
+        v[1] += r[i] * acc;
+        v[2] += r[i];
+    }
+    block_sum<3, kBlock>(v, lds);
+    if (threadIdx.x == 0) {
+        const double zbar = v[0] / (double)n;
+        const double rho = v[1] - zbar * v[2];
+        S->zbar = zbar;
+        if (!isfinite(rho)) S->done = 3;
+        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->first = 0;
+        S->rho = rho;
+    }
+}
+
+// ------------------------------------------------------ per-level kernels
 
 __global__ __launch_bounds__(kBlock) void k_up(LevelDev s, const double* __restrict__ rk,
                                                double* __restrict__ rk1, const Scal* S) {
@@ -263,6 +384,135 @@ __global__ __launch_bounds__(kBlock) void k_down(LevelDev s, const double* __res
     const int J = blockIdx.x * kBlock + threadIdx.x;
     if (J < s.nc) agg_down(s, rk, yk, yk1, J);
 }
+
+// ------------------------------------------------------- grouped levels
+
+// Flat copy global -> LDS with eight loads in flight per thread.
+__device__ inline void stage_copy(double* __restrict__ dst, const double* __restrict__ src,
+                                  int len) {
+    constexpr int U = 8, B = kGrpThreads;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * B < len; i += U * B) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = src[i + u * B];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dst[i + u * B] = t[u];
+    }
+    for (; i < len; i += B) dst[i] = src[i];
+}
+
+// Per-block bookkeeping of a group (level ranges and LDS layout) lives in
+// LDS: it is indexed by the level inside loops, and a runtime-indexed
+// private array would be placed in scratch memory.
+struct GrpBlock {
+    int32_t st[kMaxGroupLevels + 1];
+    int32_t cnt[kMaxGroupLevels + 1];
+    GrpLayout L;
+};
+
+__device__ inline void grp_setup(const GroupDev& G, int m, GrpBlock& B) {
+    if (threadIdx.x == 0) {
+        const int b = blockIdx.x, nb1 = G.nblocks + 1;
+        for (int j = 0; j <= m; ++j) {
+            B.st[j] = G.D[j * nb1 + b];
+            B.cnt[j] = G.D[j * nb1 + b + 1] - B.st[j];
+        }
+        grp_layout(m, B.cnt, B.L);
+    }
+    __syncthreads();
+}
+
+// Up-sweep of a level group [k0, k1): level-k0 residuals in, level-k1
+// residuals out; intermediate residuals and pair corrections go to the
+// block's scratch chunk for the down-sweep.
+__global__ __launch_bounds__(kGrpThreads) void k_up_grp(GroupDev G, const Scal* S) {
+    if (S->done) return;
+    extern __shared__ double sm[];
+    const int m = G.k1 - G.k0, tid = threadIdx.x, nth = blockDim.x;
+    __shared__ GrpBlock B;
+    grp_setup(G, m, B);
+    const int32_t* st = B.st;
+    const int32_t* cnt = B.cnt;
+    const GrpLayout& L = B.L;
+    stage_copy(sm, G.upack + G.uoff[blockIdx.x], L.ulen);
+    stage_copy(sm + L.ur[0], G.r_in + st[0], cnt[0]);
+    __syncthreads();
+    double* scr = G.scr + G.xoff[blockIdx.x];
+    for (int j = 0; j < m; ++j) {
+        const int na = cnt[j + 1], nl = cnt[j] - 2 * na;
+        const int* cp = reinterpret_cast<const int*>(sm + L.ucp[j]);
+        const double* sa = sm + L.us[j];
+        const double* l1 = sm + L.ul[j];
+        const double* l2 = l1 + nl;
+        const double* rk = sm + L.ur[j];
+        double* rk1 = sm + L.ur[j + 1];
+        double* eo = scr + L.xe[j];
+        double* ro = (j + 1 < m) ? scr + L.xr[j + 1] : G.r_top + st[m];
+        for (int J = tid; J < na; J += nth) {
+            const int b0 = cp[J], b1 = cp[J + 1];
+            const double ra = rk[b0], rb = rk[b0 + 1];
+            double sum = ra + rb, ga = ra, gb = rb;
+            for (int c = b0 + 2; c < b1; ++c) {
+                const int li = c - 2 * J - 2;
+                const double rv = rk[c];
+                sum += rv;
+                ga += l1[li] * rv;
+                gb += l2[li] * rv;
+            }
+            const double saa = sa[J], sab = sa[na + J], sbb = sa[2 * na + J];
+            eo[J] = saa * ga + sab * gb;
+            eo[na + J] = sab * ga + sbb * gb;
+            rk1[J] = sum;
+            ro[J] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// Down-sweep of a level group: level-k1 corrections in, level-k0 out.
+__global__ __launch_bounds__(kGrpThreads) void k_down_grp(GroupDev G, const Scal* S) {
+    if (S->done) return;
+    extern __shared__ double sm[];
+    const int m = G.k1 - G.k0, tid = threadIdx.x, nth = blockDim.x;
+    __shared__ GrpBlock B;
+    grp_setup(G, m, B);
+    const int32_t* st = B.st;
+    const int32_t* cnt = B.cnt;
+    const GrpLayout& L = B.L;
+    stage_copy(sm, G.dpack + G.doff[blockIdx.x], L.dlen);
+    stage_copy(sm + L.dx, G.scr + G.xoff[blockIdx.x], L.xlen);
+    stage_copy(sm + L.dr0, G.r_in + st[0], cnt[0]);
+    stage_copy(sm + L.dy[m], G.y_top + st[m], cnt[m]);
+    __syncthreads();
+    for (int j = m - 1; j >= 0; --j) {
+        const int na = cnt[j + 1], nl = cnt[j] - 2 * na;
+        const int* cp = reinterpret_cast<const int*>(sm + L.dcp[j]);
+        const double* l0 = sm + L.dl[j];
+        const double* l1 = l0 + nl;
+        const double* l2 = l1 + nl;
+        const double* rk = j == 0 ? sm + L.dr0 : sm + L.dx + L.xr[j];
+        const double* e = sm + L.dx + L.xe[j];
+        double* yk = sm + L.dy[j];
+        const double* yk1 = sm + L.dy[j + 1];
+        for (int J = tid; J < na; J += nth) {
+            const int b0 = cp[J], b1 = cp[J + 1];
+            const double yJ = yk1[J], ea = e[J], eb = e[na + J];
+            yk[b0] = ea + yJ;
+            yk[b0 + 1] = eb + yJ;
+            for (int c = b0 + 2; c < b1; ++c) {
+                const int li = c - 2 * J - 2;
+                yk[c] = l0[li] * rk[c] + l1[li] * ea + l2[li] * eb + yJ;
+            }
+        }
+        __syncthreads();
+    }
+    const double* y0 = sm + L.dy[0];
+    double* out = G.y_out + st[0];
+    for (int t = tid; t < cnt[0]; t += nth) out[t] = y0[t];
+}
+
+// ------------------------------------------------------------ coarse tail
 
 // Levels kt .. top in one workgroup, entirely in LDS: the coefficients of
 // those levels are staged from one packed device buffer with a coalesced
@@ -343,163 +593,84 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restric
     }
 }
 
-// z on the fine level; sums of z, r*z and r.  Last block: zbar, rho, beta.
-__global__ __launch_bounds__(kBlock) void k_down0(LevelDev s0, int n, const double* __restrict__ r,
-                                                  double* __restrict__ z,
-                                                  const double* __restrict__ y1, Scal* S,
-                                                  double* part) {
-    if (S->done) return;
-    const int J = blockIdx.x * kBlock + threadIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (J < s0.nc) {
-        const int b0 = s0.cptr[J], b1 = s0.cptr[J + 1];
-        agg_down(s0, r, z, y1, J);
-        for (int t = b0; t < b1; ++t) {
-            const double zt = z[t], rt = r[t];
-            v[0] += zt;
-            v[1] += rt * zt;
-            v[2] += rt;
-        }
-    }
-    block_partial<3>(v, part);
-}
+// ------------------------------------------------- solve set-up and finish
 
-// One-level hierarchy (top = fine level, at most kTopMax nodes): the MSP is
-// theta_0 pinv(L) = pinv(L); one workgroup applies it and does the k_down0
-// reductions itself.
-__global__ __launch_bounds__(kBlock) void k_top_only(int n, const double* __restrict__ tp,
-                                                     const double* __restrict__ r,
-                                                     double* __restrict__ z, Scal* S) {
-    if (S->done) return;
-    __shared__ double lds[3 * (kBlock / 64)];
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < n; i += kBlock) {
-        double acc = 0.0;
-        for (int j = 0; j < n; ++j) acc += tp[i * n + j] * r[j];
-        z[i] = acc;
-        v[0] += acc;
-        v[1] += r[i] * acc;
-        v[2] += r[i];
-    }
-    block_sum<3, kBlock>(v, lds);
-    if (threadIdx.x == 0) {
-        const double zbar = v[0] / (double)n;
-        const double rho = v[1] - zbar * v[2];
-        S->zbar = zbar;
-        if (!isfinite(rho)) S->done = 3;
-        S->beta = S->first ? 0.0 : rho / S->rho;
-        S->first = 0;
-        S->rho = rho;
-    }
-}
-
-// Plain CG: z = r, same reductions as k_down0.
-__global__ __launch_bounds__(kBlock) void k_prec_none(int n, const double* __restrict__ r,
-                                                      double* __restrict__ z, Scal* S,
-                                                      double* part) {
-    if (S->done) return;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (t < n) {
-        const double rt = r[t];
-        z[t] = rt;
-        v[0] = rt;
-        v[1] = rt * rt;
-        v[2] = rt;
-    }
-    block_partial<3>(v, part);
-}
-
-// dst[t] = src[perm[t]] (gather into tree order) and sum -> S->bsum.
-__global__ __launch_bounds__(kBlock) void k_gather_sum(int n, const int32_t* __restrict__ perm,
-                                                       const double* __restrict__ src,
-                                                       double* __restrict__ dst, Scal* S,
-                                                       double* part) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    double v[1] = {0.0};
-    if (t < n) {
-        const double b = src[perm[t]];
-        dst[t] = b;
-        v[0] = b;
-    }
-    block_partial<1>(v, part);
-}
-
-// b^ = b - mean; r = b^; x = p0 = p1 = 0; ||b^||^2 -> bn2, run flags.
-__global__ __launch_bounds__(kBlock) void k_init(int n, double* __restrict__ b, double* __restrict__ r,
-                                                 double* __restrict__ x, double* __restrict__ p0,
-                                                 double* __restrict__ p1, Scal* S, double* part) {
-    const double mean = S->bsum / (double)n;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    double v[1] = {0.0};
-    if (t < n) {
-        const double bh = b[t] - mean;
-        b[t] = bh;
-        r[t] = bh;
-        x[t] = 0.0;
-        p0[t] = 0.0;
-        p1[t] = 0.0;
-        v[0] = bh * bh;
-    }
-    block_partial<1>(v, part);
-}
-
-__global__ __launch_bounds__(kBlock) void k_sum(int n, const double* __restrict__ a, Scal* S,
+__global__ __launch_bounds__(kBlock) void k_sum(int n, const double* __restrict__ a,
                                                 double* part) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     double v[1] = {t < n ? a[t] : 0.0};
     block_partial<1>(v, part);
 }
 
-// xc = x - mean(x) in tree order and dst[perm[t]] = xc[t].
-__global__ __launch_bounds__(kBlock) void k_center_scatter(int n, const int32_t* __restrict__ perm,
-                                                           const double* __restrict__ x,
-                                                           double* __restrict__ xc,
-                                                           double* __restrict__ dst,
-                                                           const Scal* S) {
+// b^ = b - mean(b) (input order); r = b^ in tree order; x = p0 = p1 = 0;
+// partial ||b^||^2.
+__global__ __launch_bounds__(kBlock) void k_init(int n, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ bh, double* __restrict__ r,
+                                                 double* __restrict__ x, double* __restrict__ p0,
+                                                 double* __restrict__ p1, const Scal* S,
+                                                 double* part) {
+    const double mean = S->bsum / (double)n;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (t < n) {
+        const double bt = b[t] - mean;
+        bh[t] = bt;
+        r[t] = b[perm[t]] - mean;
+        x[t] = 0.0;
+        p0[t] = 0.0;
+        p1[t] = 0.0;
+        v[0] = bt * bt;
+    }
+    block_partial<1>(v, part);
+}
+
+// xc = x - mean(x) and the caller's copy of it (input order).
+__global__ __launch_bounds__(kBlock) void k_center_out(int n, const double* __restrict__ x,
+                                                       double* __restrict__ xc,
+                                                       double* __restrict__ dst, const Scal* S) {
     const double mean = S->xsum / (double)n;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t < n) {
         const double v = x[t] - mean;
         xc[t] = v;
-        dst[perm[t]] = v;
+        dst[t] = v;
     }
 }
 
-// ||b^ - L x||^2 -> S->res2.
+// partial ||b^ - L x||^2 (input order).
 __global__ __launch_bounds__(kBlock) void k_resid(int n, Sell A, const double* __restrict__ x,
-                                                  const double* __restrict__ bh, Scal* S,
-                                                  double* part) {
+                                                  const double* __restrict__ bh, double* part) {
     const int row = blockIdx.x * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (row < n) {
         const double xi = x[row];
         const int sl = row >> 6;
         const int base = A.off[sl] + (row & 63);
+        const int W = A.width[sl];
         double acc = 0.0;
-        for (int k = 0; k < A.width[sl]; ++k)
-            acc += A.w[base + k * 64] * (xi - x[A.col[base + k * 64]]);
+        for (int k = 0; k < W; ++k) acc += A.w[base + k * 64] * (xi - x[A.col[base + k * 64]]);
         const double d = bh[row] - acc;
         v[0] = d * d;
     }
     block_partial<1>(v, part);
 }
 
-// y[perm[t]] = (L x~)_t with x~[t] = x[perm[t]] (original order in and out).
-__global__ __launch_bounds__(kBlock) void k_spmv_orig(int n, Sell A, const int32_t* __restrict__ perm,
-                                                      const double* __restrict__ xt,
-                                                      double* __restrict__ y) {
+// y = L x (input order).
+__global__ __launch_bounds__(kBlock) void k_spmv_plain(int n, Sell A, const double* __restrict__ x,
+                                                       double* __restrict__ y) {
     const int row = blockIdx.x * kBlock + threadIdx.x;
     if (row >= n) return;
-    const double xi = xt[row];
+    const double xi = x[row];
     const int sl = row >> 6;
     const int base = A.off[sl] + (row & 63);
+    const int W = A.width[sl];
     double acc = 0.0;
-    for (int k = 0; k < A.width[sl]; ++k)
-        acc += A.w[base + k * 64] * (xi - xt[A.col[base + k * 64]]);
-    y[perm[row]] = acc;
+    for (int k = 0; k < W; ++k) acc += A.w[base + k * 64] * (xi - x[A.col[base + k * 64]]);
+    y[row] = acc;
 }
 
+// dst[t] = src[perm[t]] (input order -> tree order).
 __global__ __launch_bounds__(kBlock) void k_gather(int n, const int32_t* __restrict__ perm,
                                                    const double* __restrict__ src,
                                                    double* __restrict__ dst) {
@@ -507,12 +678,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(int n, const int32_t* __restr
     if (t < n) dst[t] = src[perm[t]];
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_center(int n, const int32_t* __restrict__ perm,
-                                                           const double* __restrict__ z,
-                                                           double* __restrict__ dst,
-                                                           const Scal* S) {
+// dst = src - zbar (input order).
+__global__ __launch_bounds__(kBlock) void k_shift_out(int n, const double* __restrict__ src,
+                                                      double* __restrict__ dst, const Scal* S) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t < n) dst[perm[t]] = z[t] - S->zbar;
+    if (t < n) dst[t] = src[t] - S->zbar;
 }
 
 }  // namespace lapgpu
@@ -543,16 +713,13 @@ void record_error(const char* what, hipError_t e, int line) {
         }                                                 \
     } while (0)
 
-int tail_max_default() {
-    const char* s = std::getenv("LAPGPU_TAIL_MAX");
-    if (s) {
-        const int v = std::atoi(s);
-        if (v > 0) return v;
-    }
-    return 1 << 30;   // largest tail that fits in LDS
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : dflt;
 }
 
 constexpr size_t kTailLdsBytes = 152 * 1024;
+constexpr int kGrpLdsDoubles = 8192;    // 64 KB per group block
 
 // Doubles of LDS the tail needs when it starts at level kt.
 size_t tail_lds_doubles(const HostPlan& P, int kt) {
@@ -611,13 +778,97 @@ void build_tail(const HostPlan& P, int kt, TailDesc& D, std::vector<double>& pac
     D.total = w;
 }
 
-int chunk_default() {
-    const char* s = std::getenv("LAPGPU_CHUNK");
-    if (s) {
-        const int v = std::atoi(s);
-        if (v >= 2) return v & ~1;
+// Partition the level-k1 nodes into blocks of whole subtrees for the group
+// [k0, k1): each block's level-k0 range holds at most `cap` nodes and its
+// LDS layouts (up and down) fit kGrpLdsDoubles.  Fails if one subtree alone
+// does not fit.
+bool plan_group(const HostPlan& P, int k0, int k1, int cap, std::vector<int32_t>& D,
+                int& nblocks, size_t& lds_up, size_t& lds_down) {
+    const int m = k1 - k0;
+    const int64_t nroot = P.lv[k1].g.n;
+    std::vector<std::vector<int32_t>> first(m + 1, std::vector<int32_t>(nroot + 1));
+    for (int64_t R = 0; R <= nroot; ++R) first[m][R] = (int32_t)R;
+    for (int j = m - 1; j >= 0; --j) {
+        const std::vector<int32_t>& cptr = P.step[k0 + j].cptr;
+        for (int64_t R = 0; R <= nroot; ++R) first[j][R] = cptr[first[j + 1][R]];
     }
-    return 8;
+    int32_t cnt[kMaxGroupLevels + 1];
+    GrpLayout lay;
+    auto fits = [&](int64_t A, int64_t B) {
+        for (int j = 0; j <= m; ++j) cnt[j] = first[j][B] - first[j][A];
+        grp_layout(m, cnt, lay);
+        return cnt[0] <= cap && lay.utotal <= kGrpLdsDoubles && lay.dtotal <= kGrpLdsDoubles;
+    };
+    std::vector<int64_t> cuts{0};
+    int32_t up = 0, dn = 0;
+    while (cuts.back() < nroot) {
+        const int64_t A = cuts.back();
+        if (!fits(A, A + 1)) return false;
+        int64_t lo = A + 1, hi = nroot;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (fits(A, mid)) lo = mid;
+            else hi = mid - 1;
+        }
+        fits(A, lo);
+        up = std::max(up, lay.utotal);
+        dn = std::max(dn, lay.dtotal);
+        cuts.push_back(lo);
+    }
+    nblocks = (int)cuts.size() - 1;
+    D.assign((size_t)(m + 1) * (nblocks + 1), 0);
+    for (int j = 0; j <= m; ++j)
+        for (int b = 0; b <= nblocks; ++b) D[(size_t)j * (nblocks + 1) + b] = first[j][cuts[b]];
+    lds_up = (size_t)up * sizeof(double);
+    lds_down = (size_t)dn * sizeof(double);
+    return true;
+}
+
+// Pack one group's per-block coefficients in the order of grp_layout.
+void pack_group(const HostPlan& P, int k0, int k1, int nblocks, const std::vector<int32_t>& D,
+                std::vector<int32_t>& uoff, std::vector<int32_t>& doff,
+                std::vector<int32_t>& xoff, std::vector<double>& up, std::vector<double>& dn) {
+    const int m = k1 - k0, nb1 = nblocks + 1;
+    uoff.assign(nb1, 0);
+    doff.assign(nb1, 0);
+    xoff.assign(nb1, 0);
+    up.clear();
+    dn.clear();
+    int32_t cnt[kMaxGroupLevels + 1], st[kMaxGroupLevels + 1];
+    GrpLayout L;
+    for (int b = 0; b < nblocks; ++b) {
+        for (int j = 0; j <= m; ++j) {
+            st[j] = D[(size_t)j * nb1 + b];
+            cnt[j] = D[(size_t)j * nb1 + b + 1] - st[j];
+        }
+        grp_layout(m, cnt, L);
+        const size_t ub = up.size(), db = dn.size();
+        up.resize(ub + L.ulen, 0.0);
+        dn.resize(db + L.dlen, 0.0);
+        for (int j = 0; j < m; ++j) {
+            const StepCoef& c = P.step[k0 + j];
+            const int na = cnt[j + 1], nl = cnt[j] - 2 * na, a0 = st[j + 1], c0 = st[j];
+            const int lb = c0 - 2 * a0;
+            int32_t* ucp = reinterpret_cast<int32_t*>(up.data() + ub + L.ucp[j]);
+            int32_t* dcp = reinterpret_cast<int32_t*>(dn.data() + db + L.dcp[j]);
+            for (int i = 0; i <= na; ++i) ucp[i] = dcp[i] = c.cptr[a0 + i] - c0;
+            for (int i = 0; i < na; ++i) {
+                up[ub + L.us[j] + i] = c.saa[a0 + i];
+                up[ub + L.us[j] + na + i] = c.sab[a0 + i];
+                up[ub + L.us[j] + 2 * na + i] = c.sbb[a0 + i];
+            }
+            for (int i = 0; i < nl; ++i) {
+                up[ub + L.ul[j] + i] = c.l1[lb + i];
+                up[ub + L.ul[j] + nl + i] = c.l2[lb + i];
+                dn[db + L.dl[j] + i] = c.l0[lb + i];
+                dn[db + L.dl[j] + nl + i] = c.l1[lb + i];
+                dn[db + L.dl[j] + 2 * nl + i] = c.l2[lb + i];
+            }
+        }
+        uoff[b + 1] = (int32_t)up.size();
+        doff[b + 1] = (int32_t)dn.size();
+        xoff[b + 1] = xoff[b] + L.xlen;
+    }
 }
 
 }  // namespace
@@ -633,20 +884,29 @@ struct lap_hierarchy {
     int64_t dev_bytes = 0;
     std::vector<void*> allocs;
     // device data
-    int32_t* perm0 = nullptr;
+    int32_t* perm0 = nullptr;    // tree position -> input vertex
     Sell A{};
     std::vector<LevelDev> lv;    // host copy of the level table
-    LevelDev* d_lv = nullptr;
     double* top_pinv = nullptr;
-    int kt = 1;
+    int kt = 1;                  // first level of the one-block tail
     TailDesc* d_tail = nullptr;
     double* tail_pack = nullptr;
     size_t tail_lds = 0;
-    // workspace
-    double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr, *xc = nullptr;
-    double* p[2] = {nullptr, nullptr};
+    struct Segment {
+        bool group = false;
+        int k0 = 0, k1 = 1;
+        GroupDev gd{};
+        size_t lds_up = 0, lds_down = 0;   // bytes of dynamic LDS
+    };
+    std::vector<Segment> segs;   // levels [1, kt), in order
+    // workspace: input order
+    double *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *zn = nullptr;
+    double *bh = nullptr, *xc = nullptr;
+    // workspace: tree order
+    double *r = nullptr, *z = nullptr;
     Scal* S = nullptr;
-    double* part = nullptr;
+    double* part = nullptr;      // per-block partial sums of the last producer
+    double* part2 = nullptr;     // per-block ||r||^2 of the update kernel
     Scal* stage = nullptr;       // pinned host copy of S
     hipStream_t cap = nullptr;   // private capture stream
     hipGraph_t graph = nullptr;
@@ -662,11 +922,14 @@ struct lap_hierarchy {
         dev_bytes += (int64_t)bytes;
         return static_cast<T*>(ptr);
     }
+    // Uploads complete before return (host vectors may be temporaries).
     template <class T>
     T* upload(const std::vector<T>& v, hipStream_t s) {
         T* d = dalloc<T>(v.size());
-        if (!v.empty())
+        if (!v.empty()) {
             HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
         return d;
     }
     ~lap_hierarchy() {
@@ -680,48 +943,69 @@ struct lap_hierarchy {
 
 namespace {
 
-// Enqueue the preconditioner (update_up0 with or without the x/r update,
-// then up, tail, down, down0) or the plain-CG equivalent.
+// One-block finish of the partials at `part` (G blocks); kFinRho may also
+// take the update kernel's ||r||^2 partials (G2 blocks at part2).
+template <int OP>
+void finish(lap_hierarchy* h, hipStream_t s, int G, int G2 = 0, const double* part = nullptr) {
+    hipLaunchKernelGGL(k_finish<OP>, dim3(1), dim3(kFinThreads), 0, s, G, (int)h->n,
+                       part ? part : h->part, G2, h->part2, h->S);
+}
+
+// The preconditioner: level-0 restriction (with the x, r update when
+// do_update), the middle levels, the tail and back, z with its reductions.
 void enqueue_precond(lap_hierarchy* h, hipStream_t s, int do_update, const double* pcur) {
     const int T = h->plan.nlev() - 1;
+    const int n = (int)h->n;
     if (!h->with_msp || T == 0) {
         if (do_update) {
-            hipLaunchKernelGGL(k_update_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n,
-                               h->x, h->r, pcur, h->q, h->S, h->part);
-            hipLaunchKernelGGL(k_finish<kFinRr>, dim3(1), dim3(kBlock), 0, s, nblk(h->n), (int)h->n, h->part, h->S);
+            hipLaunchKernelGGL(k_update_none, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, h->x,
+                               h->r, pcur, h->q, h->S, h->part2);
+            if (h->with_msp) finish<kFinRr>(h, s, nblk(n), 0, h->part2);
         }
         if (!h->with_msp) {
-            hipLaunchKernelGGL(k_prec_none, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n, h->r,
-                               h->z, h->S, h->part);
-            hipLaunchKernelGGL(k_finish<kFinRho>, dim3(1), dim3(kBlock), 0, s, nblk(h->n), (int)h->n, h->part, h->S);
+            hipLaunchKernelGGL(k_prec_none, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, h->r,
+                               h->z, h->zn, h->S, h->part);
+            finish<kFinRho>(h, s, nblk(n), do_update ? nblk(n) : 0);
         } else {
-            hipLaunchKernelGGL(k_top_only, dim3(1), dim3(kBlock), 0, s, (int)h->n, h->top_pinv,
-                               h->r, h->z, h->S);
+            hipLaunchKernelGGL(k_top_only, dim3(1), dim3(kBlock), 0, s, n, h->perm0, h->top_pinv,
+                               h->r, h->z, h->zn, h->S);
         }
         return;
     }
     const LevelDev& s0 = h->lv[0];
-    hipLaunchKernelGGL(k_update_up0, dim3(nblk(s0.nc)), dim3(kBlock), 0, s, s0, h->x, h->r, pcur,
-                       h->q, h->lv[1].r, h->S, h->part, do_update);
-    if (do_update) hipLaunchKernelGGL(k_finish<kFinRr>, dim3(1), dim3(kBlock), 0, s, nblk(s0.nc), (int)h->n, h->part, h->S);
-    for (int k = 1; k < h->kt; ++k)
-        hipLaunchKernelGGL(k_up, dim3(nblk(h->lv[k].nc)), dim3(kBlock), 0, s, h->lv[k], h->lv[k].r,
-                           h->lv[k + 1].r, h->S);
+    const int g0 = nblk(s0.nc);
+    hipLaunchKernelGGL(k_update_up0, dim3(g0), dim3(kBlock), 0, s, s0, h->perm0, h->x, h->r, pcur,
+                       h->q, h->lv[1].r, h->S, h->part2, do_update);
+    for (const auto& G : h->segs) {
+        if (G.group)
+            hipLaunchKernelGGL(k_up_grp, dim3(G.gd.nblocks), dim3(kGrpThreads), G.lds_up, s, G.gd,
+                               h->S);
+        else
+            hipLaunchKernelGGL(k_up, dim3(nblk(h->lv[G.k0].nc)), dim3(kBlock), 0, s, h->lv[G.k0],
+                               h->lv[G.k0].r, h->lv[G.k0 + 1].r, h->S);
+    }
     hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), h->tail_lds, s, h->d_tail,
                        h->tail_pack, h->lv[h->kt].r, h->lv[h->kt].y, h->S);
-    for (int k = h->kt - 1; k >= 1; --k)
-        hipLaunchKernelGGL(k_down, dim3(nblk(h->lv[k].nc)), dim3(kBlock), 0, s, h->lv[k],
-                           h->lv[k].r, h->lv[k].y, h->lv[k + 1].y, h->S);
-    hipLaunchKernelGGL(k_down0, dim3(nblk(s0.nc)), dim3(kBlock), 0, s, s0, (int)h->n, h->r, h->z,
+    for (auto it = h->segs.rbegin(); it != h->segs.rend(); ++it) {
+        const auto& G = *it;
+        if (G.group)
+            hipLaunchKernelGGL(k_down_grp, dim3(G.gd.nblocks), dim3(kGrpThreads), G.lds_down, s,
+                               G.gd, h->S);
+        else
+            hipLaunchKernelGGL(k_down, dim3(nblk(h->lv[G.k0].nc)), dim3(kBlock), 0, s,
+                               h->lv[G.k0], h->lv[G.k0].r, h->lv[G.k0].y, h->lv[G.k0 + 1].y, h->S);
+    }
+    hipLaunchKernelGGL(k_down0, dim3(g0), dim3(kBlock), 0, s, s0, h->perm0, h->r, h->zn,
                        h->lv[1].y, h->S, h->part);
-    hipLaunchKernelGGL(k_finish<kFinRho>, dim3(1), dim3(kBlock), 0, s, nblk(s0.nc), (int)h->n, h->part, h->S);
+    finish<kFinRho>(h, s, g0, do_update ? g0 : 0);
 }
 
 // One PCG iteration reading p[par] and writing p[1-par].
 void enqueue_iteration(lap_hierarchy* h, hipStream_t s, int par) {
-    hipLaunchKernelGGL(k_spmv_p, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n, h->A, h->z,
-                       h->p[par], h->p[1 - par], h->q, h->S, h->part);
-    hipLaunchKernelGGL(k_finish<kFinPq>, dim3(1), dim3(kBlock), 0, s, nblk(h->n), (int)h->n, h->part, h->S);
+    const int n = (int)h->n;
+    hipLaunchKernelGGL(k_spmv_p, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, h->zn, h->p[par],
+                       h->p[1 - par], h->q, h->S, h->part);
+    finish<kFinPq>(h, s, nblk(n));
     enqueue_precond(h, s, 1, h->p[1 - par]);
 }
 
@@ -738,14 +1022,17 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     const HostPlan& P = h->plan;
     const int L = P.nlev();
     const int T = L - 1;
+    const int64_t n = h->n;
     h->perm0 = h->upload(P.perm[0], s);
     h->A.off = h->upload(P.sell_off, s);
     h->A.width = h->upload(P.sell_width, s);
     h->A.col = h->upload(P.sell_col, s);
     h->A.w = h->upload(P.sell_w, s);
     h->with_msp = (h->params.precond == LAP_PREC_MSP);
-    h->lv.assign(L, LevelDev{});
-    const int tail_max = tail_max_default();
+    h->r = h->dalloc<double>(n);
+    h->z = h->dalloc<double>(n);
+    // the tail: the lowest level from which all coarser levels fit in LDS
+    const int tail_max = env_int("LAPGPU_TAIL_MAX", 1 << 30);
     h->kt = T;
     for (int k = 1; k <= T; ++k)
         if (P.lv[k].g.n <= tail_max && T - k <= kMaxTailSteps &&
@@ -753,6 +1040,7 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
             h->kt = k;
             break;
         }
+    h->lv.assign(L, LevelDev{});
     for (int k = 0; k < L; ++k) {
         LevelDev& d = h->lv[k];
         d.n = (int32_t)P.lv[k].g.n;
@@ -760,6 +1048,9 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
         if (k >= 1) {
             d.r = h->dalloc<double>(d.n);
             d.y = h->dalloc<double>(d.n);
+        } else {
+            d.r = h->r;
+            d.y = h->z;
         }
         if (k < T) {
             const StepCoef& c = P.step[k];
@@ -774,8 +1065,50 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
             d.eb = h->dalloc<double>(d.nc);
         }
     }
-    h->d_lv = h->upload(h->lv, s);
     h->top_pinv = h->upload(P.top_pinv, s);
+    // middle levels [1, kt): groups of consecutive levels where whole
+    // subtrees fit a block, single per-level kernels elsewhere
+    h->segs.clear();
+    const int cap = env_int("LAPGPU_GRP_CAP", 1024);
+    const int maxlev = std::min(kMaxGroupLevels, env_int("LAPGPU_GRP_MAXLEV", kMaxGroupLevels));
+    const int first_grouped = std::max(1, env_int("LAPGPU_GRP_FIRST", 2));
+    for (int k0 = 1; T >= 1 && k0 < h->kt;) {
+        lap_hierarchy::Segment sg;
+        bool placed = false;
+        for (int m = std::min(maxlev, h->kt - k0); m >= 1 && !placed && k0 >= first_grouped; --m) {
+            std::vector<int32_t> D;
+            int nb = 0;
+            if (!plan_group(P, k0, k0 + m, cap, D, nb, sg.lds_up, sg.lds_down)) continue;
+            sg.group = true;
+            sg.k0 = k0;
+            sg.k1 = k0 + m;
+            sg.gd.k0 = k0;
+            sg.gd.k1 = k0 + m;
+            sg.gd.nblocks = nb;
+            sg.gd.D = h->upload(D, s);
+            std::vector<int32_t> uoff, doff, xoff;
+            std::vector<double> up, dn;
+            pack_group(P, k0, k0 + m, nb, D, uoff, doff, xoff, up, dn);
+            sg.gd.uoff = h->upload(uoff, s);
+            sg.gd.doff = h->upload(doff, s);
+            sg.gd.xoff = h->upload(xoff, s);
+            sg.gd.upack = h->upload(up, s);
+            sg.gd.dpack = h->upload(dn, s);
+            sg.gd.scr = h->dalloc<double>(xoff.back());
+            sg.gd.r_top = h->lv[k0 + m].r;
+            sg.gd.y_top = h->lv[k0 + m].y;
+            sg.gd.r_in = h->lv[k0].r;
+            sg.gd.y_out = h->lv[k0].y;
+            placed = true;
+        }
+        if (!placed) {
+            sg.group = false;
+            sg.k0 = k0;
+            sg.k1 = k0 + 1;
+        }
+        k0 = sg.k1;
+        h->segs.push_back(sg);
+    }
     if (T >= 1) {
         TailDesc desc{};
         std::vector<double> pack;
@@ -788,24 +1121,29 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
         HIPCHK(hipFuncSetAttribute((const void*)k_tail,
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)kTailLdsBytes));
+        HIPCHK(hipFuncSetAttribute((const void*)k_up_grp,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   kGrpLdsDoubles * 8));
+        HIPCHK(hipFuncSetAttribute((const void*)k_down_grp,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   kGrpLdsDoubles * 8));
     }
-    const int64_t n = h->n;
-    h->b = h->dalloc<double>(n);
     h->x = h->dalloc<double>(n);
-    h->r = h->dalloc<double>(n);
-    h->z = h->dalloc<double>(n);
     h->q = h->dalloc<double>(n);
+    h->zn = h->dalloc<double>(n);
+    h->bh = h->dalloc<double>(n);
     h->xc = h->dalloc<double>(n);
     h->p[0] = h->dalloc<double>(n);
     h->p[1] = h->dalloc<double>(n);
     h->S = h->dalloc<Scal>(1);
     h->part = h->dalloc<double>((size_t)kMaxGridPart * nblk(n) + 64);
+    h->part2 = h->dalloc<double>((size_t)nblk(n) + 64);
     HIPCHK(hipHostMalloc((void**)&h->stage, sizeof(Scal), hipHostMallocDefault));
     std::memset(h->stage, 0, sizeof(Scal));
     HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    h->chunk = chunk_default();
+    h->chunk = std::max(2, env_int("LAPGPU_CHUNK", 8) & ~1);
     build_graph(h);
 }
 
@@ -823,40 +1161,43 @@ lap_status solve_one(lap_hierarchy* h, const double* b, double* x, double tol,
                      lap_solve_info* info, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     const int n = (int)h->n;
-    // reset scalars (counters included) and set the run parameters
+    // reset the scalars and set the run parameters
     std::memset(h->stage, 0, sizeof(Scal));
     h->stage->tol2 = tol * tol;
     h->stage->maxit = h->params.max_iter;
     HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_gather_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, b, h->b, h->S,
-                       h->part);
-    hipLaunchKernelGGL(k_finish<kFinBsum>, dim3(1), dim3(kBlock), 0, s, nblk(n), (int)h->n, h->part, h->S);
-    hipLaunchKernelGGL(k_init, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->b, h->r, h->x, h->p[0],
-                       h->p[1], h->S, h->part);
-    hipLaunchKernelGGL(k_finish<kFinBn2>, dim3(1), dim3(kBlock), 0, s, nblk(n), (int)h->n, h->part, h->S);
+    hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, b, h->part);
+    finish<kFinBsum>(h, s, nblk(n));
+    hipLaunchKernelGGL(k_init, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, b, h->bh, h->r,
+                       h->x, h->p[0], h->p[1], h->S, h->part);
+    finish<kFinBn2>(h, s, nblk(n));
     enqueue_precond(h, s, 0, h->p[0]);
     HIPCHK(hipGetLastError());
     // chunks of iterations; one chunk in flight beyond the one being checked
     hipEvent_t ev;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     const int max_chunks = h->params.max_iter / h->chunk + 2;
-    HIPCHK(hipGraphLaunch(h->exec, s));
-    for (int c = 0; c < max_chunks; ++c) {
-        HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(ev, s));
+    try {
         HIPCHK(hipGraphLaunch(h->exec, s));
-        HIPCHK(hipEventSynchronize(ev));
-        if (h->stage->done) break;
+        for (int c = 0; c < max_chunks; ++c) {
+            HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(ev, s));
+            HIPCHK(hipGraphLaunch(h->exec, s));
+            HIPCHK(hipEventSynchronize(ev));
+            if (h->stage->done) break;
+        }
+    } catch (const HipErr&) {
+        (void)hipEventDestroy(ev);
+        throw;
     }
     (void)hipEventDestroy(ev);
-    // mean-free x in original order, true residual
-    hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->x, h->S, h->part);
-    hipLaunchKernelGGL(k_finish<kFinXsum>, dim3(1), dim3(kBlock), 0, s, nblk(n), (int)h->n, h->part, h->S);
-    hipLaunchKernelGGL(k_center_scatter, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, h->x,
-                       h->xc, x, h->S);
-    hipLaunchKernelGGL(k_resid, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, h->xc, h->b, h->S,
+    // mean-free x (input order), true residual
+    hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->x, h->part);
+    finish<kFinXsum>(h, s, nblk(n));
+    hipLaunchKernelGGL(k_center_out, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->x, h->xc, x, h->S);
+    hipLaunchKernelGGL(k_resid, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, h->xc, h->bh,
                        h->part);
-    hipLaunchKernelGGL(k_finish<kFinRes2>, dim3(1), dim3(kBlock), 0, s, nblk(n), (int)h->n, h->part, h->S);
+    finish<kFinRes2>(h, s, nblk(n));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -921,9 +1262,8 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
     if (!out) return LAP_EINVAL;
     *out = nullptr;
     if (!g || !p || !g->u || !g->v || !g->w) return LAP_EINVAL;
-    if (p->precond != LAP_PREC_MSP && p->precond != LAP_PREC_NONE) {
+    if (p->precond != LAP_PREC_MSP && p->precond != LAP_PREC_NONE)
         return p->precond == LAP_PREC_PEGP ? LAP_EUNSUPPORTED : LAP_EINVAL;
-    }
     if (p->precision != LAP_FP64) return LAP_EINVAL;
     if (p->max_iter < 0) return LAP_EINVAL;
     const auto t0 = std::chrono::steady_clock::now();
@@ -942,6 +1282,7 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
         if (!h->host_only) {
             int ndev = 0;
             if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+                std::snprintf(g_last_error, sizeof(g_last_error), "no HIP device visible");
                 delete h;
                 return LAP_EDEVICE;
             }
@@ -984,10 +1325,13 @@ lap_status lap_apply_laplacian(lap_hierarchy* h, const double* x, double* y, voi
     if (h->host_only) return LAP_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)h->n;
-    hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, x, h->xc);
-    hipLaunchKernelGGL(k_spmv_orig, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, h->perm0, h->xc,
-                       y);
-    return hipGetLastError() == hipSuccess ? LAP_OK : LAP_EDEVICE;
+    hipLaunchKernelGGL(k_spmv_plain, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, x, y);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        record_error("k_spmv_plain launch", e, __LINE__);
+        return LAP_EDEVICE;
+    }
+    return LAP_OK;
 }
 
 lap_status lap_apply_precond(lap_hierarchy* h, const double* r, double* z, void* stream) {
@@ -1001,8 +1345,7 @@ lap_status lap_apply_precond(lap_hierarchy* h, const double* r, double* z, void*
         HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_gather, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, r, h->r);
         enqueue_precond(h, s, 0, h->p[0]);
-        hipLaunchKernelGGL(k_scatter_center, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->perm0, h->z,
-                           z, h->S);
+        hipLaunchKernelGGL(k_shift_out, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->zn, z, h->S);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
     } catch (const HipErr&) {
@@ -1020,29 +1363,41 @@ lap_status lap_profile_kernel(lap_hierarchy* h, int32_t kernel, int32_t reps, vo
     if ((kernel == LAP_KERNEL_UPDATE || kernel == LAP_KERNEL_DOWN0) && !levels)
         return LAP_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
-    // algorithmic bytes (FP64 values, int32 indices)
+    // Algorithmic bytes: FP64 values, int32 indices, each datum a step needs
+    // counted once (a permuted access counts as one value).
     const double n = (double)h->n, nnz = (double)h->plan.lv[0].g.nnz();
-    auto step_bytes = [&](int k, bool up) {
-        const double nk = (double)h->plan.lv[k].g.n;
-        const double nc = k < T ? (double)h->plan.lv[k + 1].g.n : 0.0;
-        const double nl = nk - 2.0 * nc;
-        if (up)   // r_k; cptr, 3 pair coefficients; 2 leftover coefficients; eta_a, eta_b, r_k+1
-            return 8.0 * nk + 4.0 * nc + 24.0 * nc + 16.0 * nl + 24.0 * nc;
-        // r_k of leftovers; cptr, eta_a, eta_b, y_k+1; 3 leftover coefficients; y_k
-        return 8.0 * nl + 28.0 * nc + 24.0 * nl + 8.0 * nk;
+    auto lvn = [&](int k) { return (double)h->plan.lv[k].g.n; };
+    // step k (level k -> k+1), up: r_k; cptr, pair coefficients, leftover
+    // coefficients (2); eta a/b and the restricted value written.
+    auto step_up = [&](int k) {
+        const double nc = lvn(k + 1), nl = lvn(k) - 2.0 * lvn(k + 1);
+        return 8.0 * lvn(k) + 4.0 * nc + 24.0 * nc + 16.0 * nl + 24.0 * nc;
+    };
+    // down: cptr, eta a/b, y_k+1; leftover coefficients (3) and residuals;
+    // y_k written.
+    auto step_down = [&](int k) {
+        const double nc = lvn(k + 1), nl = lvn(k) - 2.0 * lvn(k + 1);
+        return 4.0 * nc + 16.0 * nc + 8.0 * nc + 24.0 * nl + 8.0 * nl + 8.0 * lvn(k);
     };
     const double spmv = 32.0 * n + 12.0 * nnz;
-    const double upd = levels ? 40.0 * n + step_bytes(0, true) : 48.0 * n;
-    const double down0 = levels ? step_bytes(0, false) + 8.0 * n : 16.0 * n;
-    double prec = down0 + (levels ? step_bytes(0, true) : 0.0);
-    for (int k = 1; levels && k < T; ++k) prec += step_bytes(k, true) + step_bytes(k, false);
+    // update_up0: x, p, q, r in; x, r out; plus the step-0 restriction
+    // without re-reading r.
+    const double upd = levels ? 48.0 * n + step_up(0) - 8.0 * n : 48.0 * n;
+    // down0: step-0 prolongation (its residual read serves the dots too);
+    // z written once, in input order
+    const double down0 = levels ? step_down(0) - 8.0 * (lvn(0) - 2.0 * lvn(1)) + 8.0 * n : 24.0 * n;
+    double prec = 0.0;
+    if (levels) {
+        prec = step_up(0) + down0;
+        for (int k = 1; k < T; ++k) prec += step_up(k) + step_down(k);
+    }
     double bytes = 0.0;
     switch (kernel) {
         case LAP_KERNEL_SPMV: bytes = spmv; break;
         case LAP_KERNEL_UPDATE: bytes = upd; break;
         case LAP_KERNEL_DOWN0: bytes = down0; break;
         case LAP_KERNEL_PRECOND: bytes = prec; break;
-        default: bytes = spmv + upd + (prec - (levels ? step_bytes(0, true) : 0.0)); break;
+        default: bytes = spmv + prec + 40.0 * n; break;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     try {
@@ -1054,32 +1409,34 @@ lap_status lap_profile_kernel(lap_hierarchy* h, int32_t kernel, int32_t reps, vo
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, s));
+        const int nn = (int)h->n;
         for (int i = 0; i < reps; ++i) {
             switch (kernel) {
                 case LAP_KERNEL_SPMV:
-                    hipLaunchKernelGGL(k_spmv_p, dim3(nblk(h->n)), dim3(kBlock), 0, s, (int)h->n,
-                                       h->A, h->z, h->p[0], h->p[1], h->q, h->S, h->part);
+                    hipLaunchKernelGGL(k_spmv_p, dim3(nblk(nn)), dim3(kBlock), 0, s, nn, h->A,
+                                       h->zn, h->p[0], h->p[1], h->q, h->S, h->part);
                     break;
                 case LAP_KERNEL_UPDATE:
                     hipLaunchKernelGGL(k_update_up0, dim3(nblk(h->lv[0].nc)), dim3(kBlock), 0, s,
-                                       h->lv[0], h->x, h->r, h->p[1], h->q, h->lv[1].r, h->S,
-                                       h->part, 1);
+                                       h->lv[0], h->perm0, h->x, h->r, h->p[1], h->q, h->lv[1].r,
+                                       h->S, h->part2, 1);
                     break;
                 case LAP_KERNEL_DOWN0:
                     hipLaunchKernelGGL(k_down0, dim3(nblk(h->lv[0].nc)), dim3(kBlock), 0, s,
-                                       h->lv[0], (int)h->n, h->r, h->z, h->lv[1].y, h->S, h->part);
+                                       h->lv[0], h->perm0, h->r, h->zn, h->lv[1].y, h->S,
+                                       h->part);
                     break;
                 case LAP_KERNEL_PRECOND: enqueue_precond(h, s, 0, h->p[0]); break;
                 default: enqueue_iteration(h, s, 0); break;
             }
         }
+        HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         if (avg_ms) *avg_ms = (double)ms / reps;
         if (alg_bytes) *alg_bytes = bytes;
-        // the profiled kernels may have set flags; leave the workspace idle
         HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const bool ran = h->stage->done == 0;

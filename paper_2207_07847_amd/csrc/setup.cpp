@@ -378,38 +378,30 @@ int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
         for (double& x : plan.top_pinv) x *= plan.theta[T];
     }
 
-    // 4. fine Laplacian in tree order, sliced ELL
+    // 4. fine Laplacian in the graph's own vertex order, sliced ELL: the
+    //    SpMV gathers neighbours, and for meshes and grids the input order
+    //    keeps those gathers contiguous across a wavefront.
     const Adjacency& g0 = plan.lv[0].g;
     const int64_t nslice = (n + kSlice - 1) / kSlice;
     plan.sell_off.assign(nslice + 1, 0);
     plan.sell_width.assign(nslice, 0);
     for (int64_t s = 0; s < nslice; ++s) {
         int64_t wmax = 0;
-        for (int64_t t = s * kSlice; t < std::min<int64_t>(n, (s + 1) * kSlice); ++t) {
-            const int32_t o = plan.perm[0][t];
-            wmax = std::max<int64_t>(wmax, g0.ptr[o + 1] - g0.ptr[o]);
-        }
+        for (int64_t t = s * kSlice; t < std::min<int64_t>(n, (s + 1) * kSlice); ++t)
+            wmax = std::max<int64_t>(wmax, g0.ptr[t + 1] - g0.ptr[t]);
         plan.sell_width[s] = (int32_t)wmax;
         plan.sell_off[s + 1] = plan.sell_off[s] + (int32_t)(wmax * kSlice);
     }
     plan.sell_col.assign(plan.sell_off[nslice], 0);
     plan.sell_w.assign(plan.sell_off[nslice], 0.0);
-    std::vector<std::pair<int32_t, double>> row;
     for (int64_t t = 0; t < n; ++t) {
         const int64_t s = t / kSlice, lane = t % kSlice;
-        const int32_t o = plan.perm[0][t];
-        row.clear();
-        for (int64_t q = g0.ptr[o]; q < g0.ptr[o + 1]; ++q)
-            row.push_back({plan.inv[0][g0.col[q]], g0.w[q]});
-        std::sort(row.begin(), row.end(),
-                  [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
-                      return x.first < y.first;
-                  });
+        const int64_t deg = g0.ptr[t + 1] - g0.ptr[t];
         for (int64_t k = 0; k < plan.sell_width[s]; ++k) {
             const int64_t slot = plan.sell_off[s] + k * kSlice + lane;
-            if (k < (int64_t)row.size()) {
-                plan.sell_col[slot] = row[k].first;
-                plan.sell_w[slot] = row[k].second;
+            if (k < deg) {
+                plan.sell_col[slot] = g0.col[g0.ptr[t] + k];
+                plan.sell_w[slot] = g0.w[g0.ptr[t] + k];
             } else {
                 plan.sell_col[slot] = (int32_t)t;   // padding: w = 0 on the row itself
                 plan.sell_w[slot] = 0.0;

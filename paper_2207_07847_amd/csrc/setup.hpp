@@ -10,7 +10,7 @@
 //     aggregate the inverse of the 2x2 Schur complement of its sparsifier
 //     block, per leftover member its elimination coefficients, per level the
 //     weight theta_j, and the pseudo-inverse of the top-level Laplacian;
-//   * the fine Laplacian in sliced-ELL form in the renumbered order.
+//   * the fine Laplacian in sliced-ELL form in the graph's own order.
 #pragma once
 
 #include <cstdint>
@@ -54,7 +54,8 @@ struct HostPlan {
     std::vector<StepCoef> step;              // nlev-1 entries
     std::vector<double> theta;               // theta_k, k = 0..nlev-1
     std::vector<double> top_pinv;            // theta_top * pinv(L_top), row-major
-    // fine Laplacian, tree order, sliced ELL (64 rows per slice, column-major)
+    // fine Laplacian, input vertex order, sliced ELL (64 rows per slice,
+    // column-major)
     std::vector<int32_t> sell_off;           // slice -> first slot
     std::vector<int32_t> sell_width;         // slice -> slots per row
     std::vector<int32_t> sell_col;
