@@ -42,6 +42,32 @@ def workload(name, scale):
     return dict(n=n, u=u, v=v, w=w, b=b, mu=0.8, tol=1e-8)
 
 
+def pmc_traffic(workload_name, scale):
+    """HBM bytes per launch of k_spmv_p from the committed rocprofv3 counter
+    summary, when it was taken on this workload and on the kernel sources
+    as they are now; None otherwise."""
+    import hashlib
+    if workload_name != "grid3d_128" or scale != 1.0:
+        return None
+    path = os.path.join(ROOT, "profiles", "k_spmv_p_grid3d_128_pmc.txt")
+    csrc = os.path.join(ROOT, "paper_2207_07847_amd", "csrc")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256()
+        for f in ("lap.hip", "kernels.hpp"):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    traffic, sha = None, None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch k_spmv_p:"):
+            traffic = float(line.split(":")[1])
+        elif line.startswith("kernel source sha256[:16]"):
+            sha = line.split(":")[-1].strip()
+    return traffic if sha == h.hexdigest()[:16] else None
+
+
 def cpu_baseline(wl, gpu_iters, budget_s):
     """The oracle (single thread) on a bounded number of PCG iterations of
     the same solve, scaled to solves/s by the iteration count the solve
@@ -146,10 +172,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # dominant kernel, timed live on the solve stream
+    # kernels timed inside iterations on the solve stream
     kern = {}
     for kid, name in [(lap.LAP_KERNEL_SPMV, "spmv_p"), (lap.LAP_KERNEL_UPDATE, "update_up0"),
-                      (lap.LAP_KERNEL_DOWN0, "down0"), (lap.LAP_KERNEL_PRECOND, "precond"),
+                      (lap.LAP_KERNEL_DOWN0, "down0"),
+                      (lap.LAP_KERNEL_PRECOND, "update_precond"),
                       (lap.LAP_KERNEL_ITER, "iteration")]:
         ms, by = lap.lap_profile_kernel(h, kid, args.profile_reps, sh)
         kern[name] = {"avg_us": ms * 1e3, "alg_bytes": by, "gbs": by / (ms * 1e-3) / 1e9}
@@ -189,7 +216,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": spmv["gbs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": pmc_traffic(args.workload, args.scale),
         },
     }
     if not args.no_cpu:

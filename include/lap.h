@@ -146,18 +146,22 @@ lap_status lap_apply_laplacian(lap_hierarchy *h, const double *x, double *y,
 lap_status lap_apply_precond(lap_hierarchy *h, const double *r, double *z,
                              void *stream);
 
-/* Kernel timing for roofline reports.  Launches the chosen part of one PCG
- * iteration `reps` times on `stream` between two HIP events, on the
- * hierarchy's own workspace (its contents are overwritten; the next
- * lap_solve reinitialises it), and returns the average milliseconds per
- * launch and the algorithmic HBM bytes one launch must move:
+/* Kernel timing for roofline reports.  Runs one untimed and then `reps`
+ * timed PCG iterations on `stream`, on the hierarchy's own workspace (its
+ * contents are overwritten; the next lap_solve reinitialises it), with a
+ * pair of HIP events around the chosen part of every timed iteration, so
+ * the part is timed in the cache state of a real solve.  Returns the
+ * average milliseconds of the part and the algorithmic HBM bytes it must
+ * move (FP64 values, int32 indices, each datum counted once):
  *   LAP_KERNEL_SPMV     p update + q = L p + p^T q   (32 n + 12 nnz bytes)
  *   LAP_KERNEL_UPDATE   x, r update + level-0 restriction and pair solves
  *   LAP_KERNEL_DOWN0    level-0 prolongation + z, r^T z reductions
- *   LAP_KERNEL_PRECOND  the whole preconditioner sequence (all levels)
+ *   LAP_KERNEL_PRECOND  update through down0: the x, r update and the
+ *                       whole preconditioner (all levels)
  *   LAP_KERNEL_ITER     one whole PCG iteration
  * Errors: LAP_EINVAL (bad id, reps < 1), LAP_EUNSUPPORTED (host-only or a
- * kernel the hierarchy does not use), LAP_EDEVICE. */
+ * part the hierarchy does not have), LAP_EBREAKDOWN (the iterations hit a
+ * breakdown, so the timing is not representative), LAP_EDEVICE. */
 enum { LAP_KERNEL_SPMV = 0, LAP_KERNEL_UPDATE = 1, LAP_KERNEL_DOWN0 = 2,
        LAP_KERNEL_PRECOND = 3, LAP_KERNEL_ITER = 4 };
 lap_status lap_profile_kernel(lap_hierarchy *h, int32_t kernel, int32_t reps,

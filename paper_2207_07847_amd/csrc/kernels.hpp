@@ -15,6 +15,9 @@ constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kTailThreads = 1024; // threads of the one-block coarse tail
 constexpr int kFinThreads = 1024;  // threads of the one-block reduction finish
 constexpr int kMaxGridPart = 3;    // values reduced per block
+constexpr int kAggPerBlock = 256;  // aggregates per block of a level kernel
+constexpr int kCapP = 2048;        // children per block staged in LDS; an
+                                   // aggregate with more gets a block alone
 
 // Scalars of one PCG run, resident in device memory.
 struct Scal {
@@ -51,6 +54,8 @@ struct LevelDev {
     const double* l2;   //             w(t, b) / D_tt
     double* ea;         // eta of the pair member a (theta-scaled)
     double* eb;
+    const int32_t* bst; // block partition: block b owns aggregates [bst[b], bst[b+1])
+    int32_t nb;         // blocks of the partition
 };
 
 // Layout of the coarse tail in LDS (offsets in doubles from the start of the

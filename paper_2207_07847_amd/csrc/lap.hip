@@ -25,6 +25,7 @@
 // once when the device flag `done` is set, so chunks of iterations captured
 // in a hipGraph are replayed without a host round trip per iteration.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <chrono>
@@ -168,16 +169,27 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
 
 // --------------------------------------------------- aggregate primitives
 
+// Blocks are dispatched to the eight XCDs in turn (block b runs on XCD
+// b mod 8).  Level kernels renumber their blocks so that every XCD owns one
+// contiguous range of the partition: neighbouring aggregates, and the
+// vertices their values are gathered from, then share one L2.
+__device__ inline int xcd_block() {
+    const int b = blockIdx.x, G = gridDim.x;
+    const int x = b & 7, q = G >> 3, rem = G & 7;
+    return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
 // Restriction of level-k values onto aggregate J plus the pair solve of the
-// aggregate's sparsifier block: g = C^T r, eta = theta S^-1 g.
-__device__ inline void agg_up(const LevelDev& s, const double* __restrict__ rk,
+// aggregate's sparsifier block: g = C^T r, eta = theta S^-1 g.  The
+// children's values are read from rs[t - toff].
+__device__ inline void agg_up(const LevelDev& s, const double* rs, int toff,
                               double* __restrict__ rk1, int J) {
     const int b0 = s.cptr[J], b1 = s.cptr[J + 1];
-    const double ra = rk[b0], rb = rk[b0 + 1];
+    const double ra = rs[b0 - toff], rb = rs[b0 + 1 - toff];
     double sum = ra + rb, ga = ra, gb = rb;
     for (int t = b0 + 2; t < b1; ++t) {
         const int li = t - 2 * J - 2;
-        const double rv = rk[t];
+        const double rv = rs[t - toff];
         sum += rv;
         ga += s.l1[li] * rv;
         gb += s.l2[li] * rv;
@@ -188,17 +200,64 @@ __device__ inline void agg_up(const LevelDev& s, const double* __restrict__ rk,
     rk1[J] = sum;
 }
 
-// Prolongation from aggregate J plus the local corrections of its members.
-__device__ inline void agg_down(const LevelDev& s, const double* __restrict__ rk,
-                                double* __restrict__ yk, const double* __restrict__ yk1, int J) {
-    const int b0 = s.cptr[J], b1 = s.cptr[J + 1];
-    const double yJ = yk1[J], ea = s.ea[J], eb = s.eb[J];
-    yk[b0] = ea + yJ;
-    yk[b0 + 1] = eb + yJ;
-    for (int t = b0 + 2; t < b1; ++t) {
+// Contributions of child t of aggregate J (first child b0) to the
+// restriction sums v = {sum, g_a, g_b}.
+__device__ inline void child_up(const LevelDev& s, int J, int b0, int t, double rv,
+                                double* v) {
+    v[0] += rv;
+    if (t == b0) v[1] += rv;
+    else if (t == b0 + 1) v[2] += rv;
+    else {
         const int li = t - 2 * J - 2;
-        yk[t] = s.l0[li] * rk[t] + s.l1[li] * ea + s.l2[li] * eb + yJ;
+        v[1] += s.l1[li] * rv;
+        v[2] += s.l2[li] * rv;
     }
+}
+
+// Pair solve of aggregate J from the completed sums v (thread 0 of a block
+// that reduced them).
+__device__ inline void agg_solve(const LevelDev& s, int J, const double* v,
+                                 double* __restrict__ rk1) {
+    const double saa = s.saa[J], sab = s.sab[J], sbb = s.sbb[J];
+    s.ea[J] = saa * v[1] + sab * v[2];
+    s.eb[J] = sab * v[1] + sbb * v[2];
+    rk1[J] = v[0];
+}
+
+// Correction of child t of aggregate J (first child b0).
+__device__ inline double child_down(const LevelDev& s, int J, int b0, int t, double rt,
+                                    double yJ, double ea, double eb) {
+    if (t == b0) return ea + yJ;
+    if (t == b0 + 1) return eb + yJ;
+    const int li = t - 2 * J - 2;
+    return s.l0[li] * rt + s.l1[li] * ea + s.l2[li] * eb + yJ;
+}
+
+// Down-sweep bookkeeping of one block in LDS: the aggregate of every
+// staged child and the aggregate's values.
+struct DownBlock {
+    int32_t own[kCapP];
+    int32_t b0[kAggPerBlock];
+    double yJ[kAggPerBlock], ea[kAggPerBlock], eb[kAggPerBlock];
+};
+
+// Phase one of a down-sweep block: per aggregate, its values and the owner
+// marks of its children.  Returns false for a block holding one aggregate
+// too large to stage (every thread then handles it directly).
+__device__ inline bool down_stage(const LevelDev& s, const double* __restrict__ yk1, int J0,
+                                  int J1, int t0, int len, DownBlock& D) {
+    if (len > kCapP) return false;
+    for (int j = threadIdx.x; j < J1 - J0; j += kBlock) {
+        const int J = J0 + j;
+        const int b0 = s.cptr[J], b1 = s.cptr[J + 1];
+        D.b0[j] = b0;
+        D.yJ[j] = yk1[J];
+        D.ea[j] = s.ea[J];
+        D.eb[j] = s.eb[J];
+        for (int t = b0; t < b1; ++t) D.own[t - t0] = j;
+    }
+    __syncthreads();
+    return true;
 }
 
 // ------------------------------------------------------ fine-level kernels
@@ -212,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* 
                                                    double* part) {
     if (S->done) return;
     const double beta = S->beta, zbar = S->zbar;
-    const int row = blockIdx.x * kBlock + threadIdx.x;
+    const int row = xcd_block() * kBlock + threadIdx.x;
     double pi = 0.0, acc = 0.0;
     if (row < n) {
         const double zi = zn[row], poi = pold[row];
@@ -235,7 +294,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int n, Sell A, const double* 
 // x += alpha p (input order); r -= alpha q (tree order, q read through the
 // permutation); partial ||r||^2; restriction of r to level 1 fused with the
 // local solves of the level-0 aggregates.  The children ranges of all
-// aggregates partition [0, n), so the same ranges index x and p.
+// aggregates partition [0, n), so the same ranges index x and p.  The
+// element-wise part runs over the block's children with coalesced accesses
+// and leaves the new residuals in LDS for the per-aggregate part.
 __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev s0, const int32_t* __restrict__ perm,
                                                        double* __restrict__ x,
                                                        double* __restrict__ r,
@@ -244,48 +305,81 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev s0, const int32_
                                                        double* __restrict__ r1, Scal* S,
                                                        double* part, int do_update) {
     if (S->done) return;
+    __shared__ double rs[kCapP];
+    __shared__ double red[4 * (kBlock / 64)];
     const double alpha = S->alpha;
-    const int J = blockIdx.x * kBlock + threadIdx.x;
+    const int b = xcd_block();
+    const int J0 = s0.bst[b], J1 = s0.bst[b + 1];
+    const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
     double rr = 0.0;
-    if (J < s0.nc) {
-        const int b0 = s0.cptr[J], b1 = s0.cptr[J + 1];
-        if (do_update) {
-            for (int t = b0; t < b1; ++t) {
+    if (len <= kCapP) {
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int t = t0 + i;
+            double rt = r[t];
+            if (do_update) {
                 x[t] += alpha * p[t];
-                const double rt = r[t] - alpha * q[perm[t]];
+                rt -= alpha * q[perm[t]];
                 r[t] = rt;
                 rr += rt * rt;
             }
+            rs[i] = rt;
         }
-        agg_up(s0, r, r1, J);
+        __syncthreads();
+        for (int J = J0 + threadIdx.x; J < J1; J += kBlock) agg_up(s0, rs, t0, r1, J);
+        if (!do_update) return;
+        double v[1] = {rr};
+        block_partial<1>(v, part);
+        return;
     }
-    if (!do_update) return;
-    double v[1] = {rr};
-    block_partial<1>(v, part);
+    // one aggregate with more children than LDS holds
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < len; i += kBlock) {
+        const int t = t0 + i;
+        double rt = r[t];
+        if (do_update) {
+            x[t] += alpha * p[t];
+            rt -= alpha * q[perm[t]];
+            r[t] = rt;
+            v[3] += rt * rt;
+        }
+        child_up(s0, J0, t0, t, rt, v);
+    }
+    block_sum<4, kBlock>(v, red);
+    if (threadIdx.x == 0) {
+        agg_solve(s0, J0, v, r1);
+        if (do_update) part[blockIdx.x] = v[3];
+    }
 }
 
 // z on the fine level, written through the permutation in input order for
-// the next SpMV; partial sums of z, r z and r (tree order, in registers).
+// the next SpMV; partial sums of z, r z and r (tree order).
 __global__ __launch_bounds__(kBlock) void k_down0(LevelDev s0, const int32_t* __restrict__ perm,
                                                   const double* __restrict__ r,
                                                   double* __restrict__ zn,
                                                   const double* __restrict__ y1, Scal* S,
                                                   double* part) {
     if (S->done) return;
-    const int J = blockIdx.x * kBlock + threadIdx.x;
+    __shared__ DownBlock D;
+    const int b = xcd_block();
+    const int J0 = s0.bst[b], J1 = s0.bst[b + 1];
+    const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
     double v[3] = {0.0, 0.0, 0.0};
-    if (J < s0.nc) {
-        const int b0 = s0.cptr[J], b1 = s0.cptr[J + 1];
-        const double yJ = y1[J], ea = s0.ea[J], eb = s0.eb[J];
-        for (int t = b0; t < b1; ++t) {
+    if (down_stage(s0, y1, J0, J1, t0, len, D)) {
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int t = t0 + i, j = D.own[i];
             const double rt = r[t];
-            double zt;
-            if (t == b0) zt = ea + yJ;
-            else if (t == b0 + 1) zt = eb + yJ;
-            else {
-                const int li = t - 2 * J - 2;
-                zt = s0.l0[li] * rt + s0.l1[li] * ea + s0.l2[li] * eb + yJ;
-            }
+            const double zt = child_down(s0, J0 + j, D.b0[j], t, rt, D.yJ[j], D.ea[j], D.eb[j]);
+            zn[perm[t]] = zt;
+            v[0] += zt;
+            v[1] += rt * zt;
+            v[2] += rt;
+        }
+    } else {
+        const double yJ = y1[J0], ea = s0.ea[J0], eb = s0.eb[J0];
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int t = t0 + i;
+            const double rt = r[t];
+            const double zt = child_down(s0, J0, t0, t, rt, yJ, ea, eb);
             zn[perm[t]] = zt;
             v[0] += zt;
             v[1] += rt * zt;
@@ -373,16 +467,41 @@ __global__ __launch_bounds__(kBlock) void k_top_only(int n, const int32_t* __res
 __global__ __launch_bounds__(kBlock) void k_up(LevelDev s, const double* __restrict__ rk,
                                                double* __restrict__ rk1, const Scal* S) {
     if (S->done) return;
-    const int J = blockIdx.x * kBlock + threadIdx.x;
-    if (J < s.nc) agg_up(s, rk, rk1, J);
+    __shared__ double rs[kCapP];
+    __shared__ double red[3 * (kBlock / 64)];
+    const int b = xcd_block();
+    const int J0 = s.bst[b], J1 = s.bst[b + 1];
+    const int t0 = s.cptr[J0], len = s.cptr[J1] - t0;
+    if (len <= kCapP) {
+        for (int i = threadIdx.x; i < len; i += kBlock) rs[i] = rk[t0 + i];
+        __syncthreads();
+        for (int J = J0 + threadIdx.x; J < J1; J += kBlock) agg_up(s, rs, t0, rk1, J);
+        return;
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = t0 + threadIdx.x; t < t0 + len; t += kBlock) child_up(s, J0, t0, t, rk[t], v);
+    block_sum<3, kBlock>(v, red);
+    if (threadIdx.x == 0) agg_solve(s, J0, v, rk1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_down(LevelDev s, const double* __restrict__ rk,
                                                  double* __restrict__ yk,
                                                  const double* __restrict__ yk1, const Scal* S) {
     if (S->done) return;
-    const int J = blockIdx.x * kBlock + threadIdx.x;
-    if (J < s.nc) agg_down(s, rk, yk, yk1, J);
+    __shared__ DownBlock D;
+    const int b = xcd_block();
+    const int J0 = s.bst[b], J1 = s.bst[b + 1];
+    const int t0 = s.cptr[J0], len = s.cptr[J1] - t0;
+    if (down_stage(s, yk1, J0, J1, t0, len, D)) {
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int t = t0 + i, j = D.own[i];
+            yk[t] = child_down(s, J0 + j, D.b0[j], t, rk[t], D.yJ[j], D.ea[j], D.eb[j]);
+        }
+    } else {
+        const double yJ = yk1[J0], ea = s.ea[J0], eb = s.eb[J0];
+        for (int t = t0 + threadIdx.x; t < t0 + len; t += kBlock)
+            yk[t] = child_down(s, J0, t0, t, rk[t], yJ, ea, eb);
+    }
 }
 
 // ------------------------------------------------------- grouped levels
@@ -721,6 +840,23 @@ int env_int(const char* name, int dflt) {
 constexpr size_t kTailLdsBytes = 152 * 1024;
 constexpr int kGrpLdsDoubles = 8192;    // 64 KB per group block
 
+// Block partition of one aggregation step for the level kernels: runs of
+// at most kAggPerBlock consecutive aggregates whose children fit kCapP; an
+// aggregate with more children than kCapP forms a block of its own.
+std::vector<int32_t> block_partition(const std::vector<int32_t>& cptr) {
+    const int32_t nc = (int32_t)cptr.size() - 1;
+    std::vector<int32_t> bst{0};
+    int32_t J0 = 0;
+    while (J0 < nc) {
+        int32_t J1 = J0 + 1;
+        if (cptr[J1] - cptr[J0] <= kCapP)
+            while (J1 < nc && J1 - J0 < kAggPerBlock && cptr[J1 + 1] - cptr[J0] <= kCapP) ++J1;
+        bst.push_back(J1);
+        J0 = J1;
+    }
+    return bst;
+}
+
 // Doubles of LDS the tail needs when it starts at level kt.
 size_t tail_lds_doubles(const HostPlan& P, int kt) {
     const int T = P.nlev() - 1;
@@ -953,7 +1089,26 @@ void finish(lap_hierarchy* h, hipStream_t s, int G, int G2 = 0, const double* pa
 
 // The preconditioner: level-0 restriction (with the x, r update when
 // do_update), the middle levels, the tail and back, z with its reductions.
-void enqueue_precond(lap_hierarchy* h, hipStream_t s, int do_update, const double* pcur) {
+// Optional timing of one part of the iteration (lap_profile_kernel): the
+// part's first and last kernels carry HIP events that take the kernels' own
+// start and end timestamps, so the part is timed in the cache state of a
+// real iteration, with no marker packets between the kernels.
+struct Marks {
+    int kernel = -1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t start(int k) const { return kernel == k ? e0 : nullptr; }
+    hipEvent_t stop(int k) const { return kernel == k ? e1 : nullptr; }
+};
+
+template <class F, class... A>
+void launch_timed(F kern, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, hipEvent_t e0,
+                  hipEvent_t e1, A... args) {
+    if (e0 || e1) hipExtLaunchKernelGGL(kern, grid, block, lds, s, e0, e1, 0, args...);
+    else hipLaunchKernelGGL(kern, grid, block, lds, s, args...);
+}
+
+void enqueue_precond(lap_hierarchy* h, hipStream_t s, int do_update, const double* pcur,
+                     const Marks& mk = Marks{}) {
     const int T = h->plan.nlev() - 1;
     const int n = (int)h->n;
     if (!h->with_msp || T == 0) {
@@ -973,15 +1128,17 @@ void enqueue_precond(lap_hierarchy* h, hipStream_t s, int do_update, const doubl
         return;
     }
     const LevelDev& s0 = h->lv[0];
-    const int g0 = nblk(s0.nc);
-    hipLaunchKernelGGL(k_update_up0, dim3(g0), dim3(kBlock), 0, s, s0, h->perm0, h->x, h->r, pcur,
-                       h->q, h->lv[1].r, h->S, h->part2, do_update);
+    const int g0 = s0.nb;
+    launch_timed(k_update_up0, dim3(g0), dim3(kBlock), 0, s,
+                 mk.kernel == LAP_KERNEL_PRECOND ? mk.e0 : mk.start(LAP_KERNEL_UPDATE),
+                 mk.stop(LAP_KERNEL_UPDATE), s0, (const int32_t*)h->perm0, h->x, h->r, pcur,
+                 (const double*)h->q, h->lv[1].r, h->S, h->part2, do_update);
     for (const auto& G : h->segs) {
         if (G.group)
             hipLaunchKernelGGL(k_up_grp, dim3(G.gd.nblocks), dim3(kGrpThreads), G.lds_up, s, G.gd,
                                h->S);
         else
-            hipLaunchKernelGGL(k_up, dim3(nblk(h->lv[G.k0].nc)), dim3(kBlock), 0, s, h->lv[G.k0],
+            hipLaunchKernelGGL(k_up, dim3(h->lv[G.k0].nb), dim3(kBlock), 0, s, h->lv[G.k0],
                                h->lv[G.k0].r, h->lv[G.k0 + 1].r, h->S);
     }
     hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), h->tail_lds, s, h->d_tail,
@@ -992,21 +1149,24 @@ void enqueue_precond(lap_hierarchy* h, hipStream_t s, int do_update, const doubl
             hipLaunchKernelGGL(k_down_grp, dim3(G.gd.nblocks), dim3(kGrpThreads), G.lds_down, s,
                                G.gd, h->S);
         else
-            hipLaunchKernelGGL(k_down, dim3(nblk(h->lv[G.k0].nc)), dim3(kBlock), 0, s,
+            hipLaunchKernelGGL(k_down, dim3(h->lv[G.k0].nb), dim3(kBlock), 0, s,
                                h->lv[G.k0], h->lv[G.k0].r, h->lv[G.k0].y, h->lv[G.k0 + 1].y, h->S);
     }
-    hipLaunchKernelGGL(k_down0, dim3(g0), dim3(kBlock), 0, s, s0, h->perm0, h->r, h->zn,
-                       h->lv[1].y, h->S, h->part);
+    launch_timed(k_down0, dim3(g0), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_DOWN0),
+                 mk.kernel == LAP_KERNEL_PRECOND ? mk.e1 : mk.stop(LAP_KERNEL_DOWN0), s0,
+                 (const int32_t*)h->perm0, (const double*)h->r, h->zn, (const double*)h->lv[1].y,
+                 h->S, h->part);
     finish<kFinRho>(h, s, g0, do_update ? g0 : 0);
 }
 
 // One PCG iteration reading p[par] and writing p[1-par].
-void enqueue_iteration(lap_hierarchy* h, hipStream_t s, int par) {
+void enqueue_iteration(lap_hierarchy* h, hipStream_t s, int par, const Marks& mk = Marks{}) {
     const int n = (int)h->n;
-    hipLaunchKernelGGL(k_spmv_p, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->A, h->zn, h->p[par],
-                       h->p[1 - par], h->q, h->S, h->part);
+    launch_timed(k_spmv_p, dim3(nblk(n)), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_SPMV),
+                 mk.stop(LAP_KERNEL_SPMV), n, h->A, (const double*)h->zn,
+                 (const double*)h->p[par], h->p[1 - par], h->q, h->S, h->part);
     finish<kFinPq>(h, s, nblk(n));
-    enqueue_precond(h, s, 1, h->p[1 - par]);
+    enqueue_precond(h, s, 1, h->p[1 - par], mk);
 }
 
 void build_graph(lap_hierarchy* h) {
@@ -1063,6 +1223,9 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
             d.l2 = h->upload(c.l2, s);
             d.ea = h->dalloc<double>(d.nc);
             d.eb = h->dalloc<double>(d.nc);
+            const std::vector<int32_t> bst = block_partition(c.cptr);
+            d.nb = (int32_t)bst.size() - 1;
+            d.bst = h->upload(bst, s);
         }
     }
     h->top_pinv = h->upload(P.top_pinv, s);
@@ -1136,8 +1299,10 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     h->p[0] = h->dalloc<double>(n);
     h->p[1] = h->dalloc<double>(n);
     h->S = h->dalloc<Scal>(1);
-    h->part = h->dalloc<double>((size_t)kMaxGridPart * nblk(n) + 64);
-    h->part2 = h->dalloc<double>((size_t)nblk(n) + 64);
+    int gmax = nblk(n);
+    for (const LevelDev& d : h->lv) gmax = std::max(gmax, (int)d.nb);
+    h->part = h->dalloc<double>((size_t)kMaxGridPart * gmax + 64);
+    h->part2 = h->dalloc<double>((size_t)gmax + 64);
     HIPCHK(hipHostMalloc((void**)&h->stage, sizeof(Scal), hipHostMallocDefault));
     std::memset(h->stage, 0, sizeof(Scal));
     HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
@@ -1360,7 +1525,8 @@ lap_status lap_profile_kernel(lap_hierarchy* h, int32_t kernel, int32_t reps, vo
     if (h->host_only) return LAP_EUNSUPPORTED;
     const int T = h->plan.nlev() - 1;
     const bool levels = h->with_msp && T >= 1;
-    if ((kernel == LAP_KERNEL_UPDATE || kernel == LAP_KERNEL_DOWN0) && !levels)
+    if ((kernel == LAP_KERNEL_UPDATE || kernel == LAP_KERNEL_DOWN0 ||
+         kernel == LAP_KERNEL_PRECOND) && !levels)
         return LAP_EUNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     // Algorithmic bytes: FP64 values, int32 indices, each datum a step needs
@@ -1386,66 +1552,61 @@ lap_status lap_profile_kernel(lap_hierarchy* h, int32_t kernel, int32_t reps, vo
     // down0: step-0 prolongation (its residual read serves the dots too);
     // z written once, in input order
     const double down0 = levels ? step_down(0) - 8.0 * (lvn(0) - 2.0 * lvn(1)) + 8.0 * n : 24.0 * n;
-    double prec = 0.0;
-    if (levels) {
-        prec = step_up(0) + down0;
-        for (int k = 1; k < T; ++k) prec += step_up(k) + step_down(k);
-    }
+    // middle levels and the tail (their data is not re-counted by update/down0)
+    double mid = 0.0;
+    for (int k = 1; levels && k < T; ++k) mid += step_up(k) + step_down(k);
     double bytes = 0.0;
     switch (kernel) {
         case LAP_KERNEL_SPMV: bytes = spmv; break;
         case LAP_KERNEL_UPDATE: bytes = upd; break;
         case LAP_KERNEL_DOWN0: bytes = down0; break;
-        case LAP_KERNEL_PRECOND: bytes = prec; break;
-        default: bytes = spmv + prec + 40.0 * n; break;
+        case LAP_KERNEL_PRECOND: bytes = upd + mid + down0; break;
+        default: bytes = spmv + (levels ? upd + mid + down0 : 96.0 * n); break;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    // ITER: two events around all timed iterations; a part: its own kernels'
+    // timestamps in every timed iteration
+    const bool whole = kernel == LAP_KERNEL_ITER;
+    std::vector<hipEvent_t> ev(whole ? 2 : 2 * (size_t)reps, nullptr);
+    auto destroy = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
     try {
         std::memset(h->stage, 0, sizeof(Scal));
         h->stage->maxit = 0x7fffffff;
         h->stage->rho = 1.0;
         h->stage->bn2 = 1.0;
         HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        HIPCHK(hipEventRecord(e0, s));
-        const int nn = (int)h->n;
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        enqueue_iteration(h, s, 1);   // untimed
+        if (whole) HIPCHK(hipEventRecord(ev[0], s));
         for (int i = 0; i < reps; ++i) {
-            switch (kernel) {
-                case LAP_KERNEL_SPMV:
-                    hipLaunchKernelGGL(k_spmv_p, dim3(nblk(nn)), dim3(kBlock), 0, s, nn, h->A,
-                                       h->zn, h->p[0], h->p[1], h->q, h->S, h->part);
-                    break;
-                case LAP_KERNEL_UPDATE:
-                    hipLaunchKernelGGL(k_update_up0, dim3(nblk(h->lv[0].nc)), dim3(kBlock), 0, s,
-                                       h->lv[0], h->perm0, h->x, h->r, h->p[1], h->q, h->lv[1].r,
-                                       h->S, h->part2, 1);
-                    break;
-                case LAP_KERNEL_DOWN0:
-                    hipLaunchKernelGGL(k_down0, dim3(nblk(h->lv[0].nc)), dim3(kBlock), 0, s,
-                                       h->lv[0], h->perm0, h->r, h->zn, h->lv[1].y, h->S,
-                                       h->part);
-                    break;
-                case LAP_KERNEL_PRECOND: enqueue_precond(h, s, 0, h->p[0]); break;
-                default: enqueue_iteration(h, s, 0); break;
+            Marks mk;
+            if (!whole) {
+                mk.kernel = kernel;
+                mk.e0 = ev[2 * i];
+                mk.e1 = ev[2 * i + 1];
             }
+            enqueue_iteration(h, s, i & 1, mk);
         }
+        if (whole) HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipGetLastError());
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (avg_ms) *avg_ms = (double)ms / reps;
+        HIPCHK(hipStreamSynchronize(s));
+        double total = 0.0;
+        for (size_t i = 0; i < ev.size(); i += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            total += ms;
+        }
+        if (avg_ms) *avg_ms = total / reps;
         if (alg_bytes) *alg_bytes = bytes;
         HIPCHK(hipMemcpyAsync(h->stage, h->S, sizeof(Scal), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const bool ran = h->stage->done == 0;
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        destroy();
         return ran ? LAP_OK : LAP_EBREAKDOWN;
     } catch (const HipErr&) {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
+        destroy();
         return LAP_EDEVICE;
     }
 }
