@@ -48,7 +48,11 @@ typedef enum {
 } lap_precond;
 
 typedef enum {
-    LAP_FP64 = 0            /* all arithmetic in double precision */
+    LAP_FP64 = 0,           /* all arithmetic in double precision */
+    LAP_MIXED_FP32_FP64 = 1 /* iterative refinement: FP64 residual b - L x,
+                               x, inner products and mean projection; each
+                               correction by PCG with FP32 SpMV and FP32
+                               preconditioner (FP32 arithmetic, FP64 sums) */
 } lap_precision;
 
 /* Flags for lap_params.flags */

@@ -1,0 +1,983 @@
+// Device kernels of the solve (gfx950).  Included by lap.hip only.
+//
+// The kernels are templates on the value type T of vectors, matrix weights
+// and preconditioner coefficients: double for the FP64 solve, float for the
+// inner solve of mixed precision.  Every reduction (inner products, sums for
+// the mean projection, norms) is carried in double whatever T is.
+//
+// Vector orders.  The SpMV gathers neighbour values, so the vectors it reads
+// and writes (x, p, q and a copy of z) stay in the graph's own vertex order,
+// where neighbours of a mesh or grid row are contiguous across a wavefront.
+// The preconditioner works in the tree order of the hierarchy (children of
+// every aggregate contiguous), so r, z and all coarse-level vectors use it.
+// Level 0 converts between the two: the restriction reads q through the
+// permutation and the prolongation writes z back through it.
+//
+// One PCG iteration is this kernel sequence (all on one stream):
+//   spmv_p      p = z - zbar + beta p_old;  q = L p;  partial p^T q
+//   finish      alpha = rho / p^T q
+//   update_up0  x += alpha p;  r -= alpha q;  partial ||r||^2; restriction of
+//               r to level 1 fused with the local solves of level-0 aggregates
+//   up / group  restriction + local solves of the middle levels
+//   tail        one workgroup in LDS: the small levels and the top solve
+//   down/group  prolongation + local corrections of the middle levels
+//   down0       z on level 0 (both orders); partial sum z, r^T z, sum r
+//   finish      zbar, rho, beta, convergence
+// Every reduction ends in a one-block finish kernel that adds the per-block
+// partials in a fixed order (bitwise reproducible).  Every kernel returns at
+// once when the device flag `done` is set, so chunks of iterations captured
+// in a hipGraph are replayed without a host round trip per iteration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace lapgpu {
+
+// ------------------------------------------------------------ reductions
+
+template <class V>
+__device__ inline V wave_sum1(V v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int N>
+__device__ inline void wave_sum(double (&v)[N]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off, 64);
+}
+
+// Block sum in a fixed order; the result is valid in thread 0.
+template <int N, int NT>
+__device__ inline void block_sum(double (&v)[N], double* lds) {
+    constexpr int NW = NT / 64;
+    wave_sum<N>(v);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) lds[i * NW + wid] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double s = 0.0;
+            for (int w = 0; w < NW; ++w) s += lds[i * NW + w];
+            v[i] = s;
+        }
+}
+
+// Each block stores its partial sums (value i of block b at part[i*G + b]);
+// a one-block finish kernel adds them in block order after the producing
+// kernel has completed.  No device-scope fence is needed in the producer:
+// the kernel boundary orders the partials before the finish.
+template <int N>
+__device__ inline void block_partial(double (&v)[N], double* part) {
+    __shared__ double lds[N * (kBlock / 64)];
+    block_sum<N, kBlock>(v, lds);
+    if (threadIdx.x == 0) {
+        const int G = gridDim.x;
+#pragma unroll
+        for (int i = 0; i < N; ++i) part[i * G + blockIdx.x] = v[i];
+    }
+}
+
+enum FinOp { kFinPq, kFinRr, kFinRho, kFinBsum, kFinBn2, kFinXsum, kFinRes2 };
+
+// Sums the partials of a producer grid of G blocks in a fixed order and
+// applies the scalar step of the solver that needs the total.  kFinRho also
+// receives the ||r||^2 partials of the update kernel (G2 blocks at part2)
+// when G2 > 0 and takes the convergence decision there: the preconditioner
+// pass between the update and this point is then wasted only on the final
+// iteration, and one launch per iteration is saved.
+template <int OP>
+__global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
+                                                        const double* __restrict__ part, int G2,
+                                                        const double* __restrict__ part2,
+                                                        Scal* S) {
+    constexpr int N = (OP == kFinRho) ? 4 : 1;
+    constexpr bool loop = OP == kFinPq || OP == kFinRr || OP == kFinRho;
+    if (loop && S->done) return;
+    __shared__ double lds[N * (kFinThreads / 64)];
+    double v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = 0.0;
+    const int nv = (OP == kFinRho) ? 3 : 1;
+    for (int i = 0; i < nv; ++i) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        int b = threadIdx.x;
+        for (; b + 3 * kFinThreads < G; b += 4 * kFinThreads) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += part[i * G + b + u * kFinThreads];
+        }
+        for (; b < G; b += kFinThreads) a[0] += part[i * G + b];
+        v[i] = (a[0] + a[1]) + (a[2] + a[3]);
+    }
+    if (OP == kFinRho)
+        for (int b = threadIdx.x; b < G2; b += kFinThreads) v[N - 1] += part2[b];
+    block_sum<N, kFinThreads>(v, lds);
+    if (threadIdx.x != 0) return;
+    if (OP == kFinPq) {
+        const double pq = v[0];
+        S->pq = pq;
+        S->iter += 1;
+        if (!(pq > 0.0) || !isfinite(pq)) S->done = 3;
+        else S->alpha = S->rho / pq;
+    } else if (OP == kFinRr) {
+        S->rr = v[0];
+        if (!isfinite(v[0])) S->done = 3;
+        else if (v[0] <= S->tol2 * S->bn2) S->done = 1;
+        else if (S->iter >= S->maxit) S->done = 2;
+    } else if (OP == kFinRho) {
+        const double zbar = v[0] / (double)n;
+        const double rho = v[1] - zbar * v[2];
+        S->zbar = zbar;
+        if (!isfinite(rho)) S->done = 3;
+        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->first = 0;
+        S->rho = rho;
+        if (G2 > 0) {
+            S->rr = v[3];
+            if (!isfinite(v[3])) S->done = 3;
+            else if (v[3] <= S->tol2 * S->bn2) S->done = 1;
+            else if (S->iter >= S->maxit) S->done = 2;
+        }
+    } else if (OP == kFinBsum) {
+        S->bsum = v[0];
+    } else if (OP == kFinBn2) {
+        S->bn2 = v[0];
+        S->iter = 0;
+        S->first = 1;
+        S->alpha = 0.0;
+        S->beta = 0.0;
+        S->zbar = 0.0;
+        S->rr = v[0];
+        if (!isfinite(v[0])) S->done = 4;
+        else if (v[0] == 0.0) S->done = 1;
+        else if (S->maxit <= 0) S->done = 2;
+        else S->done = 0;
+    } else if (OP == kFinXsum) {
+        S->xsum = v[0];
+    } else if (OP == kFinRes2) {
+        S->res2 = v[0];
+    }
+}
+
+// Blocks are dispatched to the eight XCDs in turn (block b runs on XCD
+// b mod 8).  The streaming kernels renumber their blocks so that every XCD
+// owns one contiguous range of the work: neighbouring rows and aggregates,
+// and the vertices their values are gathered from, then share one L2.
+__device__ inline int xcd_block() {
+    const int b = blockIdx.x, G = gridDim.x;
+    const int x = b & 7, q = G >> 3, rem = G & 7;
+    return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
+// -------------------------------------------------------- Laplacian rows
+
+// One light row of sliced ELL: sum over its slots of w * diff(j), where
+// diff(j) is the row's value minus the neighbour's, (L v)_i = sum_j
+// w_ij (v_i - v_j) (the Laplacian of Sec. 2.1 with no stored diagonal).
+template <class T, class F>
+__device__ inline T light_row(const Sell<T>& A, int slot, F diff) {
+    const int sl = slot >> 6;
+    const int base = A.off[sl] + (slot & 63);
+    const int W = A.width[sl];
+    T acc = T(0);
+    for (int k = 0; k < W; ++k) {
+        const int j = A.col[base + k * 64];
+        acc += A.w[base + k * 64] * diff(j);
+    }
+    return acc;
+}
+
+// The same sum for heavy row h, entries strided over `nt` threads from
+// thread `t`; each thread returns its share.
+template <class T, class F>
+__device__ inline T heavy_share(const Sell<T>& A, int h, int t, int nt, F diff) {
+    T acc = T(0);
+    for (int q = A.hptr[h] + t; q < A.hptr[h + 1]; q += nt) acc += A.hw[q] * diff(A.hcol[q]);
+    return acc;
+}
+
+// Heavy block hb: calls fin(row, sum) once per heavy row, from one thread,
+// after the row's sum is complete.  One wavefront per row, or the whole
+// block for a single row above kHeavyBlockDeg.  `mk(row)` returns the
+// neighbour-difference functor of that row.
+template <class T, class Mk, class Fin>
+__device__ inline void heavy_block(const Sell<T>& A, int hb, Mk mk, Fin fin) {
+    __shared__ T red[kBlock / 64];
+    const int h0 = A.hblk[hb], h1 = A.hblk[hb + 1];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (h1 - h0 == 1 && A.hptr[h0 + 1] - A.hptr[h0] > kHeavyBlockDeg) {
+        const int row = A.hrow[h0];
+        T acc = wave_sum1(heavy_share(A, h0, (int)threadIdx.x, kBlock, mk(row)));
+        if (lane == 0) red[wid] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T tot = red[0];
+            for (int w = 1; w < kBlock / 64; ++w) tot += red[w];
+            fin(row, tot);
+        }
+    } else if (h0 + wid < h1) {
+        const int h = h0 + wid, row = A.hrow[h];
+        const T acc = wave_sum1(heavy_share(A, h, lane, 64, mk(row)));
+        if (lane == 0) fin(row, acc);
+    }
+}
+
+// ------------------------------------------------------ fine-level kernels
+
+// Input order: p = zn - zbar + beta p_old; q = L p; partial p^T q.  The
+// neighbours' p are formed on the fly from zn and p_old, as differences
+// (z_i - z_j) + beta (p_i - p_j) in which zbar cancels.  Blocks [0, nlb)
+// take the sliced rows, the rest the heavy rows.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* __restrict__ zn,
+                                                   const T* __restrict__ pold,
+                                                   T* __restrict__ pnew, T* __restrict__ q,
+                                                   Scal* S, double* part) {
+    if (S->done) return;
+    const T beta = (T)S->beta, zbar = (T)S->zbar;
+    const int lb = xcd_block();
+    double v[1] = {0.0};
+    if (lb < nlb) {
+        const int slot = lb * kBlock + threadIdx.x;
+        if (slot < A.nlight) {
+            const int row = A.row ? A.row[slot] : slot;
+            const T zi = zn[row], poi = pold[row];
+            const T pi = (zi - zbar) + beta * poi;
+            const T acc = light_row(A, slot, [&](int j) {
+                return (zi - zn[j]) + beta * (poi - pold[j]);
+            });
+            pnew[row] = pi;
+            q[row] = acc;
+            v[0] = (double)pi * (double)acc;
+        }
+    } else {
+        heavy_block(
+            A, lb - nlb,
+            [&](int row) {
+                const T zi = zn[row], poi = pold[row];
+                return [=](int j) { return (zi - zn[j]) + beta * (poi - pold[j]); };
+            },
+            [&](int row, T acc) {
+                const T pi = (zn[row] - zbar) + beta * pold[row];
+                pnew[row] = pi;
+                q[row] = acc;
+                v[0] = (double)pi * (double)acc;
+            });
+    }
+    block_partial<1>(v, part);
+}
+
+// y = L x (input order, FP64).
+__global__ __launch_bounds__(kBlock) void k_spmv_plain(int nlb, Sell<double> A,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y) {
+    const int lb = xcd_block();
+    if (lb < nlb) {
+        const int slot = lb * kBlock + threadIdx.x;
+        if (slot >= A.nlight) return;
+        const int row = A.row ? A.row[slot] : slot;
+        const double xi = x[row];
+        y[row] = light_row(A, slot, [&](int j) { return xi - x[j]; });
+    } else {
+        heavy_block(
+            A, lb - nlb,
+            [&](int row) {
+                const double xi = x[row];
+                return [=](int j) { return xi - x[j]; };
+            },
+            [&](int row, double acc) { y[row] = acc; });
+    }
+}
+
+// r = bh - L x (input order, FP64; r may be null); partial ||bh - L x||^2.
+__global__ __launch_bounds__(kBlock) void k_resid(int nlb, Sell<double> A,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ bh,
+                                                  double* __restrict__ r, double* part) {
+    const int lb = xcd_block();
+    double v[1] = {0.0};
+    if (lb < nlb) {
+        const int slot = lb * kBlock + threadIdx.x;
+        if (slot < A.nlight) {
+            const int row = A.row ? A.row[slot] : slot;
+            const double xi = x[row];
+            const double d = bh[row] - light_row(A, slot, [&](int j) { return xi - x[j]; });
+            if (r) r[row] = d;
+            v[0] = d * d;
+        }
+    } else {
+        heavy_block(
+            A, lb - nlb,
+            [&](int row) {
+                const double xi = x[row];
+                return [=](int j) { return xi - x[j]; };
+            },
+            [&](int row, double acc) {
+                const double d = bh[row] - acc;
+                if (r) r[row] = d;
+                v[0] = d * d;
+            });
+    }
+    block_partial<1>(v, part);
+}
+
+// --------------------------------------------------- aggregate primitives
+
+// Restriction of level-k values onto aggregate J plus the pair solve of the
+// aggregate's sparsifier block: g = C^T r, eta = theta S^-1 g.  The
+// children's values are read from rs[t - toff].
+template <class T>
+__device__ inline void agg_up(const LevelDev<T>& s, const T* rs, int toff, T* __restrict__ rk1,
+                              int J) {
+    const int b0 = s.cptr[J], b1 = s.cptr[J + 1];
+    const T ra = rs[b0 - toff], rb = rs[b0 + 1 - toff];
+    T sum = ra + rb, ga = ra, gb = rb;
+    for (int t = b0 + 2; t < b1; ++t) {
+        const int li = t - 2 * J - 2;
+        const T rv = rs[t - toff];
+        sum += rv;
+        ga += s.l1[li] * rv;
+        gb += s.l2[li] * rv;
+    }
+    const T saa = s.saa[J], sab = s.sab[J], sbb = s.sbb[J];
+    s.ea[J] = saa * ga + sab * gb;
+    s.eb[J] = sab * ga + sbb * gb;
+    rk1[J] = sum;
+}
+
+// Contributions of child t of aggregate J (first child b0) to the
+// restriction sums v = {sum, g_a, g_b} (double: a block-wide reduction
+// over a large aggregate follows).
+template <class T>
+__device__ inline void child_up(const LevelDev<T>& s, int J, int b0, int t, T rv, double* v) {
+    v[0] += rv;
+    if (t == b0) v[1] += rv;
+    else if (t == b0 + 1) v[2] += rv;
+    else {
+        const int li = t - 2 * J - 2;
+        v[1] += (double)s.l1[li] * rv;
+        v[2] += (double)s.l2[li] * rv;
+    }
+}
+
+// Pair solve of aggregate J from the completed sums v.
+template <class T>
+__device__ inline void agg_solve(const LevelDev<T>& s, int J, const double* v,
+                                 T* __restrict__ rk1) {
+    const T ga = (T)v[1], gb = (T)v[2];
+    const T saa = s.saa[J], sab = s.sab[J], sbb = s.sbb[J];
+    s.ea[J] = saa * ga + sab * gb;
+    s.eb[J] = sab * ga + sbb * gb;
+    rk1[J] = (T)v[0];
+}
+
+// Correction of child t of aggregate J (first child b0).
+template <class T>
+__device__ inline T child_down(const LevelDev<T>& s, int J, int b0, int t, T rt, T yJ, T ea,
+                               T eb) {
+    if (t == b0) return ea + yJ;
+    if (t == b0 + 1) return eb + yJ;
+    const int li = t - 2 * J - 2;
+    return s.l0[li] * rt + s.l1[li] * ea + s.l2[li] * eb + yJ;
+}
+
+// Down-sweep bookkeeping of one block in LDS: the aggregate of every
+// staged child and the aggregate's values.
+template <class T>
+struct DownBlock {
+    int32_t own[kCapP];
+    int32_t b0[kAggPerBlock];
+    T yJ[kAggPerBlock], ea[kAggPerBlock], eb[kAggPerBlock];
+};
+
+// Phase one of a down-sweep block: per aggregate, its values and the owner
+// marks of its children.  Returns false for a block holding one aggregate
+// too large to stage (every thread then handles it directly).
+template <class T>
+__device__ inline bool down_stage(const LevelDev<T>& s, const T* __restrict__ yk1, int J0, int J1,
+                                  int t0, int len, DownBlock<T>& D) {
+    if (len > kCapP) return false;
+    for (int j = threadIdx.x; j < J1 - J0; j += kBlock) {
+        const int J = J0 + j;
+        const int b0 = s.cptr[J], b1 = s.cptr[J + 1];
+        D.b0[j] = b0;
+        D.yJ[j] = yk1[J];
+        D.ea[j] = s.ea[J];
+        D.eb[j] = s.eb[J];
+        for (int t = b0; t < b1; ++t) D.own[t - t0] = j;
+    }
+    __syncthreads();
+    return true;
+}
+
+// x += alpha p (input order); r -= alpha q (tree order, q read through the
+// permutation); partial ||r||^2; restriction of r to level 1 fused with the
+// local solves of the level-0 aggregates.  The children ranges of all
+// aggregates partition [0, n), so the same ranges index x and p.  The
+// element-wise part runs over the block's children with coalesced accesses
+// and leaves the new residuals in LDS for the per-aggregate part.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev<T> s0,
+                                                       const int32_t* __restrict__ perm,
+                                                       T* __restrict__ x, T* __restrict__ r,
+                                                       const T* __restrict__ p,
+                                                       const T* __restrict__ q,
+                                                       T* __restrict__ r1, Scal* S, double* part,
+                                                       int do_update) {
+    if (S->done) return;
+    __shared__ T rs[kCapP];
+    __shared__ double red[4 * (kBlock / 64)];
+    const T alpha = (T)S->alpha;
+    const int b = xcd_block();
+    const int J0 = s0.bst[b], J1 = s0.bst[b + 1];
+    const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
+    double rr = 0.0;
+    if (len <= kCapP) {
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int t = t0 + i;
+            T rt = r[t];
+            if (do_update) {
+                x[t] += alpha * p[t];
+                rt -= alpha * q[perm[t]];
+                r[t] = rt;
+                rr += (double)rt * rt;
+            }
+            rs[i] = rt;
+        }
+        __syncthreads();
+        for (int J = J0 + threadIdx.x; J < J1; J += kBlock) agg_up(s0, rs, t0, r1, J);
+        if (!do_update) return;
+        double v[1] = {rr};
+        block_partial<1>(v, part);
+        return;
+    }
+    // one aggregate with more children than LDS holds
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < len; i += kBlock) {
+        const int t = t0 + i;
+        T rt = r[t];
+        if (do_update) {
+            x[t] += alpha * p[t];
+            rt -= alpha * q[perm[t]];
+            r[t] = rt;
+            v[3] += (double)rt * rt;
+        }
+        child_up(s0, J0, t0, t, rt, v);
+    }
+    block_sum<4, kBlock>(v, red);
+    if (threadIdx.x == 0) {
+        agg_solve(s0, J0, v, r1);
+        if (do_update) part[blockIdx.x] = v[3];
+    }
+}
+
+// z on the fine level, written through the permutation in input order for
+// the next SpMV; partial sums of z, r z and r (tree order).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_down0(LevelDev<T> s0, const int32_t* __restrict__ perm,
+                                                  const T* __restrict__ r, T* __restrict__ zn,
+                                                  const T* __restrict__ y1, Scal* S,
+                                                  double* part) {
+    if (S->done) return;
+    __shared__ DownBlock<T> D;
+    const int b = xcd_block();
+    const int J0 = s0.bst[b], J1 = s0.bst[b + 1];
+    const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (down_stage(s0, y1, J0, J1, t0, len, D)) {
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int t = t0 + i, j = D.own[i];
+            const T rt = r[t];
+            const T zt = child_down(s0, J0 + j, D.b0[j], t, rt, D.yJ[j], D.ea[j], D.eb[j]);
+            zn[perm[t]] = zt;
+            v[0] += zt;
+            v[1] += (double)rt * zt;
+            v[2] += rt;
+        }
+    } else {
+        const T yJ = y1[J0], ea = s0.ea[J0], eb = s0.eb[J0];
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int t = t0 + i;
+            const T rt = r[t];
+            const T zt = child_down(s0, J0, t0, t, rt, yJ, ea, eb);
+            zn[perm[t]] = zt;
+            v[0] += zt;
+            v[1] += (double)rt * zt;
+            v[2] += rt;
+        }
+    }
+    block_partial<3>(v, part);
+}
+
+// Without a hierarchy below the fine level: x and r update only.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_update_none(int n, const int32_t* __restrict__ perm,
+                                                        T* __restrict__ x, T* __restrict__ r,
+                                                        const T* __restrict__ p,
+                                                        const T* __restrict__ q, Scal* S,
+                                                        double* part) {
+    if (S->done) return;
+    const T alpha = (T)S->alpha;
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (t < n) {
+        x[t] += alpha * p[t];
+        const T rt = r[t] - alpha * q[perm[t]];
+        r[t] = rt;
+        v[0] = (double)rt * rt;
+    }
+    block_partial<1>(v, part);
+}
+
+// Plain CG: z = r (both orders) with the down0 reductions.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_prec_none(int n, const int32_t* __restrict__ perm,
+                                                      const T* __restrict__ r, T* __restrict__ z,
+                                                      T* __restrict__ zn, Scal* S, double* part) {
+    if (S->done) return;
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (t < n) {
+        const T rt = r[t];
+        z[t] = rt;
+        zn[perm[t]] = rt;
+        v[0] = rt;
+        v[1] = (double)rt * rt;
+        v[2] = rt;
+    }
+    block_partial<3>(v, part);
+}
+
+// One-level hierarchy (the fine level is the top, at most kTopMax nodes):
+// the MSP is theta_0 pinv(L) = pinv(L), applied by one workgroup, which also
+// does the finish step of the down0 reductions itself.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_top_only(int n, const int32_t* __restrict__ perm,
+                                                     const T* __restrict__ tp,
+                                                     const T* __restrict__ r, T* __restrict__ z,
+                                                     T* __restrict__ zn, Scal* S) {
+    if (S->done) return;
+    __shared__ double lds[3 * (kBlock / 64)];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        T acc = T(0);
+        for (int j = 0; j < n; ++j) acc += tp[i * n + j] * r[j];
+        z[i] = acc;
+        zn[perm[i]] = acc;
+        v[0] += acc;
+        v[1] += (double)r[i] * acc;
+        v[2] += r[i];
+    }
+    block_sum<3, kBlock>(v, lds);
+    if (threadIdx.x == 0) {
+        const double zbar = v[0] / (double)n;
+        const double rho = v[1] - zbar * v[2];
+        S->zbar = zbar;
+        if (!isfinite(rho)) S->done = 3;
+        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->first = 0;
+        S->rho = rho;
+    }
+}
+
+// ------------------------------------------------------ per-level kernels
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_up(LevelDev<T> s, const T* __restrict__ rk,
+                                               T* __restrict__ rk1, const Scal* S) {
+    if (S->done) return;
+    __shared__ T rs[kCapP];
+    __shared__ double red[3 * (kBlock / 64)];
+    const int b = xcd_block();
+    const int J0 = s.bst[b], J1 = s.bst[b + 1];
+    const int t0 = s.cptr[J0], len = s.cptr[J1] - t0;
+    if (len <= kCapP) {
+        for (int i = threadIdx.x; i < len; i += kBlock) rs[i] = rk[t0 + i];
+        __syncthreads();
+        for (int J = J0 + threadIdx.x; J < J1; J += kBlock) agg_up(s, rs, t0, rk1, J);
+        return;
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = t0 + threadIdx.x; t < t0 + len; t += kBlock) child_up(s, J0, t0, t, rk[t], v);
+    block_sum<3, kBlock>(v, red);
+    if (threadIdx.x == 0) agg_solve(s, J0, v, rk1);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_down(LevelDev<T> s, const T* __restrict__ rk,
+                                                 T* __restrict__ yk, const T* __restrict__ yk1,
+                                                 const Scal* S) {
+    if (S->done) return;
+    __shared__ DownBlock<T> D;
+    const int b = xcd_block();
+    const int J0 = s.bst[b], J1 = s.bst[b + 1];
+    const int t0 = s.cptr[J0], len = s.cptr[J1] - t0;
+    if (down_stage(s, yk1, J0, J1, t0, len, D)) {
+        for (int i = threadIdx.x; i < len; i += kBlock) {
+            const int t = t0 + i, j = D.own[i];
+            yk[t] = child_down(s, J0 + j, D.b0[j], t, rk[t], D.yJ[j], D.ea[j], D.eb[j]);
+        }
+    } else {
+        const T yJ = yk1[J0], ea = s.ea[J0], eb = s.eb[J0];
+        for (int t = t0 + threadIdx.x; t < t0 + len; t += kBlock)
+            yk[t] = child_down(s, J0, t0, t, rk[t], yJ, ea, eb);
+    }
+}
+
+// ------------------------------------------------------- grouped levels
+
+// Flat copy global -> LDS with eight loads in flight per thread.
+template <class T>
+__device__ inline void stage_copy(T* __restrict__ dst, const T* __restrict__ src, int len) {
+    constexpr int U = 8, B = kGrpThreads;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * B < len; i += U * B) {
+        T t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = src[i + u * B];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dst[i + u * B] = t[u];
+    }
+    for (; i < len; i += B) dst[i] = src[i];
+}
+
+// Per-block bookkeeping of a group (level ranges and LDS layout) lives in
+// LDS: it is indexed by the level inside loops, and a runtime-indexed
+// private array would be placed in scratch memory.
+struct GrpBlock {
+    int32_t st[kMaxGroupLevels + 1];
+    int32_t cnt[kMaxGroupLevels + 1];
+    GrpLayout L;
+};
+
+template <class T>
+__device__ inline void grp_setup(const GroupDev<T>& G, int m, GrpBlock& B) {
+    if (threadIdx.x == 0) {
+        const int b = blockIdx.x, nb1 = G.nblocks + 1;
+        for (int j = 0; j <= m; ++j) {
+            B.st[j] = G.D[j * nb1 + b];
+            B.cnt[j] = G.D[j * nb1 + b + 1] - B.st[j];
+        }
+        grp_layout(m, B.cnt, (int)(sizeof(T) / sizeof(int32_t)), B.L);
+    }
+    __syncthreads();
+}
+
+// Up-sweep of a level group [k0, k1): level-k0 residuals in, level-k1
+// residuals out; intermediate residuals and pair corrections go to the
+// block's scratch chunk for the down-sweep.
+template <class T>
+__global__ __launch_bounds__(kGrpThreads) void k_up_grp(GroupDev<T> G, const Scal* S) {
+    if (S->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    const int m = G.k1 - G.k0, tid = threadIdx.x, nth = blockDim.x;
+    __shared__ GrpBlock B;
+    grp_setup(G, m, B);
+    const int32_t* st = B.st;
+    const int32_t* cnt = B.cnt;
+    const GrpLayout& L = B.L;
+    stage_copy(sm, G.upack + G.uoff[blockIdx.x], L.ulen);
+    stage_copy(sm + L.ur[0], G.r_in + st[0], cnt[0]);
+    __syncthreads();
+    T* scr = G.scr + G.xoff[blockIdx.x];
+    for (int j = 0; j < m; ++j) {
+        const int na = cnt[j + 1], nl = cnt[j] - 2 * na;
+        const int* cp = reinterpret_cast<const int*>(sm + L.ucp[j]);
+        const T* sa = sm + L.us[j];
+        const T* l1 = sm + L.ul[j];
+        const T* l2 = l1 + nl;
+        const T* rk = sm + L.ur[j];
+        T* rk1 = sm + L.ur[j + 1];
+        T* eo = scr + L.xe[j];
+        T* ro = (j + 1 < m) ? scr + L.xr[j + 1] : G.r_top + st[m];
+        for (int J = tid; J < na; J += nth) {
+            const int b0 = cp[J], b1 = cp[J + 1];
+            const T ra = rk[b0], rb = rk[b0 + 1];
+            T sum = ra + rb, ga = ra, gb = rb;
+            for (int c = b0 + 2; c < b1; ++c) {
+                const int li = c - 2 * J - 2;
+                const T rv = rk[c];
+                sum += rv;
+                ga += l1[li] * rv;
+                gb += l2[li] * rv;
+            }
+            const T saa = sa[J], sab = sa[na + J], sbb = sa[2 * na + J];
+            eo[J] = saa * ga + sab * gb;
+            eo[na + J] = sab * ga + sbb * gb;
+            rk1[J] = sum;
+            ro[J] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// Down-sweep of a level group: level-k1 corrections in, level-k0 out.
+template <class T>
+__global__ __launch_bounds__(kGrpThreads) void k_down_grp(GroupDev<T> G, const Scal* S) {
+    if (S->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    const int m = G.k1 - G.k0, tid = threadIdx.x, nth = blockDim.x;
+    __shared__ GrpBlock B;
+    grp_setup(G, m, B);
+    const int32_t* st = B.st;
+    const int32_t* cnt = B.cnt;
+    const GrpLayout& L = B.L;
+    stage_copy(sm, G.dpack + G.doff[blockIdx.x], L.dlen);
+    stage_copy(sm + L.dx, G.scr + G.xoff[blockIdx.x], L.xlen);
+    stage_copy(sm + L.dr0, G.r_in + st[0], cnt[0]);
+    stage_copy(sm + L.dy[m], G.y_top + st[m], cnt[m]);
+    __syncthreads();
+    for (int j = m - 1; j >= 0; --j) {
+        const int na = cnt[j + 1], nl = cnt[j] - 2 * na;
+        const int* cp = reinterpret_cast<const int*>(sm + L.dcp[j]);
+        const T* l0 = sm + L.dl[j];
+        const T* l1 = l0 + nl;
+        const T* l2 = l1 + nl;
+        const T* rk = j == 0 ? sm + L.dr0 : sm + L.dx + L.xr[j];
+        const T* e = sm + L.dx + L.xe[j];
+        T* yk = sm + L.dy[j];
+        const T* yk1 = sm + L.dy[j + 1];
+        for (int J = tid; J < na; J += nth) {
+            const int b0 = cp[J], b1 = cp[J + 1];
+            const T yJ = yk1[J], ea = e[J], eb = e[na + J];
+            yk[b0] = ea + yJ;
+            yk[b0 + 1] = eb + yJ;
+            for (int c = b0 + 2; c < b1; ++c) {
+                const int li = c - 2 * J - 2;
+                yk[c] = l0[li] * rk[c] + l1[li] * ea + l2[li] * eb + yJ;
+            }
+        }
+        __syncthreads();
+    }
+    const T* y0 = sm + L.dy[0];
+    T* out = G.y_out + st[0];
+    for (int t = tid; t < cnt[0]; t += nth) out[t] = y0[t];
+}
+
+// ------------------------------------------------------------ coarse tail
+
+// Levels kt .. top in one workgroup, entirely in LDS: the coefficients of
+// those levels are staged from one packed device buffer with a coalesced
+// copy, then restriction + local solves run upwards, theta_top pinv(L_top)
+// on the top, prolongation + corrections back down to level kt.  An
+// aggregate with many children (a hub of a power-law graph) is reduced by
+// the whole workgroup after the others of its level.
+template <class T>
+__global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restrict__ D,
+                                                       const T* __restrict__ pack,
+                                                       const T* __restrict__ r_kt,
+                                                       T* __restrict__ y_kt, const Scal* S) {
+    if (S->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* sm = reinterpret_cast<T*>(smem);
+    __shared__ double red[3 * (kTailThreads / 64)];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int npack = D->pack, nsteps = D->nsteps;
+    for (int i = tid; i < npack; i += nth) sm[i] = pack[i];
+    {
+        const int n0 = nsteps > 0 ? D->st[0].nk : D->nt;
+        T* r0 = sm + D->r[0];
+        for (int i = tid; i < n0; i += nth) r0[i] = r_kt[i];
+    }
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        const TailStep t = D->st[s];
+        const int* cp = reinterpret_cast<const int*>(sm + t.cptr);
+        const T* rk = sm + D->r[s];
+        T* rk1 = sm + D->r[s + 1];
+        for (int J = tid; J < t.nc; J += nth) {
+            const int b0 = cp[J], b1 = cp[J + 1];
+            if (b1 - b0 > kTailBig) continue;
+            const T ra = rk[b0], rb = rk[b0 + 1];
+            T sum = ra + rb, ga = ra, gb = rb;
+            for (int c = b0 + 2; c < b1; ++c) {
+                const int li = c - 2 * J - 2;
+                const T rv = rk[c];
+                sum += rv;
+                ga += sm[t.l1 + li] * rv;
+                gb += sm[t.l2 + li] * rv;
+            }
+            const T saa = sm[t.saa + J], sab = sm[t.sab + J], sbb = sm[t.sbb + J];
+            sm[t.ea + J] = saa * ga + sab * gb;
+            sm[t.eb + J] = sab * ga + sbb * gb;
+            rk1[J] = sum;
+        }
+        for (int bi = 0; bi < t.nbig; ++bi) {
+            const int J = reinterpret_cast<const int*>(sm + t.big)[bi];
+            const int b0 = cp[J], b1 = cp[J + 1];
+            double v[3] = {0.0, 0.0, 0.0};
+            for (int c = b0 + tid; c < b1; c += nth) {
+                const T rv = rk[c];
+                v[0] += rv;
+                if (c == b0) v[1] += rv;
+                else if (c == b0 + 1) v[2] += rv;
+                else {
+                    const int li = c - 2 * J - 2;
+                    v[1] += (double)sm[t.l1 + li] * rv;
+                    v[2] += (double)sm[t.l2 + li] * rv;
+                }
+            }
+            block_sum<3, kTailThreads>(v, red);
+            if (tid == 0) {
+                const T ga = (T)v[1], gb = (T)v[2];
+                const T saa = sm[t.saa + J], sab = sm[t.sab + J], sbb = sm[t.sbb + J];
+                sm[t.ea + J] = saa * ga + sab * gb;
+                sm[t.eb + J] = sab * ga + sbb * gb;
+                rk1[J] = (T)v[0];
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+    {
+        const int nt = D->nt;
+        const T* rT = sm + D->r[nsteps];
+        T* yT = sm + D->y[nsteps];
+        const T* tp = sm + D->pinv;
+        for (int i = tid; i < nt; i += nth) {
+            T acc = T(0);
+            for (int j = 0; j < nt; ++j) acc += tp[i * nt + j] * rT[j];
+            yT[i] = acc;
+        }
+        __syncthreads();
+    }
+    for (int s = nsteps - 1; s >= 0; --s) {
+        const TailStep t = D->st[s];
+        const int* cp = reinterpret_cast<const int*>(sm + t.cptr);
+        const T* rk = sm + D->r[s];
+        T* yk = sm + D->y[s];
+        const T* yk1 = sm + D->y[s + 1];
+        for (int J = tid; J < t.nc; J += nth) {
+            const int b0 = cp[J], b1 = cp[J + 1];
+            if (b1 - b0 > kTailBig) continue;
+            const T yJ = yk1[J], ea = sm[t.ea + J], eb = sm[t.eb + J];
+            yk[b0] = ea + yJ;
+            yk[b0 + 1] = eb + yJ;
+            for (int c = b0 + 2; c < b1; ++c) {
+                const int li = c - 2 * J - 2;
+                yk[c] = sm[t.l0 + li] * rk[c] + sm[t.l1 + li] * ea + sm[t.l2 + li] * eb + yJ;
+            }
+        }
+        for (int bi = 0; bi < t.nbig; ++bi) {
+            const int J = reinterpret_cast<const int*>(sm + t.big)[bi];
+            const int b0 = cp[J], b1 = cp[J + 1];
+            const T yJ = yk1[J], ea = sm[t.ea + J], eb = sm[t.eb + J];
+            for (int c = b0 + tid; c < b1; c += nth) {
+                if (c == b0) yk[c] = ea + yJ;
+                else if (c == b0 + 1) yk[c] = eb + yJ;
+                else {
+                    const int li = c - 2 * J - 2;
+                    yk[c] = sm[t.l0 + li] * rk[c] + sm[t.l1 + li] * ea + sm[t.l2 + li] * eb + yJ;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    {
+        const int n0 = nsteps > 0 ? D->st[0].nk : D->nt;
+        const T* y0 = sm + D->y[0];
+        for (int i = tid; i < n0; i += nth) y_kt[i] = y0[i];
+    }
+}
+
+// ------------------------------------------------- solve set-up and finish
+
+__global__ __launch_bounds__(kBlock) void k_sum(int n, const double* __restrict__ a,
+                                                double* part) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {t < n ? a[t] : 0.0};
+    block_partial<1>(v, part);
+}
+
+// b^ = b - mean(b): into bh (input order, FP64, may be null) and into r
+// (tree order, type T); x = p0 = p1 = 0; partial ||b^||^2.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_init(int n, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ bh, T* __restrict__ r,
+                                                 T* __restrict__ x, T* __restrict__ p0,
+                                                 T* __restrict__ p1, const Scal* S,
+                                                 double* part) {
+    const double mean = S->bsum / (double)n;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (t < n) {
+        const double bt = b[t] - mean;
+        if (bh) bh[t] = bt;
+        r[t] = (T)(b[perm[t]] - mean);
+        x[t] = T(0);
+        p0[t] = T(0);
+        p1[t] = T(0);
+        v[0] = bt * bt;
+    }
+    block_partial<1>(v, part);
+}
+
+// Outer loop of mixed precision: bh = b - mean(b); x = 0; r = bh (input
+// order, FP64); partial ||bh||^2.
+__global__ __launch_bounds__(kBlock) void k_init_outer(int n, const double* __restrict__ b,
+                                                       double* __restrict__ bh,
+                                                       double* __restrict__ x,
+                                                       double* __restrict__ r, const Scal* S,
+                                                       double* part) {
+    const double mean = S->bsum / (double)n;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double v[1] = {0.0};
+    if (t < n) {
+        const double bt = b[t] - mean;
+        bh[t] = bt;
+        x[t] = 0.0;
+        r[t] = bt;
+        v[0] = bt * bt;
+    }
+    block_partial<1>(v, part);
+}
+
+// x += d (FP64 += FP32 correction, input order).
+__global__ __launch_bounds__(kBlock) void k_add_corr(int n, double* __restrict__ x,
+                                                     const float* __restrict__ d) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) x[t] += (double)d[t];
+}
+
+// xc = x - mean(x) and the caller's copy of it (input order).
+__global__ __launch_bounds__(kBlock) void k_center_out(int n, const double* __restrict__ x,
+                                                       double* __restrict__ xc,
+                                                       double* __restrict__ dst, const Scal* S) {
+    const double mean = S->xsum / (double)n;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) {
+        const double v = x[t] - mean;
+        xc[t] = v;
+        dst[t] = v;
+    }
+}
+
+// dst[t] = src[perm[t]] (input order -> tree order).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_gather(int n, const int32_t* __restrict__ perm,
+                                                   const double* __restrict__ src,
+                                                   T* __restrict__ dst) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) dst[t] = (T)src[perm[t]];
+}
+
+// dst = src - zbar (input order).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_shift_out(int n, const T* __restrict__ src,
+                                                      double* __restrict__ dst, const Scal* S) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) dst[t] = (double)src[t] - S->zbar;
+}
+
+}  // namespace lapgpu

@@ -9,6 +9,8 @@
 
 #include <cstdint>
 
+#include "setup.hpp"
+
 namespace lapgpu {
 
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
@@ -39,34 +41,41 @@ struct Scal {
     int32_t first;  // next preconditioner result starts a new direction (beta = 0)
 };
 
-// Level table entry (device copy of per-level pointers).
+// Level table entry (device copy of per-level pointers).  T is the value
+// type of the vectors and coefficients (double, or float for the inner
+// solve of mixed precision).
+template <class T>
 struct LevelDev {
     int32_t n;          // nodes on this level
     int32_t nc;         // aggregates formed from it (nodes on the next level)
-    double* r;          // restricted residual (levels >= 1)
-    double* y;          // correction (levels >= 1)
+    T* r;               // restricted residual (levels >= 1)
+    T* y;               // correction (levels >= 1)
     const int32_t* cptr;// children range of each aggregate
-    const double* saa;  // theta * inverse 2x2 Schur complement of the pair
-    const double* sab;
-    const double* sbb;
-    const double* l0;   // leftover t: theta / D_tt
-    const double* l1;   //             w(t, a) / D_tt
-    const double* l2;   //             w(t, b) / D_tt
-    double* ea;         // eta of the pair member a (theta-scaled)
-    double* eb;
+    const T* saa;       // theta * inverse 2x2 Schur complement of the pair
+    const T* sab;
+    const T* sbb;
+    const T* l0;        // leftover t: theta / D_tt
+    const T* l1;        //             w(t, a) / D_tt
+    const T* l2;        //             w(t, b) / D_tt
+    T* ea;              // eta of the pair member a (theta-scaled)
+    T* eb;
     const int32_t* bst; // block partition: block b owns aggregates [bst[b], bst[b+1])
     int32_t nb;         // blocks of the partition
 };
 
-// Layout of the coarse tail in LDS (offsets in doubles from the start of the
-// dynamic shared buffer).  The read-only part [0, pack) is a byte copy of a
-// device buffer built by the host; the rest is work space.
+// Layout of the coarse tail in LDS (offsets in values of the solve's type
+// from the start of the dynamic shared buffer).  The read-only part
+// [0, pack) is a byte copy of a device buffer built by the host; the rest is
+// work space.
 struct TailStep {
     int32_t nk, nc, nl;                // children, aggregates, leftovers
-    int32_t cptr;                      // int32[nc+1], stored in double slots
+    int32_t cptr;                      // int32[nc+1], stored in value slots
     int32_t saa, sab, sbb, l0, l1, l2; // coefficients
     int32_t ea, eb;                    // work: pair corrections
+    int32_t nbig, big;                 // aggregates with > kTailBig children:
+                                       // count, int32 list in value slots
 };
+constexpr int kTailBig = 64;
 constexpr int kMaxTailSteps = 62;
 struct TailDesc {
     int32_t nsteps;                    // levels kt .. top-1
@@ -88,24 +97,26 @@ struct TailDesc {
 // the down-sweep's carve.
 constexpr int kGrpThreads = 256;
 constexpr int kMaxGroupLevels = 12;
+template <class T>
 struct GroupDev {
     int32_t k0, k1, nblocks;
     const int32_t* D;        // (m+1) rows of nblocks+1 entries
     const int32_t* uoff;     // up pack offset of each block (nblocks+1)
     const int32_t* doff;     // down pack offset of each block
     const int32_t* xoff;     // scratch offset of each block
-    const double* upack;     // per level: cp (local), pair coefficients, l1, l2
-    const double* dpack;     // per level: cp (local), l0, l1, l2
-    double* scr;             // per level: r (levels 1..m-1), then eta a, eta b
-    double* r_top;           // level k1 residual (output of the up-sweep)
-    const double* y_top;     // level k1 correction (input of the down-sweep)
-    const double* r_in;      // level k0 residual (input)
-    double* y_out;           // level k0 correction (output)
+    const T* upack;          // per level: cp (local), pair coefficients, l1, l2
+    const T* dpack;          // per level: cp (local), l0, l1, l2
+    T* scr;                  // per level: r (levels 1..m-1), then eta a, eta b
+    T* r_top;                // level k1 residual (output of the up-sweep)
+    const T* y_top;          // level k1 correction (input of the down-sweep)
+    const T* r_in;           // level k0 residual (input)
+    T* y_out;                // level k0 correction (output)
 };
 
-// Offsets (doubles) inside one block's up pack, down pack, scratch chunk
-// and LDS carves, from the block's per-level counts.  Shared by host and
-// device so the layouts agree exactly.
+// Offsets (in values) inside one block's up pack, down pack, scratch chunk
+// and LDS carves, from the block's per-level counts; `ipv` int32 children
+// offsets fit one value slot (2 for double, 1 for float).  Shared by host
+// and device so the layouts agree exactly.
 struct GrpLayout {
     int32_t ucp[kMaxGroupLevels], us[kMaxGroupLevels], ul[kMaxGroupLevels], ulen;
     int32_t dcp[kMaxGroupLevels], dl[kMaxGroupLevels], dlen;
@@ -114,14 +125,15 @@ struct GrpLayout {
     int32_t dx, dr0, dy[kMaxGroupLevels + 1], dtotal;        // down LDS: dpack | scr | r_0 | y_0..y_m
 };
 
-__host__ __device__ inline void grp_layout(int m, const int32_t* cnt, GrpLayout& L) {
+__host__ __device__ inline void grp_layout(int m, const int32_t* cnt, int ipv, GrpLayout& L) {
     int32_t u = 0, d = 0, x = 0;
     for (int j = 0; j < m; ++j) {
         const int32_t na = cnt[j + 1], nl = cnt[j] - 2 * cnt[j + 1];
-        L.ucp[j] = u; u += (na + 2) / 2;
+        const int32_t cps = (na + 1 + ipv - 1) / ipv;
+        L.ucp[j] = u; u += cps;
         L.us[j] = u;  u += 3 * na;
         L.ul[j] = u;  u += 2 * nl;
-        L.dcp[j] = d; d += (na + 2) / 2;
+        L.dcp[j] = d; d += cps;
         L.dl[j] = d;  d += 3 * nl;
         L.xr[j] = x;  if (j >= 1) x += cnt[j];
         L.xe[j] = x;  x += 2 * na;
@@ -139,11 +151,28 @@ __host__ __device__ inline void grp_layout(int m, const int32_t* cnt, GrpLayout&
     L.dtotal = o;
 }
 
+// Fine Laplacian for the SpMV.  Light rows: sliced ELL, 64 rows per slice
+// (one wavefront), slot k of a slice's rows stored contiguously; slice s
+// holds the rows row[s*64 .. s*64+63] (row == nullptr: the identity, slot =
+// row), width[s] slots each, padding pointing at the row itself with w = 0.
+// Heavy rows (degree above kHeavyDeg) are left out of the slices and stored
+// as CSR; heavy block b handles the heavy rows [hblk[b], hblk[b+1]): one
+// wavefront per row, or the whole block for a single row of degree above
+// kHeavyBlockDeg.
+template <class T>
 struct Sell {
-    const int32_t* off;
-    const int32_t* width;
+    int32_t nlight;          // rows in the slices
+    int32_t nheavyblk;       // heavy blocks
+    const int32_t* off;      // slice -> first slot
+    const int32_t* width;    // slice -> slots per row
     const int32_t* col;
-    const double* w;
+    const T* w;
+    const int32_t* row;      // slot -> row (nullptr: identity)
+    const int32_t* hblk;     // heavy block -> first heavy row (nheavyblk+1)
+    const int32_t* hrow;     // heavy row -> row
+    const int32_t* hptr;     // heavy row -> first entry
+    const int32_t* hcol;
+    const T* hw;
 };
 
 }  // namespace lapgpu

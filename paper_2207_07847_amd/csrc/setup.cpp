@@ -378,37 +378,91 @@ int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
         for (double& x : plan.top_pinv) x *= plan.theta[T];
     }
 
-    // 4. fine Laplacian in the graph's own vertex order, sliced ELL: the
-    //    SpMV gathers neighbours, and for meshes and grids the input order
-    //    keeps those gathers contiguous across a wavefront.
-    const Adjacency& g0 = plan.lv[0].g;
-    const int64_t nslice = (n + kSlice - 1) / kSlice;
+    // 4. fine Laplacian for the SpMV
+    build_sell(plan.lv[0].g, plan);
+    return kOk;
+}
+
+// Sliced ELL in the graph's own vertex order: for meshes and grids that
+// order keeps the neighbour gathers of a wavefront within a few cache
+// lines.  Rows of degree above kHeavyDeg go to a CSR part processed a row
+// per wavefront (or per block).  When slices of consecutive rows would be
+// padded by more than 15 %, rows are sorted by degree within windows of
+// kSigma rows first (sliced ELL with sorting windows), so a slice's rows
+// have similar degrees.
+void build_sell(const Adjacency& g, HostPlan& plan) {
+    const int64_t n = g.n;
+    auto deg = [&](int64_t i) { return g.ptr[i + 1] - g.ptr[i]; };
+    std::vector<int32_t> light, heavy;
+    for (int64_t i = 0; i < n; ++i) (deg(i) > kHeavyDeg ? heavy : light).push_back((int32_t)i);
+    const int64_t nl = (int64_t)light.size();
+    int64_t nnz_l = 0, pad_id = 0;
+    for (int64_t s = 0; s * kSlice < nl; ++s) {
+        int64_t wmax = 0;
+        for (int64_t t = s * kSlice; t < std::min<int64_t>(nl, (s + 1) * kSlice); ++t) {
+            wmax = std::max<int64_t>(wmax, deg(light[t]));
+            nnz_l += deg(light[t]);
+        }
+        pad_id += wmax * kSlice;
+    }
+    const bool sorted = pad_id * 100 > nnz_l * 115;
+    if (sorted)
+        for (int64_t w0 = 0; w0 < nl; w0 += kSigma) {
+            const auto b = light.begin() + w0, e = light.begin() + std::min<int64_t>(nl, w0 + kSigma);
+            std::stable_sort(b, e, [&](int32_t x, int32_t y) { return deg(x) > deg(y); });
+        }
+    const int64_t nslice = (nl + kSlice - 1) / kSlice;
+    plan.sell_nlight = (int32_t)nl;
     plan.sell_off.assign(nslice + 1, 0);
     plan.sell_width.assign(nslice, 0);
     for (int64_t s = 0; s < nslice; ++s) {
         int64_t wmax = 0;
-        for (int64_t t = s * kSlice; t < std::min<int64_t>(n, (s + 1) * kSlice); ++t)
-            wmax = std::max<int64_t>(wmax, g0.ptr[t + 1] - g0.ptr[t]);
+        for (int64_t t = s * kSlice; t < std::min<int64_t>(nl, (s + 1) * kSlice); ++t)
+            wmax = std::max<int64_t>(wmax, deg(light[t]));
         plan.sell_width[s] = (int32_t)wmax;
         plan.sell_off[s + 1] = plan.sell_off[s] + (int32_t)(wmax * kSlice);
     }
     plan.sell_col.assign(plan.sell_off[nslice], 0);
     plan.sell_w.assign(plan.sell_off[nslice], 0.0);
-    for (int64_t t = 0; t < n; ++t) {
-        const int64_t s = t / kSlice, lane = t % kSlice;
-        const int64_t deg = g0.ptr[t + 1] - g0.ptr[t];
+    for (int64_t t = 0; t < nl; ++t) {
+        const int64_t s = t / kSlice, lane = t % kSlice, r = light[t];
         for (int64_t k = 0; k < plan.sell_width[s]; ++k) {
             const int64_t slot = plan.sell_off[s] + k * kSlice + lane;
-            if (k < deg) {
-                plan.sell_col[slot] = g0.col[g0.ptr[t] + k];
-                plan.sell_w[slot] = g0.w[g0.ptr[t] + k];
+            if (k < deg(r)) {
+                plan.sell_col[slot] = g.col[g.ptr[r] + k];
+                plan.sell_w[slot] = g.w[g.ptr[r] + k];
             } else {
-                plan.sell_col[slot] = (int32_t)t;   // padding: w = 0 on the row itself
+                plan.sell_col[slot] = (int32_t)r;   // padding: w = 0 on the row itself
                 plan.sell_w[slot] = 0.0;
             }
         }
     }
-    return kOk;
+    plan.sell_row.clear();
+    if (sorted || !heavy.empty()) plan.sell_row = light;
+    // heavy rows: CSR, grouped into blocks
+    plan.heavy_row = heavy;
+    plan.heavy_ptr.assign(heavy.size() + 1, 0);
+    plan.heavy_col.clear();
+    plan.heavy_w.clear();
+    plan.heavy_blk.assign(1, 0);
+    int32_t in_blk = 0;
+    for (size_t h = 0; h < heavy.size(); ++h) {
+        const int64_t r = heavy[h];
+        for (int64_t q = g.ptr[r]; q < g.ptr[r + 1]; ++q) {
+            plan.heavy_col.push_back(g.col[q]);
+            plan.heavy_w.push_back(g.w[q]);
+        }
+        plan.heavy_ptr[h + 1] = (int32_t)plan.heavy_col.size();
+        if (deg(r) > kHeavyBlockDeg) {
+            if (in_blk > 0) plan.heavy_blk.push_back((int32_t)h);
+            plan.heavy_blk.push_back((int32_t)h + 1);
+            in_blk = 0;
+        } else if (++in_blk == kHeavyWaves) {
+            plan.heavy_blk.push_back((int32_t)h + 1);
+            in_blk = 0;
+        }
+    }
+    if (in_blk > 0) plan.heavy_blk.push_back((int32_t)heavy.size());
 }
 
 }  // namespace lapgpu

@@ -23,6 +23,10 @@ enum Status { kOk = 0, kInval = 1, kDisconnected = 2, kNoMem = 3, kDevice = 4,
 
 constexpr int kSlice = 64;        // rows per sliced-ELL slice (one wave)
 constexpr int kTopMax = 64;       // largest top level solved on chip
+constexpr int kHeavyDeg = 128;    // rows of higher degree leave the slices
+constexpr int kHeavyBlockDeg = 4096;  // ... and above this get a block alone
+constexpr int kSigma = 512;       // rows sorted by degree within windows of this
+constexpr int kHeavyWaves = 4;    // heavy rows per heavy block (one per wave)
 
 // Symmetric weighted adjacency, neighbours ascending, no diagonal.
 struct Adjacency {
@@ -54,12 +58,19 @@ struct HostPlan {
     std::vector<StepCoef> step;              // nlev-1 entries
     std::vector<double> theta;               // theta_k, k = 0..nlev-1
     std::vector<double> top_pinv;            // theta_top * pinv(L_top), row-major
-    // fine Laplacian, input vertex order, sliced ELL (64 rows per slice,
-    // column-major)
+    // fine Laplacian, input vertex order: light rows in sliced ELL (64 rows
+    // per slice, column-major), heavy rows in CSR
+    int32_t sell_nlight = 0;
     std::vector<int32_t> sell_off;           // slice -> first slot
     std::vector<int32_t> sell_width;         // slice -> slots per row
     std::vector<int32_t> sell_col;
     std::vector<double> sell_w;
+    std::vector<int32_t> sell_row;           // slot -> row; empty: identity
+    std::vector<int32_t> heavy_blk;          // heavy block -> first heavy row
+    std::vector<int32_t> heavy_row;          // heavy row -> row
+    std::vector<int32_t> heavy_ptr;
+    std::vector<int32_t> heavy_col;
+    std::vector<double> heavy_w;
     int nlev() const { return (int)lv.size(); }
 };
 
@@ -75,5 +86,7 @@ void coarse_graph(const Adjacency& f, const std::vector<int64_t>& agg, int64_t n
 int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                const double* w, double mu, int max_levels, int64_t n_top,
                uint64_t seed, bool host_only, HostPlan& plan);
+// The SpMV layout of the fine Laplacian (part of build_plan).
+void build_sell(const Adjacency& g, HostPlan& plan);
 
 }  // namespace lapgpu

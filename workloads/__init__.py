@@ -153,6 +153,21 @@ def chung_lu(n, mean_degree=16.0, gamma=2.1, seed=0):
     return largest_component(n2, u2, v2)
 
 
+def hub_graph(n_base, hub_links, pendants, seed=0):
+    """A Chung-Lu graph on n_base ids plus one hub vertex linked to
+    `hub_links` random base vertices and to `pendants` new degree-1
+    vertices: a row far above any slice width, and an aggregate with
+    thousands of children (the pendants can only join the hub)."""
+    rng = np.random.default_rng(seed)
+    n0, u0, v0 = chung_lu(n_base, 8.0, 2.1, seed)
+    hub = n0
+    links = rng.choice(n0, size=min(hub_links, n0), replace=False)
+    pend = np.arange(n0 + 1, n0 + 1 + pendants)
+    u = np.concatenate([u0, np.full(len(links), hub), np.full(pendants, hub)])
+    v = np.concatenate([v0, links, pend])
+    return _canon(n0 + 1 + pendants, u, v)
+
+
 def rmat(scale, edge_factor=16, abcd=(0.57, 0.19, 0.19, 0.05), seed=0):
     """R-MAT graph on 2^scale ids with edge_factor*2^scale samples."""
     rng = np.random.default_rng(seed)
