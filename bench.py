@@ -33,11 +33,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+WORKLOADS = {
+    "grid3d_128": "grid3d_128^3 7-point, w=10^U(-3,3), MSP mu=0.8 level=max, 1 Gaussian RHS, tol 1e-8",
+    "chunglu_4m": "Chung-Lu 4M ids (LCC), mean degree 16, gamma 2.1, w=U(0,1], MSP mu=0.8 "
+                  "level=max, 1 Gaussian RHS, tol 1e-8",
+    "rmat_20": "R-MAT scale 20 (LCC), (0.57,0.19,0.19,0.05), 16 samples/id, w=U(0,1], MSP mu=0.8 "
+               "level=max, 1 Gaussian RHS, tol 1e-8",
+}
+
+
 def workload(name, scale):
     import workloads as W
-    if name != "grid3d_128":
+    if name not in WORKLOADS:
         raise SystemExit(f"unknown workload {name}")
-    n, u, v, w = W.config_graph("grid3d_128", scale)
+    n, u, v, w = W.config_graph(name, scale)
     b = W.gaussian_rhs(n, W.MASTER_SEED + 3)
     return dict(n=n, u=u, v=v, w=w, b=b, mu=0.8, tol=1e-8)
 
@@ -96,12 +105,49 @@ def cpu_baseline(wl, gpu_iters, budget_s):
     }
 
 
+def measure(lap, h, bd, xd, n, tol, steps, warmup, sh, stream, capped):
+    """Warm-up solves, then `steps` timed solves; per-solve latency from
+    HIP events on the solve stream."""
+    import torch
+
+    def one():
+        st, inf = lap.lap_solve(h, bd.data_ptr(), xd.data_ptr(), n, tol, stream=sh)
+        if st == lap.LAP_ENOCONV and capped:
+            return inf[0]
+        if st != 0:
+            raise SystemExit(f"solve failed: {lap.lap_status_str(st)} {inf}")
+        return inf[0]
+
+    for i in range(warmup):
+        inf = one()
+        log(f"warmup {i}: {inf['iterations']} it, {inf['refinements']} ref, "
+            f"relres {inf['relres_true']:.3e}, {inf['seconds']:.3f}s")
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        inf = one()
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+        log(f"step {i}: {inf['iterations']} it, {inf['refinements']} ref, "
+            f"relres {inf['relres_true']:.3e}, {lat[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    return dict(elapsed=elapsed, lat=lat, info=inf)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid3d_128")
+    ap.add_argument("--workload", default="grid3d_128", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"],
+                    help="both: mixed precision timed, plain FP64 timed beside it")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -122,47 +168,32 @@ def main():
     import paper_2207_07847_amd as lap
 
     torch.cuda.set_device(0)
+    t0 = time.time()
     wl = workload(args.workload, args.scale)
+    log(f"workload {args.workload}: n={wl['n']} edges={len(wl['u'])} ({time.time() - t0:.1f}s)")
     n = wl["n"]
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
+    prec = lap.LAP_FP64 if args.precision == "fp64" else lap.LAP_MIXED_FP32_FP64
     t0 = time.time()
     h = lap.lap_setup(n, wl["u"], wl["v"], wl["w"],
-                      lap.lap_default_params(mu=wl["mu"], max_iter=args.max_iter), sh)
+                      lap.lap_default_params(mu=wl["mu"], max_iter=args.max_iter,
+                                             precision=prec), sh)
     setup_s = time.time() - t0
     info = lap.lap_hierarchy_info(h)
     log(f"setup {setup_s:.2f}s levels={info['nlev']} tail={info['tail_level']} "
         f"sizes={info['sizes'][:4]}...{info['sizes'][-2:]}")
     bd = torch.tensor(wl["b"], dtype=torch.float64, device="cuda")
     xd = torch.empty_like(bd)
-
-    def one():
-        st, inf = lap.lap_solve(h, bd.data_ptr(), xd.data_ptr(), n, wl["tol"], stream=sh)
-        if st == lap.LAP_ENOCONV and args.max_iter < 200000:
-            return inf[0]
-        if st != 0:
-            raise SystemExit(f"solve failed: {lap.lap_status_str(st)} {inf}")
-        return inf[0]
-
-    for i in range(args.warmup):
-        inf = one()
-        log(f"warmup {i}: {inf['iterations']} it, relres {inf['relres_true']:.3e}, "
-            f"{inf['seconds']:.3f}s")
-    lat = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        inf = one()
-        e1.record(stream)
-        e1.synchronize()
-        lat.append(e0.elapsed_time(e1))
-        log(f"step {i}: {inf['iterations']} it, relres {inf['relres_true']:.3e}, {lat[-1]:.1f} ms")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    iters = inf["iterations"]
+    capped = args.max_iter < 200000
+    base = None
+    if args.precision == "both":
+        lap.lap_set_precision(h, lap.LAP_FP64)
+        log("plain FP64 beside it:")
+        base = measure(lap, h, bd, xd, n, wl["tol"], args.steps, args.warmup, sh, stream, capped)
+        lap.lap_set_precision(h, lap.LAP_MIXED_FP32_FP64)
+    res = measure(lap, h, bd, xd, n, wl["tol"], args.steps, args.warmup, sh, stream, capped)
+    inf = res["info"]
 
     if args.calib_copy_mb:
         src = torch.ones(args.calib_copy_mb * 131072, dtype=torch.float64, device="cuda")
@@ -172,7 +203,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # kernels timed inside iterations on the solve stream
+    # kernels timed inside iterations on the solve stream (the engine the
+    # timed solves used: FP32 for mixed precision)
     kern = {}
     for kid, name in [(lap.LAP_KERNEL_SPMV, "spmv_p"), (lap.LAP_KERNEL_UPDATE, "update_up0"),
                       (lap.LAP_KERNEL_DOWN0, "down0"),
@@ -184,27 +216,32 @@ def main():
     lap.lap_free(h)
 
     spmv = kern["spmv_p"]
+    steps = args.steps
+    dtype = "f64" if args.precision == "fp64" else "f32+f64"
     line = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": steps / res["elapsed"],
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": res["elapsed"] / steps * 1e3,
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {
-            "workload": f"grid3d_{round(128 * args.scale)}^3 7-point, w=10^U(-3,3), "
-                        f"MSP mu=0.8 level=max, FP64, 1 Gaussian RHS, tol 1e-8",
+            "workload": WORKLOADS[args.workload].replace("^3", f"^3 (scale {args.scale})")
+            if args.scale != 1.0 else WORKLOADS[args.workload],
+            "precision": "FP64" if args.precision == "fp64" else
+                         "FP32 SpMV/preconditioner inside FP64 iterative refinement",
             "n": n, "edges": int(len(wl["u"])), "levels": info["nlev"],
-            "iterations": iters, "relres_true": inf["relres_true"],
+            "iterations": inf["iterations"], "refinements": inf["refinements"],
+            "relres_true": inf["relres_true"],
         },
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
+        "p50_ms": float(np.percentile(res["lat"], 50)),
+        "p99_ms": float(np.percentile(res["lat"], 99)),
         "spmv_gbs": spmv["gbs"],
         "iteration_us": kern["iteration"]["avg_us"],
         "kernels": kern,
@@ -216,12 +253,22 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": spmv["gbs"] / HBM_PEAK_GBS,
-            "traffic": pmc_traffic(args.workload, args.scale),
+            "traffic": pmc_traffic(args.workload, args.scale) if args.precision == "fp64" else None,
         },
     }
+    if base is not None:
+        bi = base["info"]
+        line["fp64_same_gpu"] = {
+            "value": steps / base["elapsed"], "unit": "solves/s",
+            "ms_per_step": base["elapsed"] / steps * 1e3,
+            "iterations": bi["iterations"], "relres_true": bi["relres_true"],
+            "p50_ms": float(np.percentile(base["lat"], 50)),
+        }
+        line["speedup_vs_fp64"] = base["elapsed"] / res["elapsed"]
     if not args.no_cpu:
-        log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(wl, iters, args.cpu_seconds)
+        if args.workload == "grid3d_128" and args.scale == 1.0:
+            log("cpu baseline (oracle) ...")
+            line["cpu_baseline"] = cpu_baseline(wl, inf["iterations"], args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -134,10 +134,26 @@ lap_status lap_setup(const lap_graph *g, const lap_params *p, void *stream,
  * Stops when ||r_k|| <= tol ||b^||.  info: host array of nrhs entries (may
  * be NULL).  Returns the worst per-column status: LAP_ENOCONV when
  * max_iter is reached, LAP_EBREAKDOWN, LAP_EINVAL (tol <= 0, nrhs < 1,
- * ld < n, non-finite b), LAP_EDEVICE. */
+ * ld < n, non-finite b), LAP_EDEVICE.
+ *
+ * Mixed precision (LAP_MIXED_FP32_FP64): x and r = b^ - L x are kept in
+ * FP64; each refinement solves L d = r by PCG with FP32 vectors, FP32 SpMV
+ * and FP32 preconditioner (inner products and the mean projection summed in
+ * FP64) to a relative residual of max(1e-4, tol ||b^|| / (2 ||r||)), then
+ * x += d and r is recomputed in FP64.  The stop test is on that FP64 r;
+ * info->iterations counts inner iterations over all refinements,
+ * info->refinements the refinements, info->relres_true the final FP64
+ * ||b^ - L x|| / ||b^||. */
 lap_status lap_solve(lap_hierarchy *h, const double *b, double *x,
                      int32_t nrhs, int64_t ld, double tol,
                      lap_solve_info *info, void *stream);
+
+/* Precision of later lap_solve calls on h.  A hierarchy set up with
+ * LAP_MIXED_FP32_FP64 holds both the FP32 and the FP64 solve and may switch
+ * either way; one set up with LAP_FP64 only supports LAP_FP64.  Errors:
+ * LAP_EINVAL (NULL, unknown precision), LAP_EUNSUPPORTED (FP32 solve not
+ * built, or host-only). */
+lap_status lap_set_precision(lap_hierarchy *h, int32_t precision);
 
 /* y = L_G x on the device (original order).  Errors: LAP_EINVAL,
  * LAP_EDEVICE, LAP_EUNSUPPORTED for a host-only hierarchy. */

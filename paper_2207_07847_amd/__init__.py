@@ -67,6 +67,7 @@ def _load():
     L.lap_setup.argtypes = [C.POINTER(lap_graph), C.POINTER(lap_params), vp, C.POINTER(vp)]
     L.lap_solve.argtypes = [vp, vp, vp, C.c_int32, C.c_int64, C.c_double,
                             C.POINTER(lap_solve_info), vp]
+    L.lap_set_precision.argtypes = [vp, C.c_int32]
     L.lap_apply_laplacian.argtypes = [vp, vp, vp, vp]
     L.lap_apply_precond.argtypes = [vp, vp, vp, vp]
     L.lap_hierarchy_info.argtypes = [vp, C.POINTER(lap_hierarchy_desc)]
@@ -80,7 +81,8 @@ def _load():
     L.lap_last_error.restype = C.c_char_p
     L.lap_status_str.argtypes = [C.c_int]
     L.lap_status_str.restype = C.c_char_p
-    for f in ("lap_default_params", "lap_setup", "lap_solve", "lap_apply_laplacian",
+    for f in ("lap_default_params", "lap_setup", "lap_solve", "lap_set_precision",
+              "lap_apply_laplacian",
               "lap_apply_precond", "lap_hierarchy_info", "lap_export_level", "lap_export_graph",
               "lap_profile_kernel"):
         getattr(L, f).restype = C.c_int
@@ -139,6 +141,10 @@ def lap_solve(h, b_ptr: int, x_ptr: int, n: int, tol: float, nrhs: int = 1, ld: 
                 relres_recursive=i.relres_recursive, seconds=i.seconds, status=i.status)
            for i in info]
     return st, out
+
+
+def lap_set_precision(h, precision: int) -> int:
+    return _lib.lap_set_precision(C.c_void_p(h), int(precision))
 
 
 def lap_apply_laplacian(h, x_ptr: int, y_ptr: int, stream=0) -> int:

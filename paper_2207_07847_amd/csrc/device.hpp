@@ -171,10 +171,20 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
 // b mod 8).  The streaming kernels renumber their blocks so that every XCD
 // owns one contiguous range of the work: neighbouring rows and aggregates,
 // and the vertices their values are gathered from, then share one L2.
-__device__ inline int xcd_block() {
-    const int b = blockIdx.x, G = gridDim.x;
+__device__ inline int xcd_map(int b, int G) {
     const int x = b & 7, q = G >> 3, rem = G & 7;
     return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+__device__ inline int xcd_block() { return xcd_map(blockIdx.x, gridDim.x); }
+
+// SpMV grids: the heavy-row blocks come first, in dispatch order over all
+// XCDs (they are the longest); the sliced rows follow, renumbered so every
+// XCD owns one contiguous range of slices.  Returns the slice block, or -1
+// - (heavy block) for a heavy block.
+__device__ inline int spmv_block(int nhb) {
+    const int b = blockIdx.x;
+    if (b < nhb) return -1 - b;
+    return xcd_map(b - nhb, gridDim.x - nhb);
 }
 
 // -------------------------------------------------------- Laplacian rows
@@ -232,10 +242,10 @@ __device__ inline void heavy_block(const Sell<T>& A, int hb, Mk mk, Fin fin) {
 
 // ------------------------------------------------------ fine-level kernels
 
-// Input order: p = zn - zbar + beta p_old; q = L p; partial p^T q.  The
+// Solve order: p = zn - zbar + beta p_old; q = L p; partial p^T q.  The
 // neighbours' p are formed on the fly from zn and p_old, as differences
-// (z_i - z_j) + beta (p_i - p_j) in which zbar cancels.  Blocks [0, nlb)
-// take the sliced rows, the rest the heavy rows.
+// (z_i - z_j) + beta (p_i - p_j) in which zbar cancels (nlb: slice blocks;
+// the grid holds those and the heavy blocks, see spmv_block).
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* __restrict__ zn,
                                                    const T* __restrict__ pold,
@@ -243,9 +253,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* 
                                                    Scal* S, double* part) {
     if (S->done) return;
     const T beta = (T)S->beta, zbar = (T)S->zbar;
-    const int lb = xcd_block();
+    const int lb = spmv_block(A.nheavyblk);
     double v[1] = {0.0};
-    if (lb < nlb) {
+    if (lb >= 0) {
         const int slot = lb * kBlock + threadIdx.x;
         if (slot < A.nlight) {
             const int row = A.row ? A.row[slot] : slot;
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* 
         }
     } else {
         heavy_block(
-            A, lb - nlb,
+            A, -1 - lb,
             [&](int row) {
                 const T zi = zn[row], poi = pold[row];
                 return [=](int j) { return (zi - zn[j]) + beta * (poi - pold[j]); };
@@ -275,12 +285,55 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* 
     block_partial<1>(v, part);
 }
 
-// y = L x (input order, FP64).
+// p = zn - zbar + beta p_old (solve order), for the SpMV below.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_pupd(int n, const T* __restrict__ zn,
+                                                 const T* __restrict__ pold, T* __restrict__ pnew,
+                                                 const Scal* S) {
+    if (S->done) return;
+    const T beta = (T)S->beta, zbar = (T)S->zbar;
+    const int t = xcd_block() * kBlock + threadIdx.x;
+    if (t < n) pnew[t] = (zn[t] - zbar) + beta * pold[t];
+}
+
+// q = L p with p already formed (one gathered vector per neighbour instead
+// of two: the choice for graphs whose gathers are scattered); partial p^T q.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_spmv_q(int nlb, Sell<T> A, const T* __restrict__ p,
+                                                   T* __restrict__ q, Scal* S, double* part) {
+    if (S->done) return;
+    const int lb = spmv_block(A.nheavyblk);
+    double v[1] = {0.0};
+    if (lb >= 0) {
+        const int slot = lb * kBlock + threadIdx.x;
+        if (slot < A.nlight) {
+            const int row = A.row ? A.row[slot] : slot;
+            const T pi = p[row];
+            const T acc = light_row(A, slot, [&](int j) { return pi - p[j]; });
+            q[row] = acc;
+            v[0] = (double)pi * (double)acc;
+        }
+    } else {
+        heavy_block(
+            A, -1 - lb,
+            [&](int row) {
+                const T pi = p[row];
+                return [=](int j) { return pi - p[j]; };
+            },
+            [&](int row, T acc) {
+                q[row] = acc;
+                v[0] = (double)p[row] * (double)acc;
+            });
+    }
+    block_partial<1>(v, part);
+}
+
+// y = L x (solve order, FP64).
 __global__ __launch_bounds__(kBlock) void k_spmv_plain(int nlb, Sell<double> A,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ y) {
-    const int lb = xcd_block();
-    if (lb < nlb) {
+    const int lb = spmv_block(A.nheavyblk);
+    if (lb >= 0) {
         const int slot = lb * kBlock + threadIdx.x;
         if (slot >= A.nlight) return;
         const int row = A.row ? A.row[slot] : slot;
@@ -288,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_plain(int nlb, Sell<double> A,
         y[row] = light_row(A, slot, [&](int j) { return xi - x[j]; });
     } else {
         heavy_block(
-            A, lb - nlb,
+            A, -1 - lb,
             [&](int row) {
                 const double xi = x[row];
                 return [=](int j) { return xi - x[j]; };
@@ -297,14 +350,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_plain(int nlb, Sell<double> A,
     }
 }
 
-// r = bh - L x (input order, FP64; r may be null); partial ||bh - L x||^2.
+// r = bh - L x (solve order, FP64; r may be null); partial ||bh - L x||^2.
 __global__ __launch_bounds__(kBlock) void k_resid(int nlb, Sell<double> A,
                                                   const double* __restrict__ x,
                                                   const double* __restrict__ bh,
                                                   double* __restrict__ r, double* part) {
-    const int lb = xcd_block();
+    const int lb = spmv_block(A.nheavyblk);
     double v[1] = {0.0};
-    if (lb < nlb) {
+    if (lb >= 0) {
         const int slot = lb * kBlock + threadIdx.x;
         if (slot < A.nlight) {
             const int row = A.row ? A.row[slot] : slot;
@@ -315,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(int nlb, Sell<double> A,
         }
     } else {
         heavy_block(
-            A, lb - nlb,
+            A, -1 - lb,
             [&](int row) {
                 const double xi = x[row];
                 return [=](int j) { return xi - x[j]; };
@@ -351,6 +404,50 @@ __device__ inline void agg_up(const LevelDev<T>& s, const T* rs, int toff, T* __
     s.ea[J] = saa * ga + sab * gb;
     s.eb[J] = sab * ga + sbb * gb;
     rk1[J] = sum;
+}
+
+// Restriction and pair solve of aggregate J by one wavefront (aggregates
+// with more than kWaveAgg children): lanes stride over the leftovers, the
+// sums are reduced across the wavefront, lane 0 writes.
+template <class T>
+__device__ inline void agg_up_wave(const LevelDev<T>& s, const T* rs, int toff,
+                                   T* __restrict__ rk1, int J, int lane) {
+    const int b0 = s.cptr[J], b1 = s.cptr[J + 1];
+    T sum = T(0), ga = T(0), gb = T(0);
+    for (int t = b0 + 2 + lane; t < b1; t += 64) {
+        const int li = t - 2 * J - 2;
+        const T rv = rs[t - toff];
+        sum += rv;
+        ga += s.l1[li] * rv;
+        gb += s.l2[li] * rv;
+    }
+    sum = wave_sum1(sum);
+    ga = wave_sum1(ga);
+    gb = wave_sum1(gb);
+    if (lane == 0) {
+        const T ra = rs[b0 - toff], rb = rs[b0 + 1 - toff];
+        sum += ra + rb;
+        ga += ra;
+        gb += rb;
+        const T saa = s.saa[J], sab = s.sab[J], sbb = s.sbb[J];
+        s.ea[J] = saa * ga + sab * gb;
+        s.eb[J] = sab * ga + sbb * gb;
+        rk1[J] = sum;
+    }
+}
+
+// Per-aggregate part of a staged up-sweep block: small aggregates a thread
+// each, the large ones (listed in LDS) a wavefront each.
+template <class T>
+__device__ inline void up_aggregates(const LevelDev<T>& s, const T* rs, int t0, T* __restrict__ rk1,
+                                     int J0, int J1, int* nbig, int* big) {
+    for (int J = J0 + threadIdx.x; J < J1; J += kBlock) {
+        if (s.cptr[J + 1] - s.cptr[J] > kWaveAgg) big[atomicAdd(nbig, 1)] = J;
+        else agg_up(s, rs, t0, rk1, J);
+    }
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wid; i < *nbig; i += kBlock / 64) agg_up_wave(s, rs, t0, rk1, big[i], lane);
 }
 
 // Contributions of child t of aggregate J (first child b0) to the
@@ -435,25 +532,27 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev<T> s0,
     if (S->done) return;
     __shared__ T rs[kCapP];
     __shared__ double red[4 * (kBlock / 64)];
+    __shared__ int nbig, big[kAggPerBlock];
     const T alpha = (T)S->alpha;
     const int b = xcd_block();
     const int J0 = s0.bst[b], J1 = s0.bst[b + 1];
     const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
     double rr = 0.0;
     if (len <= kCapP) {
+        if (threadIdx.x == 0) nbig = 0;
         for (int i = threadIdx.x; i < len; i += kBlock) {
             const int t = t0 + i;
             T rt = r[t];
             if (do_update) {
                 x[t] += alpha * p[t];
-                rt -= alpha * q[perm[t]];
+                rt -= alpha * q[perm ? perm[t] : t];
                 r[t] = rt;
                 rr += (double)rt * rt;
             }
             rs[i] = rt;
         }
         __syncthreads();
-        for (int J = J0 + threadIdx.x; J < J1; J += kBlock) agg_up(s0, rs, t0, r1, J);
+        up_aggregates(s0, rs, t0, r1, J0, J1, &nbig, big);
         if (!do_update) return;
         double v[1] = {rr};
         block_partial<1>(v, part);
@@ -466,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev<T> s0,
         T rt = r[t];
         if (do_update) {
             x[t] += alpha * p[t];
-            rt -= alpha * q[perm[t]];
+            rt -= alpha * q[perm ? perm[t] : t];
             r[t] = rt;
             v[3] += (double)rt * rt;
         }
@@ -497,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_down0(LevelDev<T> s0, const int32_t*
             const int t = t0 + i, j = D.own[i];
             const T rt = r[t];
             const T zt = child_down(s0, J0 + j, D.b0[j], t, rt, D.yJ[j], D.ea[j], D.eb[j]);
-            zn[perm[t]] = zt;
+            zn[perm ? perm[t] : t] = zt;
             v[0] += zt;
             v[1] += (double)rt * zt;
             v[2] += rt;
@@ -508,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_down0(LevelDev<T> s0, const int32_t*
             const int t = t0 + i;
             const T rt = r[t];
             const T zt = child_down(s0, J0, t0, t, rt, yJ, ea, eb);
-            zn[perm[t]] = zt;
+            zn[perm ? perm[t] : t] = zt;
             v[0] += zt;
             v[1] += (double)rt * zt;
             v[2] += rt;
@@ -530,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_update_none(int n, const int32_t* __
     double v[1] = {0.0};
     if (t < n) {
         x[t] += alpha * p[t];
-        const T rt = r[t] - alpha * q[perm[t]];
+        const T rt = r[t] - alpha * q[perm ? perm[t] : t];
         r[t] = rt;
         v[0] = (double)rt * rt;
     }
@@ -548,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_prec_none(int n, const int32_t* __re
     if (t < n) {
         const T rt = r[t];
         z[t] = rt;
-        zn[perm[t]] = rt;
+        zn[perm ? perm[t] : t] = rt;
         v[0] = rt;
         v[1] = (double)rt * rt;
         v[2] = rt;
@@ -571,7 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_top_only(int n, const int32_t* __res
         T acc = T(0);
         for (int j = 0; j < n; ++j) acc += tp[i * n + j] * r[j];
         z[i] = acc;
-        zn[perm[i]] = acc;
+        zn[perm ? perm[i] : i] = acc;
         v[0] += acc;
         v[1] += (double)r[i] * acc;
         v[2] += r[i];
@@ -596,13 +695,15 @@ __global__ __launch_bounds__(kBlock) void k_up(LevelDev<T> s, const T* __restric
     if (S->done) return;
     __shared__ T rs[kCapP];
     __shared__ double red[3 * (kBlock / 64)];
+    __shared__ int nbig, big[kAggPerBlock];
     const int b = xcd_block();
     const int J0 = s.bst[b], J1 = s.bst[b + 1];
     const int t0 = s.cptr[J0], len = s.cptr[J1] - t0;
     if (len <= kCapP) {
+        if (threadIdx.x == 0) nbig = 0;
         for (int i = threadIdx.x; i < len; i += kBlock) rs[i] = rk[t0 + i];
         __syncthreads();
-        for (int J = J0 + threadIdx.x; J < J1; J += kBlock) agg_up(s, rs, t0, rk1, J);
+        up_aggregates(s, rs, t0, rk1, J0, J1, &nbig, big);
         return;
     }
     double v[3] = {0.0, 0.0, 0.0};
@@ -899,22 +1000,21 @@ __global__ __launch_bounds__(kBlock) void k_sum(int n, const double* __restrict_
     block_partial<1>(v, part);
 }
 
-// b^ = b - mean(b): into bh (input order, FP64, may be null) and into r
-// (tree order, type T); x = p0 = p1 = 0; partial ||b^||^2.
+// PCG start for the right-hand side rhs (solve order, FP64): r = rhs -
+// mean(rhs) in tree order (tree position t reads solve position perm[t],
+// perm null: the same position), x = p0 = p1 = 0; partial ||r||^2.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_init(int n, const int32_t* __restrict__ perm,
-                                                 const double* __restrict__ b,
-                                                 double* __restrict__ bh, T* __restrict__ r,
-                                                 T* __restrict__ x, T* __restrict__ p0,
-                                                 T* __restrict__ p1, const Scal* S,
-                                                 double* part) {
+                                                 const double* __restrict__ rhs,
+                                                 T* __restrict__ r, T* __restrict__ x,
+                                                 T* __restrict__ p0, T* __restrict__ p1,
+                                                 const Scal* S, double* part) {
     const double mean = S->bsum / (double)n;
     const int t = blockIdx.x * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (t < n) {
-        const double bt = b[t] - mean;
-        if (bh) bh[t] = bt;
-        r[t] = (T)(b[perm[t]] - mean);
+        const double bt = rhs[t] - mean;
+        r[t] = (T)(rhs[perm ? perm[t] : t] - mean);
         x[t] = T(0);
         p0[t] = T(0);
         p1[t] = T(0);
@@ -923,9 +1023,11 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, const int32_t* __restric
     block_partial<1>(v, part);
 }
 
-// Outer loop of mixed precision: bh = b - mean(b); x = 0; r = bh (input
-// order, FP64); partial ||bh||^2.
-__global__ __launch_bounds__(kBlock) void k_init_outer(int n, const double* __restrict__ b,
+// Solve start: bh = b - mean(b) in solve order (solve position s holds input
+// vertex sperm[s]; sperm null: the same); x = 0 and r = bh when given;
+// partial ||bh||^2.
+__global__ __launch_bounds__(kBlock) void k_init_outer(int n, const int32_t* __restrict__ sperm,
+                                                       const double* __restrict__ b,
                                                        double* __restrict__ bh,
                                                        double* __restrict__ x,
                                                        double* __restrict__ r, const Scal* S,
@@ -934,24 +1036,26 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(int n, const double* __re
     const int t = blockIdx.x * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (t < n) {
-        const double bt = b[t] - mean;
+        const double bt = b[sperm ? sperm[t] : t] - mean;
         bh[t] = bt;
-        x[t] = 0.0;
-        r[t] = bt;
+        if (x) x[t] = 0.0;
+        if (r) r[t] = bt;
         v[0] = bt * bt;
     }
     block_partial<1>(v, part);
 }
 
-// x += d (FP64 += FP32 correction, input order).
+// x += d (FP64 += FP32 correction, solve order).
 __global__ __launch_bounds__(kBlock) void k_add_corr(int n, double* __restrict__ x,
                                                      const float* __restrict__ d) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t < n) x[t] += (double)d[t];
 }
 
-// xc = x - mean(x) and the caller's copy of it (input order).
-__global__ __launch_bounds__(kBlock) void k_center_out(int n, const double* __restrict__ x,
+// xc = x - mean(x) (solve order) and the caller's copy of it in input
+// order.
+__global__ __launch_bounds__(kBlock) void k_center_out(int n, const int32_t* __restrict__ sperm,
+                                                       const double* __restrict__ x,
                                                        double* __restrict__ xc,
                                                        double* __restrict__ dst, const Scal* S) {
     const double mean = S->xsum / (double)n;
@@ -959,11 +1063,11 @@ __global__ __launch_bounds__(kBlock) void k_center_out(int n, const double* __re
     if (t < n) {
         const double v = x[t] - mean;
         xc[t] = v;
-        dst[t] = v;
+        dst[sperm ? sperm[t] : t] = v;
     }
 }
 
-// dst[t] = src[perm[t]] (input order -> tree order).
+// dst[t] = src[perm[t]] (a gather: input order -> tree or solve order).
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_gather(int n, const int32_t* __restrict__ perm,
                                                    const double* __restrict__ src,
@@ -972,12 +1076,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(int n, const int32_t* __restr
     if (t < n) dst[t] = (T)src[perm[t]];
 }
 
-// dst = src - zbar (input order).
+// dst[sperm[t]] = src[t] - zbar (solve order -> input order; zbar from S,
+// or 0 when S is null).
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_shift_out(int n, const T* __restrict__ src,
+__global__ __launch_bounds__(kBlock) void k_shift_out(int n, const int32_t* __restrict__ sperm,
+                                                      const T* __restrict__ src,
                                                       double* __restrict__ dst, const Scal* S) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t < n) dst[t] = (double)src[t] - S->zbar;
+    if (t < n) dst[sperm ? sperm[t] : t] = (double)src[t] - (S ? S->zbar : 0.0);
 }
 
 }  // namespace lapgpu

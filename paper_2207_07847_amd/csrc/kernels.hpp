@@ -20,6 +20,8 @@ constexpr int kMaxGridPart = 3;    // values reduced per block
 constexpr int kAggPerBlock = 256;  // aggregates per block of a level kernel
 constexpr int kCapP = 2048;        // children per block staged in LDS; an
                                    // aggregate with more gets a block alone
+constexpr int kWaveAgg = 32;       // aggregates with more children are
+                                   // restricted by a whole wavefront
 
 // Scalars of one PCG run, resident in device memory.
 struct Scal {

@@ -294,7 +294,8 @@ struct lap_hierarchy {
     lap_params params{};
     bool host_only = false;
     bool with_msp = true;
-    bool mixed = false;
+    bool mixed = false;          // solves use mixed precision
+    bool has_fp32 = false;       // the FP32 engine exists
     int64_t n = 0;
     int device = 0;
     double setup_seconds = 0.0;
@@ -302,6 +303,11 @@ struct lap_hierarchy {
     std::vector<void*> allocs;
     // integer data shared by both engines
     int32_t* perm0 = nullptr;    // tree position -> input vertex
+    // The solve order (x, p, q, the SpMV's copy of z, bh) is the input order
+    // for meshes and the tree order otherwise (HostPlan::spmv_tree):
+    const int32_t* t2s = nullptr;   // tree position -> solve position (null: same)
+    const int32_t* sperm = nullptr; // solve position -> input vertex (null: same)
+    bool fuse_p = true;             // SpMV forms p on the fly (else a p pass first)
     std::vector<const int32_t*> cptr, bst;
     std::vector<int32_t> nb;
     Sell<double> Ai{};           // the index arrays of the SpMV matrix (weights unset)
@@ -384,19 +390,17 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
     Scal* S = h->S;
     if (!h->with_msp || Tl == 0) {
         if (do_update) {
-            hipLaunchKernelGGL(k_update_none<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n,
-                               (const int32_t*)h->perm0, e.x, e.r, pcur, (const T*)e.q, S,
-                               h->part2);
+            hipLaunchKernelGGL(k_update_none<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s,
+                               e.x, e.r, pcur, (const T*)e.q, S, h->part2);
             if (h->with_msp) finish<kFinRr>(h, s, S, nblk(n), 0, h->part2);
         }
         if (!h->with_msp) {
-            hipLaunchKernelGGL(k_prec_none<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n,
-                               (const int32_t*)h->perm0, (const T*)e.r, e.z, e.zn, S, h->part);
+            hipLaunchKernelGGL(k_prec_none<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s,
+                               (const T*)e.r, e.z, e.zn, S, h->part);
             finish<kFinRho>(h, s, S, nblk(n), do_update ? nblk(n) : 0);
         } else {
-            hipLaunchKernelGGL(k_top_only<T>, dim3(1), dim3(kBlock), 0, s, n,
-                               (const int32_t*)h->perm0, (const T*)e.top_pinv, (const T*)e.r, e.z,
-                               e.zn, S);
+            hipLaunchKernelGGL(k_top_only<T>, dim3(1), dim3(kBlock), 0, s, n, h->t2s,
+                               (const T*)e.top_pinv, (const T*)e.r, e.z, e.zn, S);
         }
         return;
     }
@@ -404,7 +408,7 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
     const int g0 = s0.nb;
     launch_timed(k_update_up0<T>, dim3(g0), dim3(kBlock), 0, s,
                  mk.kernel == LAP_KERNEL_PRECOND ? mk.e0 : mk.start(LAP_KERNEL_UPDATE),
-                 mk.stop(LAP_KERNEL_UPDATE), s0, (const int32_t*)h->perm0, e.x, e.r, pcur,
+                 mk.stop(LAP_KERNEL_UPDATE), s0, h->t2s, e.x, e.r, pcur,
                  (const T*)e.q, e.lv[1].r, S, h->part2, do_update);
     for (const auto& G : e.segs) {
         if (G.group)
@@ -428,8 +432,8 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
                                (const Scal*)S);
     }
     launch_timed(k_down0<T>, dim3(g0), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_DOWN0),
-                 mk.kernel == LAP_KERNEL_PRECOND ? mk.e1 : mk.stop(LAP_KERNEL_DOWN0), s0,
-                 (const int32_t*)h->perm0, (const T*)e.r, e.zn, (const T*)e.lv[1].y, S, h->part);
+                 mk.kernel == LAP_KERNEL_PRECOND ? mk.e1 : mk.stop(LAP_KERNEL_DOWN0), s0, h->t2s,
+                 (const T*)e.r, e.zn, (const T*)e.lv[1].y, S, h->part);
     finish<kFinRho>(h, s, S, g0, do_update ? g0 : 0);
 }
 
@@ -437,9 +441,19 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
 template <class T>
 void enqueue_iteration(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int par,
                        const Marks& mk = Marks{}) {
-    launch_timed(k_spmv_p<T>, dim3(e.spmv_grid()), dim3(kBlock), 0, s,
-                 mk.start(LAP_KERNEL_SPMV), mk.stop(LAP_KERNEL_SPMV), e.nlb, e.A,
-                 (const T*)e.zn, (const T*)e.p[par], e.p[1 - par], e.q, h->S, h->part);
+    if (h->fuse_p) {
+        launch_timed(k_spmv_p<T>, dim3(e.spmv_grid()), dim3(kBlock), 0, s,
+                     mk.start(LAP_KERNEL_SPMV), mk.stop(LAP_KERNEL_SPMV), e.nlb, e.A,
+                     (const T*)e.zn, (const T*)e.p[par], e.p[1 - par], e.q, h->S, h->part);
+    } else {
+        const int n = (int)h->n;
+        launch_timed(k_pupd<T>, dim3(nblk(n)), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_SPMV),
+                     (hipEvent_t) nullptr, n, (const T*)e.zn, (const T*)e.p[par], e.p[1 - par],
+                     (const Scal*)h->S);
+        launch_timed(k_spmv_q<T>, dim3(e.spmv_grid()), dim3(kBlock), 0, s, (hipEvent_t) nullptr,
+                     mk.stop(LAP_KERNEL_SPMV), e.nlb, e.A, (const T*)e.p[1 - par], e.q, h->S,
+                     h->part);
+    }
     finish<kFinPq>(h, s, h->S, e.spmv_grid());
     enqueue_precond(h, e, s, 1, e.p[1 - par], mk);
 }
@@ -459,6 +473,10 @@ void upload_shared(lap_hierarchy* h, hipStream_t s) {
     const HostPlan& P = h->plan;
     const int T = P.nlev() - 1;
     h->perm0 = h->upload(P.perm[0], s);
+    h->t2s = P.spmv_tree ? nullptr : h->perm0;
+    h->sperm = P.spmv_tree ? h->perm0 : nullptr;
+    const int fz = env_int("LAPGPU_FUSE_P", -1);
+    h->fuse_p = fz < 0 ? !P.spmv_tree : fz != 0;
     h->cptr.assign(T, nullptr);
     h->bst.assign(T, nullptr);
     h->nb.assign(T, 0);
@@ -619,7 +637,9 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     h->with_msp = (h->params.precond == LAP_PREC_MSP);
     h->mixed = (h->params.precision == LAP_MIXED_FP32_FP64);
     upload_shared(h, s);
-    upload_engine(h, h->e64, s, h->with_msp && !h->mixed);
+    // a mixed-precision hierarchy carries the FP64 solve as well
+    // (lap_set_precision switches between them)
+    upload_engine(h, h->e64, s, h->with_msp);
     if (h->mixed) upload_engine(h, h->e32, s, h->with_msp);
     h->bh = h->dalloc<double>(n);
     h->xc = h->dalloc<double>(n);
@@ -641,8 +661,9 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     HIPCHK(hipGetLastError());
     h->chunk = std::max(2, env_int("LAPGPU_CHUNK", 8) & ~1);
     h->inner_tol = env_double("LAPGPU_INNER_TOL", 1e-4);
+    build_graph(h, h->e64);
     if (h->mixed) build_graph(h, h->e32);
-    else build_graph(h, h->e64);
+    h->has_fp32 = h->mixed;
 }
 
 lap_status to_status(int done) {
@@ -661,12 +682,12 @@ Scal read_scal(lap_hierarchy* h, const Scal* S, hipStream_t s) {
     return *h->stage;
 }
 
-// PCG on engine e for the right-hand side rhs (FP64, input order, projected
+// PCG on engine e for the right-hand side rhs (FP64, solve order, projected
 // here): x = 0 start, stop at ||r|| <= tol ||rhs^|| or after maxit products
-// with L.  bh (may be null) receives rhs^.  Returns the final scalars.
+// with L.  Returns the final scalars.
 template <class T>
-Scal run_pcg(lap_hierarchy* h, Engine<T>& e, const double* rhs, double* bh, double tol,
-             int maxit, hipStream_t s) {
+Scal run_pcg(lap_hierarchy* h, Engine<T>& e, const double* rhs, double tol, int maxit,
+             hipStream_t s) {
     const int n = (int)h->n;
     std::memset(h->stage, 0, sizeof(Scal));
     h->stage->tol2 = tol * tol;
@@ -674,8 +695,8 @@ Scal run_pcg(lap_hierarchy* h, Engine<T>& e, const double* rhs, double* bh, doub
     HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, rhs, h->part);
     finish<kFinBsum>(h, s, h->S, nblk(n));
-    hipLaunchKernelGGL(k_init<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, (const int32_t*)h->perm0,
-                       rhs, bh, e.r, e.x, e.p[0], e.p[1], (const Scal*)h->S, h->part);
+    hipLaunchKernelGGL(k_init<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s, rhs, e.r, e.x,
+                       e.p[0], e.p[1], (const Scal*)h->S, h->part);
     finish<kFinBn2>(h, s, h->S, nblk(n));
     enqueue_precond(h, e, s, 0, (const T*)e.p[0]);
     HIPCHK(hipGetLastError());
@@ -700,14 +721,14 @@ Scal run_pcg(lap_hierarchy* h, Engine<T>& e, const double* rhs, double* bh, doub
     return read_scal(h, h->S, s);
 }
 
-// Mean-free x (input order) into the caller's buffer and the true FP64
-// residual ||bh - L x||^2 into So->res2.
+// Mean-free x (solve order) into the caller's buffer (input order) and the
+// true FP64 residual ||bh - L x||^2 into So->res2.
 void finalize_x(lap_hierarchy* h, const double* xsrc, double* x, hipStream_t s) {
     const int n = (int)h->n;
     hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, xsrc, h->part);
     finish<kFinXsum>(h, s, h->So, nblk(n));
-    hipLaunchKernelGGL(k_center_out, dim3(nblk(n)), dim3(kBlock), 0, s, n, xsrc, h->xc, x,
-                       (const Scal*)h->So);
+    hipLaunchKernelGGL(k_center_out, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm, xsrc,
+                       h->xc, x, (const Scal*)h->So);
     const Engine<double>& e = h->e64;
     hipLaunchKernelGGL(k_resid, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A,
                        (const double*)h->xc, (const double*)h->bh, (double*)nullptr, h->part);
@@ -715,10 +736,26 @@ void finalize_x(lap_hierarchy* h, const double* xsrc, double* x, hipStream_t s) 
     HIPCHK(hipGetLastError());
 }
 
+// bh = b - mean(b) in solve order; for mixed precision also x64 = 0 and
+// r64 = bh.  ||bh||^2 lands in So->res2.
+void begin_solve(lap_hierarchy* h, const double* b, bool outer, hipStream_t s) {
+    const int n = (int)h->n;
+    std::memset(h->stage, 0, sizeof(Scal));
+    HIPCHK(hipMemcpyAsync(h->So, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, b, h->part);
+    finish<kFinBsum>(h, s, h->So, nblk(n));
+    hipLaunchKernelGGL(k_init_outer, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm, b, h->bh,
+                       outer ? h->x64 : nullptr, outer ? h->r64 : nullptr, (const Scal*)h->So,
+                       h->part);
+    finish<kFinRes2>(h, s, h->So, nblk(n));
+    HIPCHK(hipGetLastError());
+}
+
 lap_status solve_fp64(lap_hierarchy* h, const double* b, double* x, double tol,
                       lap_solve_info* info, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
-    const Scal R = run_pcg(h, h->e64, b, h->bh, tol, h->params.max_iter, s);
+    begin_solve(h, b, false, s);
+    const Scal R = run_pcg(h, h->e64, h->bh, tol, h->params.max_iter, s);
     finalize_x(h, h->e64.x, x, s);
     const Scal O = read_scal(h, h->So, s);
     const lap_status st = R.done == 0 ? LAP_ENOCONV : to_status(R.done);
@@ -744,14 +781,7 @@ lap_status solve_mixed(lap_hierarchy* h, const double* b, double* x, double tol,
     const auto t0 = std::chrono::steady_clock::now();
     const int n = (int)h->n;
     const Engine<double>& e = h->e64;
-    std::memset(h->stage, 0, sizeof(Scal));
-    HIPCHK(hipMemcpyAsync(h->So, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, b, h->part);
-    finish<kFinBsum>(h, s, h->So, nblk(n));
-    hipLaunchKernelGGL(k_init_outer, dim3(nblk(n)), dim3(kBlock), 0, s, n, b, h->bh, h->x64,
-                       h->r64, (const Scal*)h->So, h->part);
-    finish<kFinRes2>(h, s, h->So, nblk(n));
-    HIPCHK(hipGetLastError());
+    begin_solve(h, b, true, s);
     const double bn2 = read_scal(h, h->So, s).res2;
     if (!std::isfinite(bn2)) return LAP_EINVAL;
     double res2 = bn2;
@@ -766,7 +796,7 @@ lap_status solve_mixed(lap_hierarchy* h, const double* b, double* x, double tol,
         if (iters >= h->params.max_iter || refs >= max_refs) break;
         const double rel_needed = tol * std::sqrt(bn2 / res2);
         const double itol = std::max(h->inner_tol, 0.5 * rel_needed);
-        const Scal R = run_pcg(h, h->e32, h->r64, nullptr, itol, h->params.max_iter - iters, s);
+        const Scal R = run_pcg(h, h->e32, h->r64, itol, h->params.max_iter - iters, s);
         iters += R.iter;
         ++refs;
         if (R.iter == 0 && R.done != 1) {
@@ -825,8 +855,8 @@ void apply_precond(lap_hierarchy* h, Engine<T>& e, const double* r, double* z, h
     hipLaunchKernelGGL(k_gather<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n,
                        (const int32_t*)h->perm0, r, e.r);
     enqueue_precond(h, e, s, 0, (const T*)e.p[0]);
-    hipLaunchKernelGGL(k_shift_out<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, (const T*)e.zn, z,
-                       (const Scal*)h->S);
+    hipLaunchKernelGGL(k_shift_out<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm,
+                       (const T*)e.zn, z, (const Scal*)h->S);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
 }
@@ -851,8 +881,9 @@ double part_bytes(const lap_hierarchy* h, int kernel, double vb, bool levels) {
         const double nc = lvn(k + 1), nl = lvn(k) - 2.0 * lvn(k + 1);
         return 4.0 * nc + 2.0 * vb * nc + vb * nc + 3.0 * vb * nl + vb * nl + vb * lvn(k);
     };
-    // SpMV: z, p_old read, p, q written; col and w per stored entry
-    const double spmv = 4.0 * vb * n + (4.0 + vb) * nnz;
+    // SpMV: z, p_old read, p, q written; col and w per stored entry (with
+    // a separate p pass, p is read back once more by the SpMV)
+    const double spmv = (h->fuse_p ? 4.0 : 5.0) * vb * n + (4.0 + vb) * nnz;
     const double upd = levels ? 6.0 * vb * n + step_up(0) - vb * n : 6.0 * vb * n;
     const double down0 =
         levels ? step_down(0) - vb * (lvn(0) - 2.0 * lvn(1)) + vb * n : 3.0 * vb * n;
@@ -1020,12 +1051,34 @@ lap_status lap_solve(lap_hierarchy* h, const double* b, double* x, int32_t nrhs,
     return worst;
 }
 
+lap_status lap_set_precision(lap_hierarchy* h, int32_t precision) {
+    if (!h) return LAP_EINVAL;
+    if (precision != LAP_FP64 && precision != LAP_MIXED_FP32_FP64) return LAP_EINVAL;
+    if (h->host_only) return LAP_EUNSUPPORTED;
+    if (precision == LAP_MIXED_FP32_FP64 && !h->has_fp32) return LAP_EUNSUPPORTED;
+    h->mixed = precision == LAP_MIXED_FP32_FP64;
+    return LAP_OK;
+}
+
 lap_status lap_apply_laplacian(lap_hierarchy* h, const double* x, double* y, void* stream) {
     if (!h || !x || !y) return LAP_EINVAL;
     if (h->host_only) return LAP_EUNSUPPORTED;
     const Engine<double>& e = h->e64;
-    hipLaunchKernelGGL(k_spmv_plain, dim3(e.spmv_grid()), dim3(kBlock), 0, (hipStream_t)stream,
-                       e.nlb, e.A, x, y);
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)h->n;
+    if (h->sperm) {
+        // solve order differs from the input order: permute in and out
+        // through two FP64 work vectors of the hierarchy
+        hipLaunchKernelGGL(k_gather<double>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm, x,
+                           h->xc);
+        hipLaunchKernelGGL(k_spmv_plain, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A,
+                           (const double*)h->xc, h->bh);
+        hipLaunchKernelGGL(k_shift_out<double>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm,
+                           (const double*)h->bh, y, (const Scal*)nullptr);
+    } else {
+        hipLaunchKernelGGL(k_spmv_plain, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A, x,
+                           y);
+    }
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) {
         record_error("k_spmv_plain launch", err, __LINE__);

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <numeric>
 
 namespace lapgpu {
@@ -378,23 +380,83 @@ int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
         for (double& x : plan.top_pinv) x *= plan.theta[T];
     }
 
-    // 4. fine Laplacian for the SpMV
-    build_sell(plan.lv[0].g, plan);
+    // 4. fine Laplacian for the SpMV.  A mesh keeps its own order (its
+    //    neighbour gathers are contiguous across a wavefront); any other
+    //    graph is renumbered in the tree order of the hierarchy, where every
+    //    aggregate (a vertex with its heaviest neighbours) is contiguous and
+    //    the level-0 restriction and prolongation need no permutation.
+    const char* ord = std::getenv("LAPGPU_SPMV_ORDER");
+    if (ord && std::strcmp(ord, "tree") == 0) plan.spmv_tree = true;
+    else if (ord && std::strcmp(ord, "natural") == 0) plan.spmv_tree = false;
+    else plan.spmv_tree = !mesh_like(plan.lv[0].g);
+    if (plan.spmv_tree && T >= 1) {
+        Adjacency gt;
+        permute_graph(plan.lv[0].g, plan.perm[0], plan.inv[0], gt);
+        build_sell(gt, plan);
+    } else {
+        plan.spmv_tree = false;
+        build_sell(plan.lv[0].g, plan);
+    }
     return kOk;
 }
 
-// Sliced ELL in the graph's own vertex order: for meshes and grids that
+bool mesh_like(const Adjacency& g) {
+    int64_t nnz = 0, pad = 0;
+    for (int64_t s = 0; s * kSlice < g.n; ++s) {
+        int64_t wmax = 0;
+        for (int64_t t = s * kSlice; t < std::min<int64_t>(g.n, (s + 1) * kSlice); ++t) {
+            const int64_t d = g.ptr[t + 1] - g.ptr[t];
+            if (d > kHeavyDeg) return false;
+            wmax = std::max(wmax, d);
+            nnz += d;
+        }
+        pad += wmax * kSlice;
+    }
+    return pad * 100 <= nnz * 115;
+}
+
+void permute_graph(const Adjacency& g, const std::vector<int32_t>& perm,
+                   const std::vector<int32_t>& inv, Adjacency& out) {
+    out.n = g.n;
+    out.ptr.assign(g.n + 1, 0);
+    out.col.resize(g.nnz());
+    out.w.resize(g.nnz());
+    for (int64_t t = 0; t < g.n; ++t) out.ptr[t + 1] = out.ptr[t] + (g.ptr[perm[t] + 1] - g.ptr[perm[t]]);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t t = 0; t < g.n; ++t) {
+        const int64_t i = perm[t];
+        row.clear();
+        for (int64_t k = g.ptr[i]; k < g.ptr[i + 1]; ++k) row.push_back({inv[g.col[k]], g.w[k]});
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                      return a.first < b.first;
+                  });
+        for (size_t q = 0; q < row.size(); ++q) {
+            out.col[out.ptr[t] + q] = row[q].first;
+            out.w[out.ptr[t] + q] = row[q].second;
+        }
+    }
+}
+
+// Sliced ELL in the given vertex order: for meshes and grids that
 // order keeps the neighbour gathers of a wavefront within a few cache
 // lines.  Rows of degree above kHeavyDeg go to a CSR part processed a row
 // per wavefront (or per block).  When slices of consecutive rows would be
 // padded by more than 15 %, rows are sorted by degree within windows of
 // kSigma rows first (sliced ELL with sorting windows), so a slice's rows
 // have similar degrees.
+static int env_or(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : dflt;
+}
+
 void build_sell(const Adjacency& g, HostPlan& plan) {
     const int64_t n = g.n;
+    const int64_t heavy_deg = std::max(16, env_or("LAPGPU_HEAVY_DEG", kHeavyDeg));
+    const int64_t sigma = std::max(kSlice, env_or("LAPGPU_SIGMA", kSigma));
     auto deg = [&](int64_t i) { return g.ptr[i + 1] - g.ptr[i]; };
     std::vector<int32_t> light, heavy;
-    for (int64_t i = 0; i < n; ++i) (deg(i) > kHeavyDeg ? heavy : light).push_back((int32_t)i);
+    for (int64_t i = 0; i < n; ++i) (deg(i) > heavy_deg ? heavy : light).push_back((int32_t)i);
     const int64_t nl = (int64_t)light.size();
     int64_t nnz_l = 0, pad_id = 0;
     for (int64_t s = 0; s * kSlice < nl; ++s) {
@@ -407,8 +469,8 @@ void build_sell(const Adjacency& g, HostPlan& plan) {
     }
     const bool sorted = pad_id * 100 > nnz_l * 115;
     if (sorted)
-        for (int64_t w0 = 0; w0 < nl; w0 += kSigma) {
-            const auto b = light.begin() + w0, e = light.begin() + std::min<int64_t>(nl, w0 + kSigma);
+        for (int64_t w0 = 0; w0 < nl; w0 += sigma) {
+            const auto b = light.begin() + w0, e = light.begin() + std::min<int64_t>(nl, w0 + sigma);
             std::stable_sort(b, e, [&](int32_t x, int32_t y) { return deg(x) > deg(y); });
         }
     const int64_t nslice = (nl + kSlice - 1) / kSlice;

@@ -23,9 +23,9 @@ enum Status { kOk = 0, kInval = 1, kDisconnected = 2, kNoMem = 3, kDevice = 4,
 
 constexpr int kSlice = 64;        // rows per sliced-ELL slice (one wave)
 constexpr int kTopMax = 64;       // largest top level solved on chip
-constexpr int kHeavyDeg = 128;    // rows of higher degree leave the slices
+constexpr int kHeavyDeg = 64;     // rows of higher degree leave the slices
 constexpr int kHeavyBlockDeg = 4096;  // ... and above this get a block alone
-constexpr int kSigma = 512;       // rows sorted by degree within windows of this
+constexpr int kSigma = 65536;     // rows sorted by degree within windows of this
 constexpr int kHeavyWaves = 4;    // heavy rows per heavy block (one per wave)
 
 // Symmetric weighted adjacency, neighbours ascending, no diagonal.
@@ -58,8 +58,11 @@ struct HostPlan {
     std::vector<StepCoef> step;              // nlev-1 entries
     std::vector<double> theta;               // theta_k, k = 0..nlev-1
     std::vector<double> top_pinv;            // theta_top * pinv(L_top), row-major
-    // fine Laplacian, input vertex order: light rows in sliced ELL (64 rows
-    // per slice, column-major), heavy rows in CSR
+    // fine Laplacian for the SpMV, in the solve order: the graph's own order
+    // (spmv_tree false) or the tree order of level 0 (spmv_tree true; then
+    // solve position t is input vertex perm[0][t]).  Light rows in sliced
+    // ELL (64 rows per slice, column-major), heavy rows in CSR.
+    bool spmv_tree = false;
     int32_t sell_nlight = 0;
     std::vector<int32_t> sell_off;           // slice -> first slot
     std::vector<int32_t> sell_width;         // slice -> slots per row
@@ -86,7 +89,13 @@ void coarse_graph(const Adjacency& f, const std::vector<int64_t>& agg, int64_t n
 int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                const double* w, double mu, int max_levels, int64_t n_top,
                uint64_t seed, bool host_only, HostPlan& plan);
-// The SpMV layout of the fine Laplacian (part of build_plan).
+// The SpMV layout of the fine Laplacian g (part of build_plan).
 void build_sell(const Adjacency& g, HostPlan& plan);
+// Whether g is mesh-like for the SpMV: no row above kHeavyDeg and slices of
+// consecutive rows padded by at most 15 %.
+bool mesh_like(const Adjacency& g);
+// g renumbered: new id of old vertex i is inv[i], rows ascending.
+void permute_graph(const Adjacency& g, const std::vector<int32_t>& perm,
+                   const std::vector<int32_t>& inv, Adjacency& out);
 
 }  // namespace lapgpu

@@ -145,8 +145,10 @@ def chung_lu(n, mean_degree=16.0, gamma=2.1, seed=0):
     cdf = np.cumsum(wdeg)
     cdf /= cdf[-1]
     m = int(round(n * mean_degree / 2))
-    u = np.searchsorted(cdf, rng.random(m), side="right")
-    v = np.searchsorted(cdf, rng.random(m), side="right")
+    # inverse-CDF draws of both endpoints; sorted queries make the searches
+    # cache-friendly, and a random permutation of the second end pairs them
+    u = np.searchsorted(cdf, np.sort(rng.random(m)), side="right")
+    v = np.searchsorted(cdf, np.sort(rng.random(m)), side="right")[rng.permutation(m)]
     np.minimum(u, n - 1, out=u)
     np.minimum(v, n - 1, out=v)
     n2, u2, v2 = _canon(n, u, v)
