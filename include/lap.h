@@ -59,6 +59,9 @@ typedef enum {
 #define LAP_FLAG_HOST_ONLY 1u  /* lap_setup builds the host hierarchy only:
                                   export/info calls work, solves return
                                   LAP_EUNSUPPORTED; no device is touched. */
+#define LAP_FLAG_MULTI_RHS 2u  /* lap_setup also builds the block solve: calls
+                                  with nrhs > 1 advance up to 64 columns
+                                  together (see lap_solve) */
 
 /* Undirected weighted graph, host memory, edges (u[e], v[e], w[e]).
  * Requirements: n >= 2; 0 <= u, v < n; u != v; w finite and > 0.

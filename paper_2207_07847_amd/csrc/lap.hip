@@ -14,6 +14,7 @@
 #include <new>
 #include <vector>
 
+#include "block.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 #include "lap.h"
@@ -287,6 +288,69 @@ struct Engine {
     }
 };
 
+// Chunked work list over segments [ptr[i], ptr[i+1]) (rows of a matrix or
+// children of aggregates): segments longer than `chunk` are split, their
+// chunks writing partial rows to scratch slots that a combine pass adds.
+template <class P>
+struct ChunkHost {
+    std::vector<int32_t> id, t0, t1, slot, multi, mfirst{0};
+    void build(const std::vector<P>& ptr, int chunk) {
+        const size_t nseg = ptr.size() - 1;
+        int32_t ns = 0;
+        for (size_t i = 0; i < nseg; ++i) {
+            const P a = ptr[i], b = ptr[i + 1];
+            if (b - a <= chunk) {
+                id.push_back((int32_t)i);
+                t0.push_back((int32_t)a);
+                t1.push_back((int32_t)b);
+                slot.push_back(-1);
+                continue;
+            }
+            multi.push_back((int32_t)i);
+            for (P c = a; c < b; c += chunk) {
+                id.push_back((int32_t)i);
+                t0.push_back((int32_t)c);
+                t1.push_back((int32_t)std::min<P>(b, c + chunk));
+                slot.push_back(ns++);
+            }
+            mfirst.push_back(ns);
+        }
+    }
+    int32_t nslots() const { return mfirst.back(); }
+};
+
+// Device data of the block solve of one value type: the Laplacian in CSR
+// (solve order) with its chunk list, per step the up and down chunk lists,
+// the block vectors of every level.
+template <class T>
+struct EngineM {
+    bool on = false;
+    Csr<T> A{};
+    Chunks CA{};
+    T* scrA = nullptr;           // partial rows of split SpMM rows
+    std::vector<LevelDev<T>> lv; // block vectors r, y, ea, eb (rows of kCols)
+    std::vector<Chunks> up, down;
+    std::vector<T*> scrU;        // per step: 3 partial rows per split chunk
+    T* top_pinv = nullptr;
+    T *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *zn = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        exec = nullptr;
+        graph = nullptr;
+        cap = nullptr;
+    }
+};
+
+inline int mm_grid(int64_t items) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((items + kMmWaves - 1) / kMmWaves,
+                                                       kMmMaxGrid));
+}
+
 }  // namespace
 
 struct lap_hierarchy {
@@ -313,6 +377,19 @@ struct lap_hierarchy {
     Sell<double> Ai{};           // the index arrays of the SpMV matrix (weights unset)
     Engine<double> e64;          // FP64 solve (matrix always: residuals, apply)
     Engine<float> e32;           // inner solve of mixed precision
+    // block solve (LAP_FLAG_MULTI_RHS): kCols columns at once
+    bool has_block = false;
+    EngineM<double> m64;         // FP64 block solve
+    EngineM<float> m32;          // FP32 inner block solve (mixed precision)
+    Csr<double> A64m{};          // FP64 CSR for block residuals
+    Chunks CA64{};
+    double* scrA64 = nullptr;
+    double *bhm = nullptr, *xm = nullptr, *rm = nullptr, *xcm = nullptr;   // FP64 block vectors
+    ScalM* Sm = nullptr;         // scalars of the inner block runs
+    ScalM* Smo = nullptr;        // scalars of the outer block loop
+    ScalM* stagem = nullptr;     // pinned host copy
+    double* partm = nullptr;     // per-block per-column partials
+    double* partm2 = nullptr;
     // FP64 vectors in input order
     double *bh = nullptr, *xc = nullptr, *x64 = nullptr, *r64 = nullptr;
     Scal* S = nullptr;           // scalars of the PCG run
@@ -345,8 +422,24 @@ struct lap_hierarchy {
     ~lap_hierarchy() {
         e64.release();
         e32.release();
+        m64.release();
+        m32.release();
         for (void* ptr : allocs) (void)hipFree(ptr);
         if (stage) (void)hipHostFree(stage);
+        if (stagem) (void)hipHostFree(stagem);
+    }
+    template <class P>
+    Chunks upload_chunks(const ChunkHost<P>& c, hipStream_t s) {
+        Chunks d{};
+        d.nitems = (int32_t)c.id.size();
+        d.id = upload(c.id, s);
+        d.t0 = upload(c.t0, s);
+        d.t1 = upload(c.t1, s);
+        d.slot = upload(c.slot, s);
+        d.nmulti = (int32_t)c.multi.size();
+        d.multi = upload(c.multi, s);
+        d.mfirst = upload(c.mfirst, s);
+        return d;
     }
 };
 
@@ -666,6 +759,170 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     h->has_fp32 = h->mixed;
 }
 
+// ------------------------------------------------------------ block solve
+
+template <class T>
+void upload_block_engine(lap_hierarchy* h, EngineM<T>& m, const Engine<T>& e, hipStream_t s) {
+    const HostPlan& P = h->plan;
+    const int L = P.nlev();
+    const int Tl = L - 1;
+    const int64_t n = h->n;
+    const size_t K = kCols;
+    m.on = true;
+    {
+        const Adjacency& g = P.solve_graph();
+        m.A.n = (int32_t)n;
+        m.A.ptr = h->upload(g.ptr, s);
+        m.A.col = h->upload(g.col, s);
+        m.A.w = h->upload(convert<T>(g.w), s);
+        ChunkHost<int64_t> ch;
+        ch.build(g.ptr, kMmChunk);
+        m.CA = h->upload_chunks(ch, s);
+        m.scrA = h->dalloc<T>((size_t)std::max(1, ch.nslots()) * K);
+    }
+    m.x = h->dalloc<T>(n * K);
+    m.q = h->dalloc<T>(n * K);
+    m.zn = h->dalloc<T>(n * K);
+    m.p[0] = h->dalloc<T>(n * K);
+    m.p[1] = h->dalloc<T>(n * K);
+    m.lv.assign(L, LevelDev<T>{});
+    m.up.assign(std::max(Tl, 0), Chunks{});
+    m.down.assign(std::max(Tl, 0), Chunks{});
+    m.scrU.assign(std::max(Tl, 0), nullptr);
+    for (int k = 0; k < L; ++k) {
+        LevelDev<T>& d = m.lv[k];
+        d.n = (int32_t)P.lv[k].g.n;
+        d.nc = k < Tl ? (int32_t)P.lv[k + 1].g.n : 0;
+        d.r = h->dalloc<T>((size_t)d.n * K);
+        d.y = h->dalloc<T>((size_t)d.n * K);
+        if (k < Tl && h->with_msp) {
+            const LevelDev<T>& c = e.lv[k];
+            d.cptr = c.cptr;
+            d.saa = c.saa;
+            d.sab = c.sab;
+            d.sbb = c.sbb;
+            d.l0 = c.l0;
+            d.l1 = c.l1;
+            d.l2 = c.l2;
+            d.ea = h->dalloc<T>((size_t)d.nc * K);
+            d.eb = h->dalloc<T>((size_t)d.nc * K);
+            ChunkHost<int32_t> ch;
+            ch.build(P.step[k].cptr, kMmChunk);
+            m.up[k] = h->upload_chunks(ch, s);
+            m.down[k] = m.up[k];
+            m.scrU[k] = h->dalloc<T>((size_t)std::max(1, ch.nslots()) * 3 * K);
+        }
+    }
+    if (h->with_msp) m.top_pinv = e.top_pinv;
+}
+
+void upload_block(lap_hierarchy* h, hipStream_t s) {
+    const int64_t n = h->n;
+    const size_t K = kCols;
+    if (h->has_fp32) upload_block_engine(h, h->m32, h->e32, s);
+    upload_block_engine(h, h->m64, h->e64, s);
+    h->A64m = h->m64.A;
+    h->CA64 = h->m64.CA;
+    h->scrA64 = h->m64.scrA;
+    h->bhm = h->dalloc<double>(n * K);
+    h->xm = h->dalloc<double>(n * K);
+    h->rm = h->dalloc<double>(n * K);
+    h->xcm = h->dalloc<double>(n * K);
+    h->Sm = h->dalloc<ScalM>(1);
+    h->Smo = h->dalloc<ScalM>(1);
+    h->partm = h->dalloc<double>((size_t)3 * kMmMaxGrid * K + 64);
+    h->partm2 = h->dalloc<double>((size_t)kMmMaxGrid * K + 64);
+    HIPCHK(hipHostMalloc((void**)&h->stagem, sizeof(ScalM), hipHostMallocDefault));
+    std::memset(h->stagem, 0, sizeof(ScalM));
+    h->has_block = true;
+}
+
+template <int OP>
+void finish_m(lap_hierarchy* h, hipStream_t s, ScalM* S, int G, int G2 = 0) {
+    hipLaunchKernelGGL(k_mm_finish<OP>, dim3(1), dim3(1024), 0, s, G, (int)h->n,
+                       (const double*)h->partm, G2, (const double*)h->partm2, S);
+}
+
+// The block preconditioner: level-0 update (when do_update), restriction
+// and local solves up the levels, the top, prolongation back, z with its
+// per-column sums.
+template <class T>
+void enqueue_mm_precond(lap_hierarchy* h, EngineM<T>& m, hipStream_t s, int do_update,
+                        const T* pcur) {
+    const int Tl = h->plan.nlev() - 1;
+    const int n = (int)h->n;
+    ScalM* S = h->Sm;
+    const int gn = mm_grid(n);
+    LevelDev<T>& l0 = m.lv[0];
+    if (do_update)
+        hipLaunchKernelGGL(k_mm_update<T>, dim3(gn), dim3(kMmWaves * 64), 0, s, n, h->t2s, m.x,
+                           l0.r, pcur, (const T*)m.q, (const ScalM*)S, h->partm2);
+    if (!h->with_msp) {
+        hipLaunchKernelGGL(k_mm_copy<T>, dim3(gn), dim3(kMmWaves * 64), 0, s, n, (const T*)l0.r,
+                           l0.y, (const ScalM*)S);
+    } else {
+        for (int k = 0; k < Tl; ++k) {
+            const Chunks& C = m.up[k];
+            hipLaunchKernelGGL(k_mm_up<T>, dim3(mm_grid(C.nitems)), dim3(kMmWaves * 64), 0, s,
+                               m.lv[k], C, (const T*)m.lv[k].r, m.lv[k + 1].r, m.scrU[k],
+                               (const ScalM*)S);
+            if (C.nmulti > 0)
+                hipLaunchKernelGGL(k_mm_up_combine<T>, dim3(mm_grid(C.nmulti)),
+                                   dim3(kMmWaves * 64), 0, s, m.lv[k], C, m.lv[k + 1].r,
+                                   (const T*)m.scrU[k], (const ScalM*)S);
+        }
+        hipLaunchKernelGGL(k_mm_top<T>, dim3(1), dim3(kMmWaves * 64), 0, s,
+                           (int)h->plan.lv[Tl].g.n, (const T*)m.top_pinv, (const T*)m.lv[Tl].r,
+                           m.lv[Tl].y, (const ScalM*)S);
+        for (int k = Tl - 1; k >= 0; --k) {
+            const Chunks& C = m.down[k];
+            hipLaunchKernelGGL(k_mm_down<T>, dim3(mm_grid(C.nitems)), dim3(kMmWaves * 64), 0, s,
+                               m.lv[k], C, (const T*)m.lv[k].r, m.lv[k].y,
+                               (const T*)m.lv[k + 1].y, (const ScalM*)S);
+        }
+    }
+    hipLaunchKernelGGL(k_mm_zout<T>, dim3(gn), dim3(kMmWaves * 64), 0, s, n, h->t2s,
+                       (const T*)l0.r, (const T*)l0.y, m.zn, (const ScalM*)S, h->partm);
+    finish_m<kMmRho>(h, s, S, gn, do_update ? gn : 0);
+}
+
+template <class T>
+void enqueue_mm_iteration(lap_hierarchy* h, EngineM<T>& m, hipStream_t s, int par) {
+    const int n = (int)h->n;
+    ScalM* S = h->Sm;
+    hipLaunchKernelGGL(k_mm_pupd<T>, dim3(mm_grid(n)), dim3(kMmWaves * 64), 0, s, n,
+                       (const T*)m.zn, (const T*)m.p[par], m.p[1 - par], (const ScalM*)S);
+    const int ga = mm_grid(m.CA.nitems);
+    hipLaunchKernelGGL(k_mm_spmm<T>, dim3(ga), dim3(kMmWaves * 64), 0, s, m.A, m.CA,
+                       (const T*)m.p[1 - par], m.q, m.scrA, (const ScalM*)S, h->partm);
+    int gc = 0;
+    if (m.CA.nmulti > 0) {
+        // split rows: their Q rows and p^T q shares come from the combine
+        gc = mm_grid(m.CA.nmulti);
+        hipLaunchKernelGGL(k_mm_spmm_combine<T>, dim3(gc), dim3(kMmWaves * 64), 0, s, m.CA,
+                           (const T*)m.p[1 - par], m.q, (const T*)m.scrA, (const ScalM*)S,
+                           h->partm2);
+    }
+    finish_m<kMmPq>(h, s, S, ga, gc);
+    enqueue_mm_precond(h, m, s, 1, (const T*)m.p[1 - par]);
+}
+
+template <class T>
+void build_mm_graph(lap_hierarchy* h, EngineM<T>& m) {
+    HIPCHK(hipStreamCreateWithFlags(&m.cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(m.cap, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < h->chunk; ++i) enqueue_mm_iteration(h, m, m.cap, i & 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamEndCapture(m.cap, &m.graph));
+    HIPCHK(hipGraphInstantiate(&m.exec, m.graph, nullptr, nullptr, 0));
+}
+
+void setup_block(lap_hierarchy* h, hipStream_t s) {
+    upload_block(h, s);
+    build_mm_graph(h, h->m64);
+    if (h->m32.on) build_mm_graph(h, h->m32);
+}
+
 lap_status to_status(int done) {
     switch (done) {
         case 1: return LAP_OK;
@@ -833,6 +1090,182 @@ lap_status solve_mixed(lap_hierarchy* h, const double* b, double* x, double tol,
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return st;
+}
+
+int rank_status(lap_status s);
+
+ScalM read_scalm(lap_hierarchy* h, const ScalM* S, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(h->stagem, S, sizeof(ScalM), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return *h->stagem;
+}
+
+// Inner block PCG on engine m for the right-hand sides rhs (FP64 block,
+// solve order): columns with active[c] false take no part; column c stops
+// at ||r|| <= sqrt(tol2[c]) ||r_0||.
+template <class T>
+ScalM run_mm_pcg(lap_hierarchy* h, EngineM<T>& m, const double* rhs, const bool* active,
+                 const double* tol2, int maxit, hipStream_t s) {
+    const int n = (int)h->n, gn = mm_grid(n);
+    ScalM& st = *h->stagem;
+    std::memset(&st, 0, sizeof(ScalM));
+    for (int c = 0; c < kCols; ++c) {
+        st.done[c] = active[c] ? 0 : 5;
+        st.tol2[c] = tol2[c];
+    }
+    st.maxit = maxit;
+    HIPCHK(hipMemcpyAsync(h->Sm, &st, sizeof(ScalM), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_mm_colsum, dim3(gn), dim3(kMmWaves * 64), 0, s, n, rhs, h->partm);
+    finish_m<kMmSum>(h, s, h->Sm, gn);
+    hipLaunchKernelGGL(k_mm_init<T>, dim3(gn), dim3(kMmWaves * 64), 0, s, n, h->t2s, rhs,
+                       m.lv[0].r, m.x, m.p[0], m.p[1], (const ScalM*)h->Sm, h->partm);
+    finish_m<kMmBn2>(h, s, h->Sm, gn);
+    enqueue_mm_precond(h, m, s, 0, (const T*)m.p[0]);
+    HIPCHK(hipGetLastError());
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    const int max_chunks = maxit / h->chunk + 2;
+    try {
+        HIPCHK(hipGraphLaunch(m.exec, s));
+        for (int c = 0; c < max_chunks; ++c) {
+            HIPCHK(hipMemcpyAsync(&h->stagem->all_done, &h->Sm->all_done, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(ev, s));
+            HIPCHK(hipGraphLaunch(m.exec, s));
+            HIPCHK(hipEventSynchronize(ev));
+            if (h->stagem->all_done) break;
+        }
+    } catch (const HipErr&) {
+        (void)hipEventDestroy(ev);
+        throw;
+    }
+    (void)hipEventDestroy(ev);
+    return read_scalm(h, h->Sm, s);
+}
+
+// r = bh - L x for the block (FP64), per-column ||r||^2 into So->res2.
+void block_residual(lap_hierarchy* h, const double* x, hipStream_t s) {
+    const Chunks& C = h->CA64;
+    const int ga = mm_grid(C.nitems);
+    hipLaunchKernelGGL(k_mm_resid, dim3(ga), dim3(kMmWaves * 64), 0, s, h->A64m, C, x,
+                       (const double*)h->bhm, h->rm, h->scrA64, h->partm);
+    int gc = 0;
+    if (C.nmulti > 0) {
+        gc = mm_grid(C.nmulti);
+        hipLaunchKernelGGL(k_mm_resid_combine, dim3(gc), dim3(kMmWaves * 64), 0, s, C,
+                           (const double*)h->bhm, h->rm, (const double*)h->scrA64, h->partm2);
+    }
+    finish_m<kMmRes2>(h, s, h->Smo, ga, gc);
+    HIPCHK(hipGetLastError());
+}
+
+// Up to kCols right-hand sides at once (caller's columns c < nrhs at
+// b + c*ld).  Mixed precision: each refinement runs the FP32 block PCG on
+// the FP64 residuals of the columns not yet converged; FP64: the FP64
+// block PCG, refined only if a column's recursive residual drifted.
+lap_status solve_block(lap_hierarchy* h, const double* b, double* x, int nrhs, int64_t ld,
+                       double tol, lap_solve_info* info, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int n = (int)h->n, gn = mm_grid(n);
+    std::memset(h->stagem, 0, sizeof(ScalM));
+    HIPCHK(hipMemcpyAsync(h->Smo, h->stagem, sizeof(ScalM), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_mm_colsum_in, dim3(gn), dim3(kMmWaves * 64), 0, s, n, b, ld, nrhs,
+                       h->partm);
+    finish_m<kMmSum>(h, s, h->Smo, gn);
+    hipLaunchKernelGGL(k_mm_begin, dim3(gn), dim3(kMmWaves * 64), 0, s, n, h->sperm, b, ld, nrhs,
+                       h->bhm, h->xm, h->rm, (const ScalM*)h->Smo, h->partm);
+    finish_m<kMmRes2>(h, s, h->Smo, gn);
+    HIPCHK(hipGetLastError());
+    ScalM O = read_scalm(h, h->Smo, s);
+    double bn2[kCols], res2[kCols], tol2[kCols];
+    bool active[kCols];
+    int iters[kCols] = {0}, stalls[kCols] = {0};
+    lap_status st[kCols];
+    for (int c = 0; c < kCols; ++c) {
+        bn2[c] = res2[c] = O.res2[c];
+        active[c] = c < nrhs;
+        st[c] = LAP_ENOCONV;
+        if (c < nrhs && !std::isfinite(bn2[c])) {
+            st[c] = LAP_EINVAL;
+            active[c] = false;
+        }
+    }
+    int refs = 0;
+    const bool mixed = h->mixed && h->m32.on;
+    while (refs < 40) {
+        bool any = false;
+        for (int c = 0; c < nrhs; ++c) {
+            if (!active[c]) continue;
+            if (res2[c] <= tol * tol * bn2[c]) {
+                st[c] = LAP_OK;
+                active[c] = false;
+            } else if (iters[c] >= h->params.max_iter || stalls[c] >= 3) {
+                active[c] = false;
+            }
+            any |= active[c];
+            const double need = tol * std::sqrt(bn2[c] / std::max(res2[c], 1e-300));
+            const double it = mixed ? std::max(h->inner_tol, 0.5 * need) : 0.9 * need;
+            tol2[c] = it * it;
+        }
+        if (!any) break;
+        int maxit = 0;
+        for (int c = 0; c < nrhs; ++c)
+            if (active[c]) maxit = std::max(maxit, h->params.max_iter - iters[c]);
+        ScalM R;
+        if (mixed) R = run_mm_pcg(h, h->m32, h->rm, active, tol2, maxit, s);
+        else R = run_mm_pcg(h, h->m64, h->rm, active, tol2, maxit, s);
+        ++refs;
+        for (int c = 0; c < nrhs; ++c)
+            if (active[c]) iters[c] += R.iter[c];
+        if (mixed)
+            hipLaunchKernelGGL(k_mm_addcorr<float>, dim3(gn), dim3(kMmWaves * 64), 0, s, n,
+                               h->xm, (const float*)h->m32.x);
+        else
+            hipLaunchKernelGGL(k_mm_addcorr<double>, dim3(gn), dim3(kMmWaves * 64), 0, s, n,
+                               h->xm, (const double*)h->m64.x);
+        block_residual(h, h->xm, s);
+        O = read_scalm(h, h->Smo, s);
+        for (int c = 0; c < nrhs; ++c) {
+            if (!active[c]) continue;
+            if (R.done[c] == 3 && R.iter[c] == 0) {
+                st[c] = LAP_EBREAKDOWN;
+                active[c] = false;
+                continue;
+            }
+            if (!std::isfinite(O.res2[c])) {
+                st[c] = LAP_EBREAKDOWN;
+                active[c] = false;
+                continue;
+            }
+            stalls[c] = O.res2[c] > 0.25 * res2[c] ? stalls[c] + 1 : 0;
+            res2[c] = O.res2[c];
+        }
+    }
+    // mean-free x to the caller, true residuals
+    hipLaunchKernelGGL(k_mm_colsum, dim3(gn), dim3(kMmWaves * 64), 0, s, n, (const double*)h->xm,
+                       h->partm);
+    finish_m<kMmSum>(h, s, h->Smo, gn);
+    hipLaunchKernelGGL(k_mm_out, dim3(gn), dim3(kMmWaves * 64), 0, s, n, h->sperm,
+                       (const double*)h->xm, h->xcm, x, ld, nrhs, (const ScalM*)h->Smo);
+    block_residual(h, h->xcm, s);
+    O = read_scalm(h, h->Smo, s);
+    lap_status worst = LAP_OK;
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int c = 0; c < nrhs; ++c) {
+        if (st[c] == LAP_OK && !(O.res2[c] <= tol * tol * bn2[c] * 1.0001)) st[c] = LAP_ENOCONV;
+        if (info) {
+            const double bn = std::sqrt(bn2[c]);
+            info[c].iterations = iters[c];
+            info[c].refinements = refs;
+            info[c].relres_true = bn > 0 ? std::sqrt(O.res2[c]) / bn : 0.0;
+            info[c].relres_recursive = bn > 0 ? std::sqrt(res2[c]) / bn : 0.0;
+            info[c].status = st[c];
+            info[c].seconds = secs;
+        }
+        if (rank_status(st[c]) > rank_status(worst)) worst = st[c];
+    }
+    return worst;
 }
 
 int rank_status(lap_status s) {
@@ -1016,6 +1449,7 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
             }
             HIPCHK(hipGetDevice(&h->device));
             upload_plan(h, (hipStream_t)stream);
+            if (p->flags & LAP_FLAG_MULTI_RHS) setup_block(h, (hipStream_t)stream);
         }
     } catch (const std::bad_alloc&) {
         delete h;
@@ -1037,6 +1471,16 @@ lap_status lap_solve(lap_hierarchy* h, const double* b, double* x, int32_t nrhs,
     if (h->host_only) return LAP_EUNSUPPORTED;
     lap_status worst = LAP_OK;
     try {
+        if (nrhs > 1 && h->has_block) {
+            for (int c0 = 0; c0 < nrhs; c0 += kCols) {
+                const int nb = std::min(kCols, nrhs - c0);
+                const lap_status st = solve_block(h, b + (int64_t)c0 * ld, x + (int64_t)c0 * ld,
+                                                  nb, ld, tol, info ? info + c0 : nullptr,
+                                                  (hipStream_t)stream);
+                if (rank_status(st) > rank_status(worst)) worst = st;
+            }
+            return worst;
+        }
         for (int c = 0; c < nrhs; ++c) {
             const double* bc = b + (int64_t)c * ld;
             double* xc = x + (int64_t)c * ld;

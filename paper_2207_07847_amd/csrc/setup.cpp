@@ -390,9 +390,8 @@ int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
     else if (ord && std::strcmp(ord, "natural") == 0) plan.spmv_tree = false;
     else plan.spmv_tree = !mesh_like(plan.lv[0].g);
     if (plan.spmv_tree && T >= 1) {
-        Adjacency gt;
-        permute_graph(plan.lv[0].g, plan.perm[0], plan.inv[0], gt);
-        build_sell(gt, plan);
+        permute_graph(plan.lv[0].g, plan.perm[0], plan.inv[0], plan.solve_g);
+        build_sell(plan.solve_g, plan);
     } else {
         plan.spmv_tree = false;
         build_sell(plan.lv[0].g, plan);

@@ -63,6 +63,8 @@ struct HostPlan {
     // solve position t is input vertex perm[0][t]).  Light rows in sliced
     // ELL (64 rows per slice, column-major), heavy rows in CSR.
     bool spmv_tree = false;
+    Adjacency solve_g;                       // the graph in tree order (spmv_tree)
+    const Adjacency& solve_graph() const { return spmv_tree ? solve_g : lv[0].g; }
     int32_t sell_nlight = 0;
     std::vector<int32_t> sell_off;           // slice -> first slot
     std::vector<int32_t> sell_width;         // slice -> slots per row

@@ -44,6 +44,20 @@ class GpuLap:
         t.cuda.synchronize()
         return st, xd.cpu().numpy(), info[0]
 
+    def solve_many(self, B, tol, ld=None):
+        """B: (nrhs, n) host array, column c = B[c]; returns (status, X, infos)."""
+        t = self.torch
+        nrhs = B.shape[0]
+        ld = ld or self.n
+        Bp = np.zeros((nrhs, ld))
+        Bp[:, :self.n] = B
+        bd = self.dev(Bp.ravel())
+        xd = t.full((nrhs * ld,), float("nan"), dtype=t.float64, device="cuda")
+        st, info = self.lap.lap_solve(self.h, bd.data_ptr(), xd.data_ptr(), self.n, tol,
+                                      nrhs=nrhs, ld=ld, stream=self.stream())
+        t.cuda.synchronize()
+        return st, xd.cpu().numpy().reshape(nrhs, ld)[:, :self.n], info
+
     def apply_laplacian(self, x):
         xd = self.dev(x)
         yd = self.torch.empty_like(xd)
