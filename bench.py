@@ -38,16 +38,21 @@ WORKLOADS = {
     "chunglu_4m": "Chung-Lu 4M ids (LCC), mean degree 16, gamma 2.1, w=U(0,1], MSP mu=0.8 "
                   "level=max, 1 Gaussian RHS, tol 1e-8",
     "rmat_20": "R-MAT scale 20 (LCC), (0.57,0.19,0.19,0.05), 16 samples/id, w=U(0,1], MSP mu=0.8 "
-               "level=max, 1 Gaussian RHS, tol 1e-8",
+               "level=max, tol 1e-8",
 }
 
 
-def workload(name, scale):
+def workload(name, scale, nrhs=1):
+    """Graph, right-hand side(s) and solver settings.  nrhs > 1: columns
+    e_i - e_j for seeded random pairs (shape (nrhs, n))."""
     import workloads as W
     if name not in WORKLOADS:
         raise SystemExit(f"unknown workload {name}")
     n, u, v, w = W.config_graph(name, scale)
-    b = W.gaussian_rhs(n, W.MASTER_SEED + 3)
+    if nrhs > 1:
+        b = W.pair_rhs(n, nrhs, W.MASTER_SEED + 6)
+    else:
+        b = W.gaussian_rhs(n, W.MASTER_SEED + 3)
     return dict(n=n, u=u, v=v, w=w, b=b, mu=0.8, tol=1e-8)
 
 
@@ -105,18 +110,20 @@ def cpu_baseline(wl, gpu_iters, budget_s):
     }
 
 
-def measure(lap, h, bd, xd, n, tol, steps, warmup, sh, stream, capped):
-    """Warm-up solves, then `steps` timed solves; per-solve latency from
-    HIP events on the solve stream."""
+def measure(lap, h, bd, xd, n, tol, steps, warmup, sh, stream, capped, nrhs=1):
+    """Warm-up solves, then `steps` timed solves (of nrhs columns each);
+    per-solve latency from HIP events on the solve stream."""
     import torch
 
     def one():
-        st, inf = lap.lap_solve(h, bd.data_ptr(), xd.data_ptr(), n, tol, stream=sh)
+        st, inf = lap.lap_solve(h, bd.data_ptr(), xd.data_ptr(), n, tol, nrhs=nrhs,
+                                stream=sh)
         if st == lap.LAP_ENOCONV and capped:
             return inf[0]
         if st != 0:
-            raise SystemExit(f"solve failed: {lap.lap_status_str(st)} {inf}")
-        return inf[0]
+            raise SystemExit(f"solve failed: {lap.lap_status_str(st)} {inf[:2]}")
+        worst = max(inf, key=lambda i: i["relres_true"])
+        return dict(worst, iterations=max(i["iterations"] for i in inf))
 
     for i in range(warmup):
         inf = one()
@@ -149,6 +156,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"],
                     help="both: mixed precision timed, plain FP64 timed beside it")
     ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides per solve (> 1: the 64-column block solve)")
+    ap.add_argument("--compare-cols", type=int, default=8,
+                    help="with --nrhs > 1: columns timed as single FP64 solves beside it")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-reps", type=int, default=100)
@@ -169,30 +180,52 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    wl = workload(args.workload, args.scale)
+    wl = workload(args.workload, args.scale, args.nrhs)
     log(f"workload {args.workload}: n={wl['n']} edges={len(wl['u'])} ({time.time() - t0:.1f}s)")
     n = wl["n"]
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
     prec = lap.LAP_FP64 if args.precision == "fp64" else lap.LAP_MIXED_FP32_FP64
     t0 = time.time()
+    flags = lap.LAP_FLAG_MULTI_RHS if args.nrhs > 1 else 0
     h = lap.lap_setup(n, wl["u"], wl["v"], wl["w"],
                       lap.lap_default_params(mu=wl["mu"], max_iter=args.max_iter,
-                                             precision=prec), sh)
+                                             precision=prec, flags=flags), sh)
     setup_s = time.time() - t0
     info = lap.lap_hierarchy_info(h)
     log(f"setup {setup_s:.2f}s levels={info['nlev']} tail={info['tail_level']} "
         f"sizes={info['sizes'][:4]}...{info['sizes'][-2:]}")
-    bd = torch.tensor(wl["b"], dtype=torch.float64, device="cuda")
+    bd = torch.tensor(np.ascontiguousarray(wl["b"]).ravel(), dtype=torch.float64, device="cuda")
     xd = torch.empty_like(bd)
     capped = args.max_iter < 200000
     base = None
-    if args.precision == "both":
+    if args.nrhs > 1:
+        # single FP64 solves of the first columns, on the same hierarchy
+        lap.lap_set_precision(h, lap.LAP_FP64)
+        k = min(args.compare_cols, args.nrhs)
+        log(f"plain FP64 single solves of {k} columns beside it:")
+        t0 = time.perf_counter()
+        its = []
+        for c in range(k):
+            st, inf = lap.lap_solve(h, bd.data_ptr() + 8 * c * n, xd.data_ptr() + 8 * c * n, n,
+                                    wl["tol"], nrhs=1, stream=sh)
+            torch.cuda.synchronize()
+            if st != 0:
+                raise SystemExit(f"single solve failed: {lap.lap_status_str(st)}")
+            its.append(inf[0]["iterations"])
+        dt = time.perf_counter() - t0
+        log(f"  {k} single FP64 solves: {dt:.3f}s, iterations {min(its)}..{max(its)}")
+        base = dict(elapsed=dt / k * args.nrhs, lat=[dt / k * 1e3], info=dict(
+            iterations=max(its), relres_true=inf[0]["relres_true"]), cols=k)
+        if args.precision != "fp64":
+            lap.lap_set_precision(h, lap.LAP_MIXED_FP32_FP64)
+    elif args.precision == "both":
         lap.lap_set_precision(h, lap.LAP_FP64)
         log("plain FP64 beside it:")
         base = measure(lap, h, bd, xd, n, wl["tol"], args.steps, args.warmup, sh, stream, capped)
         lap.lap_set_precision(h, lap.LAP_MIXED_FP32_FP64)
-    res = measure(lap, h, bd, xd, n, wl["tol"], args.steps, args.warmup, sh, stream, capped)
+    res = measure(lap, h, bd, xd, n, wl["tol"], args.steps, args.warmup, sh, stream, capped,
+                  args.nrhs)
     inf = res["info"]
 
     if args.calib_copy_mb:
@@ -213,10 +246,17 @@ def main():
         ms, by = lap.lap_profile_kernel(h, kid, args.profile_reps, sh)
         kern[name] = {"avg_us": ms * 1e3, "alg_bytes": by, "gbs": by / (ms * 1e-3) / 1e9}
         log(f"kernel {name}: {ms * 1e3:.1f} us, {by / 1e6:.1f} MB, {kern[name]['gbs']:.0f} GB/s")
+    if args.nrhs > 1:
+        for kid, name in [(lap.LAP_KERNEL_BLOCK_SPMM, "block_spmm"),
+                          (lap.LAP_KERNEL_BLOCK_ITER, "block_iteration")]:
+            ms, by = lap.lap_profile_kernel(h, kid, max(3, args.profile_reps // 10), sh)
+            kern[name] = {"avg_us": ms * 1e3, "alg_bytes": by,
+                          "gbs": by / (ms * 1e-3) / 1e9 if by else None}
+            log(f"kernel {name}: {ms * 1e3:.1f} us, {by / 1e6:.1f} MB")
     lap.lap_free(h)
 
-    spmv = kern["spmv_p"]
-    steps = args.steps
+    spmv = kern["spmv_p"] if args.nrhs == 1 else kern["block_spmm"]
+    steps = args.steps * args.nrhs       # right-hand sides solved
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
     line = {
         "metric": METRIC,
@@ -225,7 +265,7 @@ def main():
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": res["elapsed"] / steps * 1e3,
+        "ms_per_step": res["elapsed"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
@@ -236,7 +276,7 @@ def main():
             if args.scale != 1.0 else WORKLOADS[args.workload],
             "precision": "FP64" if args.precision == "fp64" else
                          "FP32 SpMV/preconditioner inside FP64 iterative refinement",
-            "n": n, "edges": int(len(wl["u"])), "levels": info["nlev"],
+            "n": n, "edges": int(len(wl["u"])), "levels": info["nlev"], "nrhs": args.nrhs,
             "iterations": inf["iterations"], "refinements": inf["refinements"],
             "relres_true": inf["relres_true"],
         },
@@ -248,7 +288,7 @@ def main():
         "setup_s": setup_s,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_spmv_p",
+            "kernel": "k_spmv_p" if args.nrhs == 1 else "k_mm_spmm",
             "achieved": spmv["gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -259,12 +299,16 @@ def main():
     if base is not None:
         bi = base["info"]
         line["fp64_same_gpu"] = {
-            "value": steps / base["elapsed"], "unit": "solves/s",
-            "ms_per_step": base["elapsed"] / steps * 1e3,
+            "value": steps / base["elapsed"] if args.nrhs == 1 else args.nrhs / base["elapsed"],
+            "unit": "solves/s",
+            "ms_per_step": base["elapsed"] / (args.steps if args.nrhs == 1 else 1) * 1e3,
             "iterations": bi["iterations"], "relres_true": bi["relres_true"],
             "p50_ms": float(np.percentile(base["lat"], 50)),
+            "what": "plain FP64 PCG, one right-hand side per solve" +
+                    (f" (timed on {base['cols']} of the columns)" if args.nrhs > 1 else ""),
         }
-        line["speedup_vs_fp64"] = base["elapsed"] / res["elapsed"]
+        line["speedup_vs_fp64"] = (base["elapsed"] / res["elapsed"]) if args.nrhs == 1 else \
+            (base["elapsed"] / (res["elapsed"] / args.steps))
     if not args.no_cpu:
         if args.workload == "grid3d_128" and args.scale == 1.0:
             log("cpu baseline (oracle) ...")

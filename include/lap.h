@@ -182,11 +182,15 @@ lap_status lap_apply_precond(lap_hierarchy *h, const double *r, double *z,
  *   LAP_KERNEL_PRECOND  update through down0: the x, r update and the
  *                       whole preconditioner (all levels)
  *   LAP_KERNEL_ITER     one whole PCG iteration
+ *   LAP_KERNEL_BLOCK_SPMM  block solve (LAP_FLAG_MULTI_RHS): Q = L P over 64
+ *                       columns (2 n 64 v + (4 + v) nnz bytes, v = value size)
+ *   LAP_KERNEL_BLOCK_ITER  one whole iteration of the block solve
  * Errors: LAP_EINVAL (bad id, reps < 1), LAP_EUNSUPPORTED (host-only or a
  * part the hierarchy does not have), LAP_EBREAKDOWN (the iterations hit a
  * breakdown, so the timing is not representative), LAP_EDEVICE. */
 enum { LAP_KERNEL_SPMV = 0, LAP_KERNEL_UPDATE = 1, LAP_KERNEL_DOWN0 = 2,
-       LAP_KERNEL_PRECOND = 3, LAP_KERNEL_ITER = 4 };
+       LAP_KERNEL_PRECOND = 3, LAP_KERNEL_ITER = 4,
+       LAP_KERNEL_BLOCK_SPMM = 5, LAP_KERNEL_BLOCK_ITER = 6 };
 lap_status lap_profile_kernel(lap_hierarchy *h, int32_t kernel, int32_t reps,
                               void *stream, double *avg_ms, double *alg_bytes);
 

@@ -29,6 +29,7 @@ LAP_FLAG_HOST_ONLY = 1
 LAP_FLAG_MULTI_RHS = 2
 LAP_MAX_LEVELS = 64
 LAP_KERNEL_SPMV, LAP_KERNEL_UPDATE, LAP_KERNEL_DOWN0, LAP_KERNEL_PRECOND, LAP_KERNEL_ITER = range(5)
+LAP_KERNEL_BLOCK_SPMM, LAP_KERNEL_BLOCK_ITER = 5, 6
 
 
 class lap_graph(C.Structure):

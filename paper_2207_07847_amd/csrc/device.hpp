@@ -1045,6 +1045,13 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(int n, const int32_t* __r
     block_partial<1>(v, part);
 }
 
+// A fixed non-constant vector (kCols columns per row when cols > 1), the
+// start of timing runs: v = ((i * 2654435761) mod 1024) / 1024 - 1/2.
+__global__ __launch_bounds__(kBlock) void k_pattern(int64_t count, double* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) dst[i] = (double)((uint64_t)(i * 2654435761ull) & 1023u) / 1024.0 - 0.5;
+}
+
 // x += d (FP64 += FP32 correction, solve order).
 __global__ __launch_bounds__(kBlock) void k_add_corr(int n, double* __restrict__ x,
                                                      const float* __restrict__ d) {

@@ -55,6 +55,7 @@ double env_double(const char* name, double dflt) {
 }
 
 constexpr size_t kTailLdsBytes = 152 * 1024;
+constexpr int kProfGroup = 10;          // timed iterations per fresh run (profiling)
 constexpr size_t kGrpLdsBytes = 64 * 1024;
 
 // int32 entries that fit one value slot of type T.
@@ -887,14 +888,15 @@ void enqueue_mm_precond(lap_hierarchy* h, EngineM<T>& m, hipStream_t s, int do_u
 }
 
 template <class T>
-void enqueue_mm_iteration(lap_hierarchy* h, EngineM<T>& m, hipStream_t s, int par) {
+void enqueue_mm_iteration(lap_hierarchy* h, EngineM<T>& m, hipStream_t s, int par,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     const int n = (int)h->n;
     ScalM* S = h->Sm;
     hipLaunchKernelGGL(k_mm_pupd<T>, dim3(mm_grid(n)), dim3(kMmWaves * 64), 0, s, n,
                        (const T*)m.zn, (const T*)m.p[par], m.p[1 - par], (const ScalM*)S);
     const int ga = mm_grid(m.CA.nitems);
-    hipLaunchKernelGGL(k_mm_spmm<T>, dim3(ga), dim3(kMmWaves * 64), 0, s, m.A, m.CA,
-                       (const T*)m.p[1 - par], m.q, m.scrA, (const ScalM*)S, h->partm);
+    launch_timed(k_mm_spmm<T>, dim3(ga), dim3(kMmWaves * 64), 0, s, e0, e1, m.A, m.CA,
+                 (const T*)m.p[1 - par], m.q, m.scrA, (const ScalM*)S, h->partm);
     int gc = 0;
     if (m.CA.nmulti > 0) {
         // split rows: their Q rows and p^T q shares come from the combine
@@ -1343,30 +1345,43 @@ lap_status profile(lap_hierarchy* h, Engine<T>& e, int32_t kernel, int32_t reps,
     // ITER: two events around all timed iterations; a part: its own kernels'
     // timestamps in every timed iteration
     const bool whole = kernel == LAP_KERNEL_ITER;
-    std::vector<hipEvent_t> ev(whole ? 2 : 2 * (size_t)reps, nullptr);
+    const int groups = (reps + kProfGroup - 1) / kProfGroup;
+    std::vector<hipEvent_t> ev(whole ? 2 * (size_t)groups : 2 * (size_t)reps, nullptr);
     auto destroy = [&]() {
         for (hipEvent_t x : ev)
             if (x) (void)hipEventDestroy(x);
     };
     try {
-        std::memset(h->stage, 0, sizeof(Scal));
-        h->stage->maxit = 0x7fffffff;
-        h->stage->rho = 1.0;
-        h->stage->bn2 = 1.0;
-        HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
         for (auto& x : ev) HIPCHK(hipEventCreate(&x));
-        enqueue_iteration(h, e, s, 1);   // untimed
-        if (whole) HIPCHK(hipEventRecord(ev[0], s));
-        for (int i = 0; i < reps; ++i) {
-            Marks mk;
-            if (!whole) {
-                mk.kernel = kernel;
-                mk.e0 = ev[2 * i];
-                mk.e1 = ev[2 * i + 1];
+        // a fresh PCG run from a fixed right-hand side every kProfGroup
+        // timed iterations, so no run nears convergence while timed
+        const int n = (int)h->n;
+        hipLaunchKernelGGL(k_pattern, dim3(nblk(n)), dim3(kBlock), 0, s, (int64_t)n, h->xc);
+        for (int i0 = 0; i0 < reps; i0 += kProfGroup) {
+            std::memset(h->stage, 0, sizeof(Scal));
+            h->stage->maxit = 0x7fffffff;
+            HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, (const double*)h->xc,
+                               h->part);
+            finish<kFinBsum>(h, s, h->S, nblk(n));
+            hipLaunchKernelGGL(k_init<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s,
+                               (const double*)h->xc, e.r, e.x, e.p[0], e.p[1], (const Scal*)h->S,
+                               h->part);
+            finish<kFinBn2>(h, s, h->S, nblk(n));
+            enqueue_precond(h, e, s, 0, (const T*)e.p[0]);
+            const int i1 = std::min(reps, i0 + kProfGroup);
+            if (whole) HIPCHK(hipEventRecord(ev[2 * (i0 / kProfGroup)], s));
+            for (int i = i0; i < i1; ++i) {
+                Marks mk;
+                if (!whole) {
+                    mk.kernel = kernel;
+                    mk.e0 = ev[2 * i];
+                    mk.e1 = ev[2 * i + 1];
+                }
+                enqueue_iteration(h, e, s, i & 1, mk);
             }
-            enqueue_iteration(h, e, s, i & 1, mk);
+            if (whole) HIPCHK(hipEventRecord(ev[2 * (i0 / kProfGroup) + 1], s));
         }
-        if (whole) HIPCHK(hipEventRecord(ev[1], s));
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         double total = 0.0;
@@ -1380,6 +1395,64 @@ lap_status profile(lap_hierarchy* h, Engine<T>& e, int32_t kernel, int32_t reps,
         const bool ran = read_scal(h, h->S, s).done == 0;
         destroy();
         return ran ? LAP_OK : LAP_EBREAKDOWN;
+    } catch (const HipErr&) {
+        destroy();
+        return LAP_EDEVICE;
+    }
+}
+
+template <class T>
+lap_status profile_block(lap_hierarchy* h, EngineM<T>& m, int32_t kernel, int32_t reps,
+                         hipStream_t s, double* avg_ms, double* alg_bytes) {
+    const double vb = (double)sizeof(T), n = (double)h->n, K = kCols;
+    const double nnz = (double)h->plan.lv[0].g.nnz();
+    const double spmm = 2.0 * n * K * vb + (4.0 + vb) * nnz;
+    const bool whole = kernel == LAP_KERNEL_BLOCK_ITER;
+    const int groups = (reps + kProfGroup - 1) / kProfGroup;
+    std::vector<hipEvent_t> ev(whole ? 2 * (size_t)groups : 2 * (size_t)reps, nullptr);
+    auto destroy = [&]() {
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+    };
+    try {
+        for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+        const int nn = (int)h->n, gn = mm_grid(nn);
+        const int64_t cnt = (int64_t)nn * kCols;
+        hipLaunchKernelGGL(k_pattern, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, s, cnt, h->xcm);
+        for (int i0 = 0; i0 < reps; i0 += kProfGroup) {
+            ScalM& st = *h->stagem;
+            std::memset(&st, 0, sizeof(ScalM));
+            st.maxit = 0x7fffffff;
+            HIPCHK(hipMemcpyAsync(h->Sm, &st, sizeof(ScalM), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_mm_colsum, dim3(gn), dim3(kMmWaves * 64), 0, s, nn,
+                               (const double*)h->xcm, h->partm);
+            finish_m<kMmSum>(h, s, h->Sm, gn);
+            hipLaunchKernelGGL(k_mm_init<T>, dim3(gn), dim3(kMmWaves * 64), 0, s, nn, h->t2s,
+                               (const double*)h->xcm, m.lv[0].r, m.x, m.p[0], m.p[1],
+                               (const ScalM*)h->Sm, h->partm);
+            finish_m<kMmBn2>(h, s, h->Sm, gn);
+            enqueue_mm_precond(h, m, s, 0, (const T*)m.p[0]);
+            const int i1 = std::min(reps, i0 + kProfGroup);
+            if (whole) HIPCHK(hipEventRecord(ev[2 * (i0 / kProfGroup)], s));
+            for (int i = i0; i < i1; ++i) {
+                if (whole) enqueue_mm_iteration(h, m, s, i & 1);
+                else enqueue_mm_iteration(h, m, s, i & 1, ev[2 * i], ev[2 * i + 1]);
+            }
+            if (whole) HIPCHK(hipEventRecord(ev[2 * (i0 / kProfGroup) + 1], s));
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+        double total = 0.0;
+        for (size_t i = 0; i < ev.size(); i += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            total += ms;
+        }
+        if (avg_ms) *avg_ms = total / reps;
+        if (alg_bytes) *alg_bytes = whole ? 0.0 : spmm;
+        destroy();
+        return LAP_OK;
     } catch (const HipErr&) {
         destroy();
         return LAP_EDEVICE;
@@ -1545,8 +1618,15 @@ lap_status lap_apply_precond(lap_hierarchy* h, const double* r, double* z, void*
 
 lap_status lap_profile_kernel(lap_hierarchy* h, int32_t kernel, int32_t reps, void* stream,
                               double* avg_ms, double* alg_bytes) {
-    if (!h || reps < 1 || kernel < 0 || kernel > LAP_KERNEL_ITER) return LAP_EINVAL;
+    if (!h || reps < 1 || kernel < 0 || kernel > LAP_KERNEL_BLOCK_ITER) return LAP_EINVAL;
     if (h->host_only) return LAP_EUNSUPPORTED;
+    if (kernel >= LAP_KERNEL_BLOCK_SPMM) {
+        if (!h->has_block) return LAP_EUNSUPPORTED;
+        return h->mixed ? profile_block(h, h->m32, kernel, reps, (hipStream_t)stream, avg_ms,
+                                        alg_bytes)
+                        : profile_block(h, h->m64, kernel, reps, (hipStream_t)stream, avg_ms,
+                                        alg_bytes);
+    }
     return h->mixed ? profile(h, h->e32, kernel, reps, (hipStream_t)stream, avg_ms, alg_bytes)
                     : profile(h, h->e64, kernel, reps, (hipStream_t)stream, avg_ms, alg_bytes);
 }
