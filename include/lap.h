@@ -212,6 +212,61 @@ lap_status lap_export_level(const lap_hierarchy *h, int32_t level,
 lap_status lap_export_graph(const lap_hierarchy *h, int32_t level,
                             int64_t *ptr, int64_t *col, double *w);
 
+/* ------------------------------------------------------------ serving
+ *
+ * A request server over resident hierarchies (continuous batching).  Every
+ * registered hierarchy (set up with LAP_FLAG_MULTI_RHS) keeps its FP64
+ * block solve resident with its own stream: 64 column slots, each running
+ * its own PCG (per-column scalars and stop test).  A background thread
+ * advances the graphs with work in chunks of iterations and, at every chunk
+ * boundary of a graph, hands out the columns that have stopped and admits
+ * queued requests into the free slots while the other columns keep
+ * iterating; graphs run concurrently on their streams.  A request (1..64
+ * right-hand sides of one graph) is admitted when it fits the free slots
+ * and its staging memory fits the HBM budget (resident hierarchies count
+ * against the budget too).  Each column's result is the same PCG run as a
+ * block solve of that column alone: columns never mix.
+ */
+typedef struct lap_server lap_server;
+
+typedef struct {
+    int64_t tag;               /* the caller's tag */
+    int32_t graph;             /* graph id of the request */
+    int32_t nrhs;
+    int32_t status;            /* worst lap_status of the columns */
+    int32_t iterations_max;    /* PCG iterations of the slowest column */
+    double relres_max;         /* max over columns of ||r|| / ||b^|| (FP64 recursive) */
+    double queue_seconds;      /* submit -> admission */
+    double total_seconds;      /* submit -> result in the caller's buffer */
+} lap_request_result;
+
+/* New server with an HBM budget in bytes (0: no limit).  Errors:
+ * LAP_EINVAL, LAP_ENOMEM, LAP_EDEVICE. */
+lap_status lap_server_create(int64_t hbm_budget_bytes, lap_server **out);
+
+/* Register h (set up with LAP_FLAG_MULTI_RHS, not host-only) under a new
+ * graph id.  The server uses h exclusively until lap_server_destroy; h is
+ * freed by the caller afterwards.  Errors: LAP_EINVAL, LAP_EUNSUPPORTED
+ * (no block solve), LAP_ENOMEM (budget exceeded), LAP_EDEVICE. */
+lap_status lap_server_add(lap_server *srv, lap_hierarchy *h, int32_t *graph_id);
+
+/* Queue a request: nrhs (1..64) right-hand sides of graph `graph`, host
+ * array b (column c at b + c*n, original vertex order), solution written
+ * to the host array x (same layout, mean-free) before the result is
+ * returned by lap_server_poll; both must stay valid until then.  Stop at
+ * ||r|| <= tol ||b^|| per column.  Errors: LAP_EINVAL. */
+lap_status lap_server_submit(lap_server *srv, int32_t graph, const double *b,
+                             double *x, int32_t nrhs, double tol, int64_t tag);
+
+/* Completed requests, at most max, waiting up to wait_ms for the first
+ * one (0: no wait); *count receives how many were written to out. */
+lap_status lap_server_poll(lap_server *srv, lap_request_result *out,
+                           int32_t max, int32_t wait_ms, int32_t *count);
+
+/* Finish every queued request, stop the server thread, release the
+ * server's staging memory (not the hierarchies).  NULL is a no-op. */
+void lap_server_destroy(lap_server *srv);
+
 /* Release the hierarchy and its device memory (NULL is a no-op). */
 void lap_free(lap_hierarchy *h);
 

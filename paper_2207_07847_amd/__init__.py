@@ -55,6 +55,13 @@ class lap_hierarchy_desc(C.Structure):
                 ("nnz", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double)]
 
 
+class lap_request_result(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("graph", C.c_int32), ("nrhs", C.c_int32),
+                ("status", C.c_int32), ("iterations_max", C.c_int32),
+                ("relres_max", C.c_double), ("queue_seconds", C.c_double),
+                ("total_seconds", C.c_double)]
+
+
 def _load():
     # Device buffers come from torch, so the library must run on the same HIP
     # runtime instance: torch ships its own libamdhip64.so.7; importing torch
@@ -79,6 +86,15 @@ def _load():
                                      C.POINTER(C.c_double)]
     L.lap_free.argtypes = [vp]
     L.lap_free.restype = None
+    L.lap_server_create.argtypes = [C.c_int64, C.POINTER(vp)]
+    L.lap_server_add.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+    L.lap_server_submit.argtypes = [vp, C.c_int32, vp, vp, C.c_int32, C.c_double, C.c_int64]
+    L.lap_server_poll.argtypes = [vp, C.POINTER(lap_request_result), C.c_int32, C.c_int32,
+                                  C.POINTER(C.c_int32)]
+    L.lap_server_destroy.argtypes = [vp]
+    L.lap_server_destroy.restype = None
+    for f in ("lap_server_create", "lap_server_add", "lap_server_submit", "lap_server_poll"):
+        getattr(L, f).restype = C.c_int
     L.lap_last_error.argtypes = []
     L.lap_last_error.restype = C.c_char_p
     L.lap_status_str.argtypes = [C.c_int]
@@ -204,3 +220,45 @@ def lap_profile_kernel(h, kernel: int, reps: int, stream=0):
 def lap_free(h) -> None:
     if h:
         _lib.lap_free(C.c_void_p(h))
+
+
+def lap_server_create(hbm_budget_bytes: int = 0):
+    srv = C.c_void_p()
+    st = _lib.lap_server_create(int(hbm_budget_bytes), C.byref(srv))
+    if st != LAP_OK:
+        raise LapError(st, "lap_server_create")
+    return srv.value
+
+
+def lap_server_add(srv, h) -> int:
+    gid = C.c_int32()
+    st = _lib.lap_server_add(C.c_void_p(srv), C.c_void_p(h), C.byref(gid))
+    if st != LAP_OK:
+        raise LapError(st, "lap_server_add")
+    return gid.value
+
+
+def lap_server_submit(srv, graph: int, b_ptr: int, x_ptr: int, nrhs: int, tol: float,
+                      tag: int) -> int:
+    """b_ptr, x_ptr: host addresses (e.g. numpy .ctypes.data), column-major,
+    kept alive by the caller until the result is polled."""
+    return _lib.lap_server_submit(C.c_void_p(srv), int(graph), C.c_void_p(b_ptr),
+                                  C.c_void_p(x_ptr), int(nrhs), float(tol), int(tag))
+
+
+def lap_server_poll(srv, max_results: int = 256, wait_ms: int = 0) -> list:
+    out = (lap_request_result * max(1, max_results))()
+    cnt = C.c_int32()
+    st = _lib.lap_server_poll(C.c_void_p(srv), out, int(max_results), int(wait_ms),
+                              C.byref(cnt))
+    if st != LAP_OK:
+        raise LapError(st, "lap_server_poll")
+    return [dict(tag=o.tag, graph=o.graph, nrhs=o.nrhs, status=o.status,
+                 iterations_max=o.iterations_max, relres_max=o.relres_max,
+                 queue_seconds=o.queue_seconds, total_seconds=o.total_seconds)
+            for o in out[:cnt.value]]
+
+
+def lap_server_destroy(srv) -> None:
+    if srv:
+        _lib.lap_server_destroy(C.c_void_p(srv))

@@ -32,7 +32,20 @@ struct ScalM {
     int32_t done[kCols];     // 0 running, 1 converged, 2 max_iter, 3 breakdown,
                              // 4 bad input, 5 not part of this run
     int32_t iter[kCols];     // products with L performed by the column's run
-    int32_t maxit, first, all_done, pad;
+    int32_t fresh[kCols];    // 1: the next rho finish starts the column's run (beta = 0)
+    int32_t maxit, admit, all_done, pad;   // admit: the next rho finish serves
+                                           // fresh columns only (a column admission)
+};
+
+// Column admission and extraction of the serving loop (device copy, set by
+// the host before it enqueues the kernels that read it): column c takes a
+// new right-hand side from src[c] (input order, FP64) with stop tolerance
+// tol2[c], or hands its mean-free solution to dst[c] (input order); null
+// pointers leave the column alone.
+struct ServeCtl {
+    const double* src[kCols];
+    double* dst[kCols];
+    double tol2[kCols];
 };
 
 // Work items: chunk i covers entries (children) [t0[i], t1[i]) of row (or
@@ -98,7 +111,7 @@ __device__ inline void mm_partial(const double (&v)[NV], double* part) {
     }
 }
 
-enum MmFin { kMmPq, kMmRho, kMmSum, kMmBn2, kMmRes2 };
+enum MmFin { kMmPq, kMmRho, kMmSum, kMmBn2, kMmRes2, kMmAdmit };
 
 // One-block finish: 1024 threads = 16 groups x 64 columns; group g adds the
 // partials of blocks g, g+16, ... of its column, then the groups are added
@@ -108,7 +121,7 @@ enum MmFin { kMmPq, kMmRho, kMmSum, kMmBn2, kMmRes2 };
 template <int OP>
 __global__ __launch_bounds__(1024) void k_mm_finish(int G, int n, const double* __restrict__ part,
                                                     int G2, const double* __restrict__ part2,
-                                                    ScalM* S) {
+                                                    ScalM* S, const ServeCtl* ctl = nullptr) {
     if ((OP == kMmPq || OP == kMmRho) && S->all_done) return;
     constexpr int NV = OP == kMmRho ? 3 : 1;
     constexpr int NG = 16;
@@ -151,9 +164,11 @@ __global__ __launch_bounds__(1024) void k_mm_finish(int G, int n, const double* 
     } else if (OP == kMmRho) {
         const double zbar = t[0] / (double)n;
         const double rho = t[1] - zbar * t[2];
-        if (d == 0) {
+        const int fresh = S->fresh[c];
+        if (d == 0 && (fresh || !S->admit)) {
             S->zbar[c] = zbar;
-            S->beta[c] = S->first ? 0.0 : rho / S->rho[c];
+            S->beta[c] = fresh ? 0.0 : rho / S->rho[c];
+            S->fresh[c] = 0;
             S->rho[c] = rho;
             if (!isfinite(rho)) S->done[c] = 3;
             if (G2 > 0) {
@@ -167,17 +182,24 @@ __global__ __launch_bounds__(1024) void k_mm_finish(int G, int n, const double* 
         // (group 0 is one wavefront: a vote over its lanes)
         const unsigned long long stopped = __ballot(S->done[c] != 0);
         if (c == 0) {
-            S->first = 0;
+            S->admit = 0;
             S->all_done = stopped == ~0ull;
         }
     } else if (OP == kMmSum) {
         S->sum[c] = t[0];
-    } else if (OP == kMmBn2) {
-        S->bn2[c] = t[0];
-        S->rr[c] = t[0];
-        S->iter[c] = 0;
-        S->alpha[c] = S->beta[c] = S->zbar[c] = 0.0;
-        if (S->done[c] != 5) {
+    } else if (OP == kMmBn2 || OP == kMmAdmit) {
+        // kMmBn2: a new run of every column not marked 5; kMmAdmit: a new
+        // run of the columns the serving loop admits, the others untouched
+        const bool start = OP == kMmBn2 ? S->done[c] != 5 : ctl->src[c] != nullptr;
+        if (start || OP == kMmBn2) {
+            S->bn2[c] = t[0];
+            S->rr[c] = t[0];
+            S->iter[c] = 0;
+            S->alpha[c] = S->beta[c] = S->zbar[c] = 0.0;
+            S->fresh[c] = 1;
+        }
+        if (start) {
+            if (OP == kMmAdmit) S->tol2[c] = ctl->tol2[c];
             if (!isfinite(t[0])) S->done[c] = 4;
             else if (t[0] == 0.0) S->done[c] = 1;
             else if (S->maxit <= 0) S->done[c] = 2;
@@ -185,7 +207,7 @@ __global__ __launch_bounds__(1024) void k_mm_finish(int G, int n, const double* 
         }
         const unsigned long long stopped = __ballot(S->done[c] != 0);
         if (c == 0) {
-            S->first = 1;
+            S->admit = OP == kMmAdmit;
             S->all_done = stopped == ~0ull;
         }
     } else if (OP == kMmRes2) {
@@ -568,6 +590,70 @@ __global__ __launch_bounds__(kMmWaves * 64) void k_mm_out(int n, const int32_t* 
         xc[o] = v;
         if (c < nrhs) dst[(size_t)c * ld + (sperm ? sperm[t] : t)] = v;
     }
+}
+
+// ------------------------------------------------------------- serving
+
+// Per-column sums of the admitted right-hand sides (ctl->src, input order).
+__global__ __launch_bounds__(kMmWaves * 64) void k_srv_colsum(int n, const ServeCtl* ctl,
+                                                              double* part) {
+    const int c = threadIdx.x & 63;
+    const double* src = ctl->src[c];
+    double v[1] = {0.0};
+    if (src) {
+        MM_FOR(t, n) v[0] += src[t];
+    }
+    mm_partial<1>(v, part);
+}
+
+// Admitted column c: r = src - mean in tree order (tree row t is input
+// vertex perm0[t]), x = p0 = p1 = 0 (solve order); partial ||r||^2.
+template <class T>
+__global__ __launch_bounds__(kMmWaves * 64) void k_srv_admit(int n, const int32_t* __restrict__ perm0,
+                                                             const ServeCtl* ctl,
+                                                             T* __restrict__ r, T* __restrict__ x,
+                                                             T* __restrict__ p0, T* __restrict__ p1,
+                                                             const ScalM* S, double* part) {
+    const int c = threadIdx.x & 63;
+    const double* src = ctl->src[c];
+    double v[1] = {0.0};
+    if (src) {
+        const double mean = S->sum[c] / (double)n;
+        MM_FOR(t, n) {
+            const size_t o = (size_t)t * kCols + c;
+            const double bt = src[perm0[t]] - mean;
+            r[o] = (T)bt;
+            x[o] = T(0);
+            p0[o] = T(0);
+            p1[o] = T(0);
+            v[0] += bt * bt;
+        }
+    }
+    mm_partial<1>(v, part);
+}
+
+// Extracted column c: dst = x - mean(x) in input order (solve row s is
+// input vertex sperm[s]; sperm null: the same).  Column sums from S->sum.
+template <class T>
+__global__ __launch_bounds__(kMmWaves * 64) void k_srv_extract(int n, const int32_t* __restrict__ sperm,
+                                                               const ServeCtl* ctl,
+                                                               const T* __restrict__ x,
+                                                               const ScalM* S) {
+    const int c = threadIdx.x & 63;
+    double* dst = ctl->dst[c];
+    if (!dst) return;
+    const double mean = S->sum[c] / (double)n;
+    MM_FOR(t, n) dst[sperm ? sperm[t] : t] = (double)x[(size_t)t * kCols + c] - mean;
+}
+
+// Per-column sums of a block vector of type T.
+template <class T>
+__global__ __launch_bounds__(kMmWaves * 64) void k_srv_xsum(int n, const T* __restrict__ x,
+                                                            double* part) {
+    const int c = threadIdx.x & 63;
+    double v[1] = {0.0};
+    MM_FOR(t, n) v[0] += (double)x[(size_t)t * kCols + c];
+    mm_partial<1>(v, part);
 }
 
 }  // namespace lapgpu

@@ -6,12 +6,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "block.hpp"
@@ -839,9 +845,10 @@ void upload_block(lap_hierarchy* h, hipStream_t s) {
 }
 
 template <int OP>
-void finish_m(lap_hierarchy* h, hipStream_t s, ScalM* S, int G, int G2 = 0) {
+void finish_m(lap_hierarchy* h, hipStream_t s, ScalM* S, int G, int G2 = 0,
+              const ServeCtl* ctl = nullptr) {
     hipLaunchKernelGGL(k_mm_finish<OP>, dim3(1), dim3(1024), 0, s, G, (int)h->n,
-                       (const double*)h->partm, G2, (const double*)h->partm2, S);
+                       (const double*)h->partm, G2, (const double*)h->partm2, S, ctl);
 }
 
 // The block preconditioner: level-0 update (when do_update), restriction
@@ -1459,6 +1466,257 @@ lap_status profile_block(lap_hierarchy* h, EngineM<T>& m, int32_t kernel, int32_
     }
 }
 
+// ---------------------------------------------------------------- serving
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct SrvRequest {
+    int64_t tag = 0;
+    int graph = 0, nrhs = 0;
+    double tol = 0.0;
+    const double* b = nullptr;      // caller's host buffers
+    double* x = nullptr;
+    double* db = nullptr;           // device staging: right-hand sides, solutions
+    double* dx = nullptr;
+    double* pin = nullptr;          // pinned staging (b in, then x out)
+    size_t bytes = 0;               // device staging bytes (budget)
+    int cols_left = 0;
+    int32_t it_max = 0;
+    double rel_max = 0.0;
+    lap_status status = LAP_OK;
+    hipEvent_t done_ev = nullptr;
+    double t_submit = 0.0, t_admit = 0.0;
+};
+
+struct SrvLane {
+    lap_hierarchy* h = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;        // end of the chunk in flight (and its status copy)
+    bool busy = false;
+    SrvRequest* slot_req[kCols] = {};
+    int slot_col[kCols] = {};
+    std::deque<SrvRequest*> pending;
+    ServeCtl* dctl = nullptr;       // device
+    ServeCtl* pctl = nullptr;       // pinned, written only after the previous copy ran
+    ScalM* pst = nullptr;           // pinned status copy after each chunk
+};
+
+// Pinned host buffers reused by size (page-locking is slow).
+struct PinPool {
+    std::multimap<size_t, double*> free_;
+    double* get(size_t count) {
+        auto it = free_.lower_bound(count);
+        if (it != free_.end() && it->first <= 2 * count) {
+            double* p = it->second;
+            free_.erase(it);
+            return p;
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, count * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return nullptr;
+        sizes_[p] = count;
+        return static_cast<double*>(p);
+    }
+    void put(double* p) { free_.insert({sizes_[p], p}); }
+    ~PinPool() {
+        for (auto& kv : sizes_) (void)hipHostFree(kv.first);
+    }
+    std::map<void*, size_t> sizes_;
+};
+
+}  // namespace
+
+struct lap_server {
+    int device = 0;
+    int64_t budget = 0;             // 0: unlimited
+    int64_t used = 0;               // resident hierarchies + request staging
+    int64_t resident = 0;           // resident hierarchies
+    std::vector<SrvLane> lanes;
+    std::mutex mu;
+    std::condition_variable cv_out;
+    std::deque<SrvRequest*> inbox, outbox;
+    std::vector<SrvRequest*> copying;
+    int64_t inflight = 0;           // submitted and not yet polled out
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    std::atomic<bool> failed{false};
+    PinPool pins;
+};
+
+namespace {
+
+bool lane_active(const SrvLane& L) {
+    for (int c = 0; c < kCols; ++c)
+        if (L.slot_req[c]) return true;
+    return false;
+}
+
+// One chunk boundary of a lane: hand out stopped columns, admit queued
+// requests, launch the next chunk if any column is running.
+void srv_boundary(lap_server* S, SrvLane& L) {
+    lap_hierarchy* h = L.h;
+    EngineM<double>& m = h->m64;
+    const int n = (int)h->n, gn = mm_grid(n);
+    const ScalM& st = *L.pst;
+    ServeCtl& ctl = *L.pctl;
+    std::memset(&ctl, 0, sizeof(ServeCtl));
+    bool extract = false, admit = false;
+    std::vector<SrvRequest*> touched;
+    for (int c = 0; c < kCols; ++c) {
+        SrvRequest* r = L.slot_req[c];
+        if (!r || st.done[c] == 0) continue;
+        const int j = L.slot_col[c];
+        ctl.dst[c] = r->dx + (size_t)j * n;
+        r->it_max = std::max(r->it_max, st.iter[c]);
+        const double rel = st.bn2[c] > 0 ? std::sqrt(st.rr[c] / st.bn2[c]) : 0.0;
+        r->rel_max = std::max(r->rel_max, rel);
+        const lap_status cs = to_status(st.done[c]);
+        if (rank_status(cs) > rank_status(r->status)) r->status = cs;
+        L.slot_req[c] = nullptr;
+        if (--r->cols_left == 0) touched.push_back(r);
+        extract = true;
+    }
+    // admission: whole requests, first come first served, while slots and
+    // the HBM budget allow
+    int nfree = 0;
+    for (int c = 0; c < kCols; ++c) nfree += L.slot_req[c] == nullptr;
+    std::vector<SrvRequest*> admitted;
+    while (!L.pending.empty()) {
+        SrvRequest* r = L.pending.front();
+        if (r->nrhs > nfree) break;
+        const size_t bytes = 2 * (size_t)n * r->nrhs * sizeof(double);
+        // over budget: wait for running requests to finish (a request that
+        // would not fit even alone is admitted once nothing else runs)
+        if (S->budget > 0 && S->used + (int64_t)bytes > S->budget && S->used > S->resident)
+            break;
+        void* db = nullptr;
+        if (hipMallocAsync(&db, bytes, L.s) != hipSuccess) break;
+        r->db = static_cast<double*>(db);
+        r->dx = r->db + (size_t)n * r->nrhs;
+        r->bytes = bytes;
+        S->used += (int64_t)bytes;
+        r->pin = S->pins.get((size_t)n * r->nrhs);
+        std::memcpy(r->pin, r->b, (size_t)n * r->nrhs * sizeof(double));
+        HIPCHK(hipMemcpyAsync(r->db, r->pin, (size_t)n * r->nrhs * sizeof(double),
+                              hipMemcpyHostToDevice, L.s));
+        r->t_admit = now_s();
+        int j = 0;
+        for (int c = 0; c < kCols && j < r->nrhs; ++c) {
+            if (L.slot_req[c]) continue;
+            L.slot_req[c] = r;
+            L.slot_col[c] = j;
+            ctl.src[c] = r->db + (size_t)j * n;
+            ctl.tol2[c] = r->tol * r->tol;
+            ++j;
+        }
+        r->cols_left = r->nrhs;
+        nfree -= r->nrhs;
+        L.pending.pop_front();
+        admitted.push_back(r);
+        admit = true;
+    }
+    if (extract || admit)
+        HIPCHK(hipMemcpyAsync(L.dctl, L.pctl, sizeof(ServeCtl), hipMemcpyHostToDevice, L.s));
+    if (extract) {
+        hipLaunchKernelGGL(k_srv_xsum<double>, dim3(gn), dim3(kMmWaves * 64), 0, L.s, n,
+                           (const double*)m.x, h->partm);
+        finish_m<kMmSum>(h, L.s, h->Sm, gn);
+        hipLaunchKernelGGL(k_srv_extract<double>, dim3(gn), dim3(kMmWaves * 64), 0, L.s, n,
+                           h->sperm, (const ServeCtl*)L.dctl, (const double*)m.x,
+                           (const ScalM*)h->Sm);
+        for (SrvRequest* r : touched) {
+            // every column of r has been extracted: copy out, then done
+            HIPCHK(hipMemcpyAsync(r->pin, r->dx, (size_t)n * r->nrhs * sizeof(double),
+                                  hipMemcpyDeviceToHost, L.s));
+            HIPCHK(hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(r->done_ev, L.s));
+            HIPCHK(hipFreeAsync(r->db, L.s));
+            S->copying.push_back(r);
+        }
+    }
+    if (admit) {
+        hipLaunchKernelGGL(k_srv_colsum, dim3(gn), dim3(kMmWaves * 64), 0, L.s, n,
+                           (const ServeCtl*)L.dctl, h->partm);
+        finish_m<kMmSum>(h, L.s, h->Sm, gn);
+        hipLaunchKernelGGL(k_srv_admit<double>, dim3(gn), dim3(kMmWaves * 64), 0, L.s, n,
+                           (const int32_t*)h->perm0, (const ServeCtl*)L.dctl, m.lv[0].r, m.x,
+                           m.p[0], m.p[1], (const ScalM*)h->Sm, h->partm);
+        finish_m<kMmAdmit>(h, L.s, h->Sm, gn, 0, (const ServeCtl*)L.dctl);
+        enqueue_mm_precond(h, m, L.s, 0, (const double*)m.p[0]);
+    }
+    HIPCHK(hipGetLastError());
+    if (lane_active(L)) {
+        HIPCHK(hipGraphLaunch(m.exec, L.s));
+        HIPCHK(hipMemcpyAsync(L.pst, h->Sm, sizeof(ScalM), hipMemcpyDeviceToHost, L.s));
+        HIPCHK(hipEventRecord(L.ev, L.s));
+        L.busy = true;
+    }
+}
+
+void srv_loop(lap_server* S) {
+    (void)hipSetDevice(S->device);
+    try {
+        while (true) {
+            bool work = false;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                while (!S->inbox.empty()) {
+                    SrvRequest* r = S->inbox.front();
+                    S->inbox.pop_front();
+                    S->lanes[r->graph].pending.push_back(r);
+                }
+            }
+            for (SrvLane& L : S->lanes) {
+                if (L.busy) {
+                    work = true;
+                    if (hipEventQuery(L.ev) != hipSuccess) continue;
+                    L.busy = false;
+                }
+                if (lane_active(L) || !L.pending.empty()) {
+                    work = true;
+                    srv_boundary(S, L);
+                }
+            }
+            for (size_t i = 0; i < S->copying.size();) {
+                SrvRequest* r = S->copying[i];
+                work = true;
+                if (hipEventQuery(r->done_ev) != hipSuccess) {
+                    ++i;
+                    continue;
+                }
+                const size_t cnt = (size_t)S->lanes[r->graph].h->n * r->nrhs;
+                std::memcpy(r->x, r->pin, cnt * sizeof(double));
+                S->pins.put(r->pin);
+                (void)hipEventDestroy(r->done_ev);
+                S->used -= (int64_t)r->bytes;
+                S->copying[i] = S->copying.back();
+                S->copying.pop_back();
+                {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    S->outbox.push_back(r);
+                }
+                S->cv_out.notify_all();
+            }
+            if (!work) {
+                if (S->stop.load()) {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    if (S->inbox.empty()) break;
+                    continue;
+                }
+                std::this_thread::sleep_for(std::chrono::microseconds(50));
+            } else {
+                std::this_thread::yield();
+            }
+        }
+    } catch (const HipErr&) {
+        S->failed.store(true);
+        S->cv_out.notify_all();
+    }
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -1663,6 +1921,126 @@ lap_status lap_export_graph(const lap_hierarchy* h, int32_t level, int64_t* ptr,
         for (int64_t k = 0; k < g.nnz(); ++k) col[k] = g.col[k];
     if (w) std::memcpy(w, g.w.data(), g.w.size() * sizeof(double));
     return LAP_OK;
+}
+
+lap_status lap_server_create(int64_t hbm_budget_bytes, lap_server** out) {
+    if (!out || hbm_budget_bytes < 0) return LAP_EINVAL;
+    *out = nullptr;
+    lap_server* S = new (std::nothrow) lap_server();
+    if (!S) return LAP_ENOMEM;
+    S->budget = hbm_budget_bytes;
+    if (hipGetDevice(&S->device) != hipSuccess) {
+        delete S;
+        return LAP_EDEVICE;
+    }
+    *out = S;
+    return LAP_OK;
+}
+
+lap_status lap_server_add(lap_server* S, lap_hierarchy* h, int32_t* graph_id) {
+    if (!S || !h || !graph_id) return LAP_EINVAL;
+    if (h->host_only || !h->has_block) return LAP_EUNSUPPORTED;
+    if (S->worker.joinable()) return LAP_EINVAL;        // before the first submit only
+    if (S->budget > 0 && S->used + h->dev_bytes > S->budget) return LAP_ENOMEM;
+    SrvLane L;
+    L.h = h;
+    try {
+        HIPCHK(hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
+        L.dctl = h->dalloc<ServeCtl>(1);
+        HIPCHK(hipHostMalloc((void**)&L.pctl, sizeof(ServeCtl), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&L.pst, sizeof(ScalM), hipHostMallocDefault));
+        std::memset(L.pctl, 0, sizeof(ServeCtl));
+        std::memset(L.pst, 0, sizeof(ScalM));
+        // all slots idle: a ScalM with every column stopped
+        ScalM& st = *h->stagem;
+        std::memset(&st, 0, sizeof(ScalM));
+        for (int c = 0; c < kCols; ++c) st.done[c] = 5;
+        st.maxit = h->params.max_iter;
+        st.all_done = 1;
+        HIPCHK(hipMemcpyAsync(h->Sm, &st, sizeof(ScalM), hipMemcpyHostToDevice, L.s));
+        HIPCHK(hipStreamSynchronize(L.s));
+    } catch (const std::bad_alloc&) {
+        return LAP_ENOMEM;
+    } catch (const HipErr&) {
+        return LAP_EDEVICE;
+    }
+    S->used += h->dev_bytes;
+    S->resident += h->dev_bytes;
+    *graph_id = (int32_t)S->lanes.size();
+    S->lanes.push_back(L);
+    return LAP_OK;
+}
+
+lap_status lap_server_submit(lap_server* S, int32_t graph, const double* b, double* x,
+                             int32_t nrhs, double tol, int64_t tag) {
+    if (!S || !b || !x || graph < 0 || graph >= (int32_t)S->lanes.size() || nrhs < 1 ||
+        nrhs > kCols || !(tol > 0.0) || !std::isfinite(tol))
+        return LAP_EINVAL;
+    if (S->failed.load()) return LAP_EDEVICE;
+    SrvRequest* r = new (std::nothrow) SrvRequest();
+    if (!r) return LAP_ENOMEM;
+    r->tag = tag;
+    r->graph = graph;
+    r->nrhs = nrhs;
+    r->tol = tol;
+    r->b = b;
+    r->x = x;
+    r->t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->inbox.push_back(r);
+        ++S->inflight;
+        if (!S->worker.joinable()) S->worker = std::thread(srv_loop, S);
+    }
+    return LAP_OK;
+}
+
+lap_status lap_server_poll(lap_server* S, lap_request_result* out, int32_t max, int32_t wait_ms,
+                           int32_t* count) {
+    if (!S || !count || max < 0 || (max > 0 && !out)) return LAP_EINVAL;
+    *count = 0;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (wait_ms > 0 && S->outbox.empty())
+        S->cv_out.wait_for(lk, std::chrono::milliseconds(wait_ms),
+                           [&] { return !S->outbox.empty() || S->failed.load(); });
+    if (S->failed.load() && S->outbox.empty()) return LAP_EDEVICE;
+    int32_t k = 0;
+    while (k < max && !S->outbox.empty()) {
+        SrvRequest* r = S->outbox.front();
+        S->outbox.pop_front();
+        lap_request_result& o = out[k++];
+        o.tag = r->tag;
+        o.graph = r->graph;
+        o.nrhs = r->nrhs;
+        o.status = r->status;
+        o.iterations_max = r->it_max;
+        o.relres_max = r->rel_max;
+        o.queue_seconds = r->t_admit - r->t_submit;
+        o.total_seconds = now_s() - r->t_submit;
+        --S->inflight;
+        delete r;
+    }
+    *count = k;
+    return LAP_OK;
+}
+
+void lap_server_destroy(lap_server* S) {
+    if (!S) return;
+    S->stop.store(true);
+    if (S->worker.joinable()) S->worker.join();
+    for (SrvLane& L : S->lanes) {
+        if (L.s) {
+            (void)hipStreamSynchronize(L.s);
+            (void)hipStreamDestroy(L.s);
+        }
+        if (L.ev) (void)hipEventDestroy(L.ev);
+        if (L.pctl) (void)hipHostFree(L.pctl);
+        if (L.pst) (void)hipHostFree(L.pst);
+        for (SrvRequest* r : L.pending) delete r;
+    }
+    for (SrvRequest* r : S->outbox) delete r;
+    delete S;
 }
 
 void lap_free(lap_hierarchy* h) { delete h; }
