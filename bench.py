@@ -147,6 +147,151 @@ def measure(lap, h, bd, xd, n, tol, steps, warmup, sh, stream, capped, nrhs=1):
     return dict(elapsed=elapsed, lat=lat, info=inf)
 
 
+def serve_pool(count, n_min, n_max, seed):
+    """Graphs of the serving stream: half 2D/3D grids (log-uniform weights),
+    half Chung-Lu (mean degree 16, exponent 2.1, U(0,1] weights), sizes
+    log-uniform in [n_min, n_max]."""
+    import numpy as np
+
+    import workloads as W
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(count):
+        target = float(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+        if i % 2 == 0:
+            if i % 4 == 0:
+                a = max(4, int(round(target ** 0.5)))
+                n, u, v = W.grid2d(a)
+            else:
+                a = max(3, int(round(target ** (1 / 3))))
+                n, u, v = W.grid3d(a)
+            w = W.loguniform_weights(len(u), seed + i)
+            kind = "grid"
+        else:
+            n, u, v = W.chung_lu(max(64, int(target)), 16.0, 2.1, seed + i)
+            w = W.uniform01_weights(len(u), seed + 1000 + i)
+            kind = "chung-lu"
+        pool.append(dict(n=n, u=u, v=v, w=w, kind=kind))
+    return pool
+
+
+def serve(args):
+    """Serving stream: Poisson arrivals of requests (1-16 Gaussian right-hand
+    sides, tol 1e-6 or 1e-8) over a pool of resident hierarchies, through
+    the continuous-batching server; latency per request, throughput in
+    right-hand sides solved per second."""
+    import numpy as np
+    import torch
+
+    import paper_2207_07847_amd as lap
+
+    torch.cuda.set_device(0)
+    sh = torch.cuda.current_stream().cuda_stream
+    t0 = time.time()
+    pool = serve_pool(args.serve_graphs, args.serve_nmin, args.serve_nmax, 20220715 + 7)
+    log(f"pool: {len(pool)} graphs, n {min(g['n'] for g in pool)}..{max(g['n'] for g in pool)} "
+        f"({time.time() - t0:.1f}s)")
+    t0 = time.time()
+    hs = []
+    for g in pool:
+        p = lap.lap_default_params(mu=0.8, max_iter=20000, flags=lap.LAP_FLAG_MULTI_RHS)
+        hs.append(lap.lap_setup(g["n"], g["u"], g["v"], g["w"], p, sh))
+    torch.cuda.synchronize()
+    resident = sum(lap.lap_hierarchy_info(h)["device_bytes"] for h in hs)
+    log(f"setup {time.time() - t0:.1f}s, resident {resident / 2**30:.1f} GiB")
+    rng = np.random.default_rng(20220715 + 8)
+    reqs = []
+    for k in range(args.serve_requests):
+        gi = int(rng.integers(len(pool)))
+        m = int(rng.integers(1, 17))
+        tol = 1e-8 if rng.random() < 0.5 else 1e-6
+        b = rng.standard_normal((m, pool[gi]["n"]))
+        reqs.append(dict(g=gi, b=b, x=np.empty_like(b), tol=tol, m=m))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, len(reqs)))
+    # plain FP64 single solves of a sample of the requests' columns, on the
+    # same hierarchies before they are handed to the server
+    sample = reqs[:args.serve_compare]
+    cols = 0
+    t0 = time.perf_counter()
+    for r in sample:
+        g = pool[r["g"]]
+        for j in range(r["m"]):
+            bd = torch.tensor(r["b"][j], dtype=torch.float64, device="cuda")
+            xd = torch.empty_like(bd)
+            st, _ = lap.lap_solve(hs[r["g"]], bd.data_ptr(), xd.data_ptr(), g["n"], r["tol"],
+                                  stream=sh)
+            cols += 1
+    torch.cuda.synchronize()
+    single_rate = cols / (time.perf_counter() - t0)
+    log(f"plain FP64 single solves: {cols} right-hand sides, {single_rate:.1f} /s")
+    srv = lap.lap_server_create(args.serve_budget_gib * 2**30 if args.serve_budget_gib else 0)
+    gids = [lap.lap_server_add(srv, h) for h in hs]
+    res = {}
+    t_start = time.perf_counter()
+    t_log = t_start
+    k = 0
+    while len(res) < len(reqs):
+        now = time.perf_counter() - t_start
+        if time.perf_counter() - t_log > 5.0:
+            t_log = time.perf_counter()
+            log(f"  {now:6.1f}s: submitted {k}, completed {len(res)}")
+        while k < len(reqs) and arrivals[k] <= now:
+            r = reqs[k]
+            st = lap.lap_server_submit(srv, gids[r["g"]], r["b"].ctypes.data, r["x"].ctypes.data,
+                                       r["m"], r["tol"], k)
+            if st != 0:
+                raise SystemExit(f"submit failed: {lap.lap_status_str(st)}")
+            k += 1
+        for o in lap.lap_server_poll(srv, 512, 1 if k == len(reqs) else 0):
+            res[o["tag"]] = o
+        if k < len(reqs) and arrivals[k] > now:
+            time.sleep(min(0.0005, arrivals[k] - now))
+    elapsed = time.perf_counter() - t_start
+    lap.lap_server_destroy(srv)
+    for h in hs:
+        lap.lap_free(h)
+    lat = np.array([res[i]["total_seconds"] for i in range(len(reqs))]) * 1e3
+    qlat = np.array([res[i]["queue_seconds"] for i in range(len(reqs))]) * 1e3
+    bad = [i for i in range(len(reqs)) if res[i]["status"] != 0]
+    ncols = sum(r["m"] for r in reqs)
+    worst = max(res[i]["relres_max"] / reqs[i]["tol"] for i in range(len(reqs)))
+    log(f"served {len(reqs)} requests ({ncols} right-hand sides) in {elapsed:.2f}s, "
+        f"p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms, "
+        f"failed {len(bad)}, worst relres/tol {worst:.3f}")
+    line = {
+        "metric": METRIC,
+        "value": ncols / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 0,
+        "ms_per_step": elapsed / len(reqs) * 1e3,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"serving stream: {len(reqs)} requests, Poisson arrivals at "
+                        f"{args.serve_rate:g}/s, {len(pool)} graphs (half 2D/3D grids, half "
+                        f"Chung-Lu) of {args.serve_nmin}..{args.serve_nmax} vertices, 1-16 "
+                        f"Gaussian RHS per request, tol 1e-6 or 1e-8, MSP mu=0.8, FP64",
+            "right_hand_sides": ncols, "resident_gib": resident / 2**30,
+            "failed_requests": len(bad), "worst_relres_over_tol": worst,
+        },
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "queue_p50_ms": float(np.percentile(qlat, 50)),
+        "queue_p99_ms": float(np.percentile(qlat, 99)),
+        "requests_per_s": len(reqs) / elapsed,
+        "fp64_same_gpu": {"value": single_rate, "unit": "solves/s",
+                          "what": f"plain FP64 PCG, one right-hand side per solve, "
+                                  f"{cols} columns of the first {len(sample)} requests"},
+        "speedup_vs_fp64": (ncols / elapsed) / single_rate,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +310,16 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=100)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="the serving stream instead of single solves")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=400.0, help="arrivals per second")
+    ap.add_argument("--serve-graphs", type=int, default=32)
+    ap.add_argument("--serve-nmin", type=int, default=1000)
+    ap.add_argument("--serve-nmax", type=int, default=1000000)
+    ap.add_argument("--serve-budget-gib", type=float, default=0.0)
+    ap.add_argument("--serve-compare", type=int, default=20,
+                    help="requests whose columns are also timed as single FP64 solves")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="cap per solve (profiling runs); a capped solve is not a valid step")
     args = ap.parse_args()
@@ -172,6 +327,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve is "
               f"not sharded across GPUs in this build.", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve(args)
+        return
 
     import numpy as np
     import torch

@@ -55,7 +55,7 @@ def positive_part(Gt):
 class PEGP:
     """z = P(mu) pinv(L_H~) P(mu)^T r (mean-free) for a fixed hierarchy."""
 
-    def __init__(self, n, u, v, w, aggs, mu):
+    def __init__(self, n, u, v, w, aggs, mu, permc_spec="COLAMD"):
         self.n = int(n)
         self.mu = float(mu)
         L = laplacian_sparse(n, np.asarray(u), np.asarray(v), w)
@@ -68,7 +68,9 @@ class PEGP:
         D = sp.diags(self.d)
         S = (D @ self.Ht @ D).tocsc()
         self.nt = S.shape[0]
-        self._lu = spla.splu(S[:-1, :-1].tocsc())
+        # permc_spec: the fill ordering of the sparse LU (any ordering gives
+        # the same solve up to rounding; tests use two to measure that spread)
+        self._lu = spla.splu(S[:-1, :-1].tocsc(), permc_spec=permc_spec)
 
     @property
     def nnz_ht(self):

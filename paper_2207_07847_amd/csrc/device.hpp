@@ -1045,6 +1045,127 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(int n, const int32_t* __r
     block_partial<1>(v, part);
 }
 
+// ------------------------------------------------------------------ PEGP
+
+// Rows [r0, r1) of one level of a level-scheduled triangular solve on the
+// LDS vector f: f[v] = f[v] * (scale ? 1/d_v : 1) - sum_k val[k] f[col[k]]
+// over row v's entries.  Many rows: a thread each; few rows: a wavefront
+// each; one long row: the whole block.
+__device__ inline void pegp_rows(double* f, const int32_t* __restrict__ rows,
+                                 const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                 const double* __restrict__ val, int r0, int r1, double* red) {
+    const int nr = r1 - r0, tid = threadIdx.x;
+    const int wid = tid >> 6, lane = tid & 63;
+    constexpr int NW = kPegpThreads / 64;
+    if (nr == 1 && ptr[r0 + 1] - ptr[r0] > 256) {
+        const int v = rows[r0];
+        double acc = 0.0;
+        for (int k = ptr[r0] + tid; k < ptr[r0 + 1]; k += kPegpThreads) acc += val[k] * f[col[k]];
+        acc = wave_sum1(acc);
+        if (lane == 0) red[wid] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < NW; ++w) t += red[w];
+            f[v] -= t;
+        }
+    } else if (nr <= NW) {
+        if (wid < nr) {
+            const int r = r0 + wid, v = rows[r];
+            double acc = 0.0;
+            for (int k = ptr[r] + lane; k < ptr[r + 1]; k += 64) acc += val[k] * f[col[k]];
+            acc = wave_sum1(acc);
+            if (lane == 0) f[v] -= acc;
+        }
+    } else {
+        for (int r = r0 + tid; r < r1; r += kPegpThreads) {
+            const int v = rows[r];
+            double acc = 0.0;
+            for (int k = ptr[r]; k < ptr[r + 1]; ++k) acc += val[k] * f[col[k]];
+            f[v] -= acc;
+        }
+    }
+    __syncthreads();
+}
+
+// z = P(mu) S^-1 D P(mu)^T r with S = D L_H~ D grounded (Sec. 3.1-3.2),
+// then mean removed, in one workgroup: restriction sums up the tree, signs
+// (-1)^k (D P(mu)^T = (-1)^k times the plain sums on level k), forward
+// solve, diagonal, backward solve, signs, prolongation down the tree.  Writes
+// z (tree order) and zn (solve order, tree position t at perm[t]) and does
+// the finish step of the rho / zbar / beta reductions itself.
+__global__ __launch_bounds__(kPegpThreads) void k_pegp(PegpDev P,
+                                                       const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ r,
+                                                       double* __restrict__ z,
+                                                       double* __restrict__ zn, Scal* S) {
+    if (S->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* f = reinterpret_cast<double*>(smem);
+    __shared__ double red[3 * (kPegpThreads / 64)];
+    const int tid = threadIdx.x, nth = kPegpThreads;
+    const int n0 = P.off[1] - P.off[0], T = P.nlev - 1;
+    for (int t = tid; t < n0; t += nth) f[t] = r[t];
+    __syncthreads();
+    for (int k = 0; k < T; ++k) {
+        const int nc = P.off[k + 2] - P.off[k + 1];
+        const int32_t* cp = P.cptr[k];
+        const double* fk = f + P.off[k];
+        double* fk1 = f + P.off[k + 1];
+        for (int J = tid; J < nc; J += nth) {
+            double s = 0.0;
+            for (int t = cp[J]; t < cp[J + 1]; ++t) s += fk[t];
+            fk1[J] = s;
+        }
+        __syncthreads();
+    }
+    for (int k = 1; k <= T; k += 2)
+        for (int e = P.off[k] + tid; e < P.off[k + 1]; e += nth) f[e] = -f[e];
+    __syncthreads();
+    if (tid == 0) f[P.ground] = 0.0;
+    __syncthreads();
+    for (int l = 0; l < P.nflev; ++l)
+        pegp_rows(f, P.frow, P.fptr, P.fcol, P.fval, P.flev[l], P.flev[l + 1], red);
+    for (int e = tid; e < P.nt; e += nth)
+        if (e != P.ground) f[e] /= P.diag[e];
+    __syncthreads();
+    for (int l = 0; l < P.nblev; ++l)
+        pegp_rows(f, P.brow, P.bptr, P.bcol, P.bval, P.blev[l], P.blev[l + 1], red);
+    for (int k = 1; k <= T; k += 2)
+        for (int e = P.off[k] + tid; e < P.off[k + 1]; e += nth) f[e] = -f[e];
+    __syncthreads();
+    for (int k = T - 1; k >= 0; --k) {
+        const int nc = P.off[k + 2] - P.off[k + 1];
+        const int32_t* cp = P.cptr[k];
+        double* fk = f + P.off[k];
+        const double* fk1 = f + P.off[k + 1];
+        for (int J = tid; J < nc; J += nth) {
+            const double y = fk1[J];
+            for (int t = cp[J]; t < cp[J + 1]; ++t) fk[t] += y;
+        }
+        __syncthreads();
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = tid; t < n0; t += nth) {
+        const double zt = f[t], rt = r[t];
+        z[t] = zt;
+        zn[perm ? perm[t] : t] = zt;
+        v[0] += zt;
+        v[1] += rt * zt;
+        v[2] += rt;
+    }
+    block_sum<3, kPegpThreads>(v, red);
+    if (tid == 0) {
+        const double zbar = v[0] / (double)n0;
+        const double rho = v[1] - zbar * v[2];
+        S->zbar = zbar;
+        if (!isfinite(rho)) S->done = 3;
+        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->first = 0;
+        S->rho = rho;
+    }
+}
+
 // A fixed non-constant vector (kCols columns per row when cols > 1), the
 // start of timing runs: v = ((i * 2654435761) mod 1024) / 1024 - 1/2.
 __global__ __launch_bounds__(kBlock) void k_pattern(int64_t count, double* __restrict__ dst) {

@@ -177,4 +177,21 @@ struct Sell {
     const T* hw;
 };
 
+// PEGP on the device (one workgroup, expanded vector in LDS): the factored
+// grounded system of PegpPlan (setup.hpp) and the tree links for the
+// restriction and prolongation of P(mu).
+constexpr int kPegpThreads = 1024;
+constexpr int kPegpMaxLevels = 64;
+constexpr int kPegpMaxNodes = 19456;     // expanded nodes held in LDS (152 KB)
+struct PegpDev {
+    int32_t nt, nlev, ground, nflev, nblev;
+    int32_t off[kPegpMaxLevels + 1];     // level -> first expanded index
+    const int32_t* cptr[kPegpMaxLevels]; // children ranges of level k+1 nodes
+    const double* diag;
+    const int32_t *flev, *frow, *fptr, *fcol;
+    const double* fval;
+    const int32_t *blev, *brow, *bptr, *bcol;
+    const double* bval;
+};
+
 }  // namespace lapgpu

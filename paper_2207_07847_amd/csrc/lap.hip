@@ -18,6 +18,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "block.hpp"
@@ -367,6 +368,10 @@ struct lap_hierarchy {
     bool with_msp = true;
     bool mixed = false;          // solves use mixed precision
     bool has_fp32 = false;       // the FP32 engine exists
+    bool pegp = false;           // preconditioner: PEGP (FP64 solves only)
+    PegpPlan pegp_plan;
+    PegpDev pegp_dev{};
+    size_t pegp_lds = 0;
     int64_t n = 0;
     int device = 0;
     double setup_seconds = 0.0;
@@ -488,6 +493,18 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
     const int Tl = h->plan.nlev() - 1;
     const int n = (int)h->n;
     Scal* S = h->S;
+    if constexpr (std::is_same<T, double>::value) {
+        if (h->pegp) {
+            if (do_update) {
+                hipLaunchKernelGGL(k_update_none<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n,
+                                   h->t2s, e.x, e.r, pcur, (const T*)e.q, S, h->part2);
+                finish<kFinRr>(h, s, S, nblk(n), 0, h->part2);
+            }
+            hipLaunchKernelGGL(k_pegp, dim3(1), dim3(kPegpThreads), h->pegp_lds, s, h->pegp_dev,
+                               h->t2s, (const double*)e.r, e.z, e.zn, S);
+            return;
+        }
+    }
     if (!h->with_msp || Tl == 0) {
         if (do_update) {
             hipLaunchKernelGGL(k_update_none<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s,
@@ -732,11 +749,41 @@ void upload_engine(lap_hierarchy* h, Engine<T>& e, hipStream_t s, bool with_leve
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGrpLdsBytes));
 }
 
+// The factored PEGP system on the device.
+void upload_pegp(lap_hierarchy* h, hipStream_t s) {
+    const PegpPlan& G = h->pegp_plan;
+    const HostPlan& P = h->plan;
+    PegpDev& d = h->pegp_dev;
+    d.nt = G.nt;
+    d.nlev = P.nlev();
+    d.ground = G.ground;
+    for (int k = 0; k <= d.nlev; ++k) d.off[k] = G.off[k];
+    for (int k = 0; k + 1 < d.nlev; ++k) d.cptr[k] = h->cptr[k];
+    d.diag = h->upload(G.diag, s);
+    d.nflev = (int32_t)G.flev.size() - 1;
+    d.flev = h->upload(G.flev, s);
+    d.frow = h->upload(G.frow, s);
+    d.fptr = h->upload(G.fptr, s);
+    d.fcol = h->upload(G.fcol, s);
+    d.fval = h->upload(G.fval, s);
+    d.nblev = (int32_t)G.blev.size() - 1;
+    d.blev = h->upload(G.blev, s);
+    d.brow = h->upload(G.brow, s);
+    d.bptr = h->upload(G.bptr, s);
+    d.bcol = h->upload(G.bcol, s);
+    d.bval = h->upload(G.bval, s);
+    h->pegp_lds = (size_t)G.nt * sizeof(double);
+    HIPCHK(hipFuncSetAttribute((const void*)k_pegp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)h->pegp_lds));
+}
+
 void upload_plan(lap_hierarchy* h, hipStream_t s) {
     const int64_t n = h->n;
     h->with_msp = (h->params.precond == LAP_PREC_MSP);
+    h->pegp = (h->params.precond == LAP_PREC_PEGP);
     h->mixed = (h->params.precision == LAP_MIXED_FP32_FP64);
     upload_shared(h, s);
+    if (h->pegp) upload_pegp(h, s);
     // a mixed-precision hierarchy carries the FP64 solve as well
     // (lap_set_precision switches between them)
     upload_engine(h, h->e64, s, h->with_msp);
@@ -1754,9 +1801,13 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
     if (!out) return LAP_EINVAL;
     *out = nullptr;
     if (!g || !p || !g->u || !g->v || !g->w) return LAP_EINVAL;
-    if (p->precond != LAP_PREC_MSP && p->precond != LAP_PREC_NONE)
-        return p->precond == LAP_PREC_PEGP ? LAP_EUNSUPPORTED : LAP_EINVAL;
+    if (p->precond != LAP_PREC_MSP && p->precond != LAP_PREC_NONE && p->precond != LAP_PREC_PEGP)
+        return LAP_EINVAL;
     if (p->precision != LAP_FP64 && p->precision != LAP_MIXED_FP32_FP64) return LAP_EINVAL;
+    // PEGP: FP64 single solves only
+    if (p->precond == LAP_PREC_PEGP &&
+        (p->precision != LAP_FP64 || (p->flags & LAP_FLAG_MULTI_RHS)))
+        return LAP_EUNSUPPORTED;
     if (p->max_iter < 0) return LAP_EINVAL;
     const auto t0 = std::chrono::steady_clock::now();
     lap_hierarchy* h = new (std::nothrow) lap_hierarchy();
@@ -1764,13 +1815,28 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
     h->params = *p;
     h->host_only = (p->flags & LAP_FLAG_HOST_ONLY) != 0;
     try {
+        // only the MSP solves the top level on chip (a dense pseudo-inverse)
+        const bool any_top = h->host_only || p->precond != LAP_PREC_MSP;
         const int rc = build_plan(g->n, g->m, g->u, g->v, g->w, p->mu, p->max_levels, p->n_top,
-                                  p->mwm_seed, h->host_only, h->plan);
+                                  p->mwm_seed, any_top, h->plan);
         if (rc != kOk) {
             delete h;
             return (lap_status)rc;
         }
         h->n = g->n;
+        if (p->precond == LAP_PREC_PEGP) {
+            int64_t nt = 0;
+            for (int k = 0; k < h->plan.nlev(); ++k) nt += h->plan.lv[k].g.n;
+            if (nt > kPegpMaxNodes || h->plan.nlev() > kPegpMaxLevels) {
+                delete h;
+                return LAP_EUNSUPPORTED;
+            }
+            const int prc = build_pegp(h->plan, p->mu, h->pegp_plan);
+            if (prc != kOk) {
+                delete h;
+                return (lap_status)prc;
+            }
+        }
         if (!h->host_only) {
             int ndev = 0;
             if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <unordered_map>
 
 namespace lapgpu {
 
@@ -259,7 +260,7 @@ static double level_theta(double mu, int k) {
 
 int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                const double* w, double mu, int max_levels, int64_t n_top,
-               uint64_t seed, bool host_only, HostPlan& plan) {
+               uint64_t seed, bool any_top, HostPlan& plan) {
     if (!(mu > 0.0 && mu < 1.0) || n_top < 2 || max_levels < 0) return kInval;
     plan = HostPlan();
     plan.mu = mu;
@@ -290,7 +291,7 @@ int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
     }
     const int L = plan.nlev();
     const int T = L - 1;
-    if (plan.lv[T].g.n > kTopMax && !host_only) return kUnsupported;
+    if (plan.lv[T].g.n > kTopMax && !any_top) return kUnsupported;
 
     // 2. tree numbering, top level first
     plan.perm.assign(L, {});
@@ -524,6 +525,193 @@ void build_sell(const Adjacency& g, HostPlan& plan) {
         }
     }
     if (in_blk > 0) plan.heavy_blk.push_back((int32_t)heavy.size());
+}
+
+// ------------------------------------------------------------------ PEGP
+
+int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
+    const int L = P.nlev();
+    const int T = L - 1;
+    out = PegpPlan();
+    out.off.assign(L + 1, 0);
+    for (int k = 0; k < L; ++k) out.off[k + 1] = out.off[k] + (int32_t)P.lv[k].g.n;
+    const int32_t nt = out.off[L];
+    out.nt = nt;
+    // parent (tree numbering) of every node of levels 0..T-1
+    std::vector<std::vector<int32_t>> par(T);
+    for (int k = 0; k < T; ++k) {
+        par[k].resize(P.lv[k].g.n);
+        const std::vector<int32_t>& cp = P.step[k].cptr;
+        for (size_t J = 0; J + 1 < cp.size(); ++J)
+            for (int32_t t = cp[J]; t < cp[J + 1]; ++t) par[k][t] = (int32_t)J;
+    }
+    auto lev = [&](int32_t e) {
+        return (int)(std::upper_bound(out.off.begin(), out.off.end(), e) - out.off.begin()) - 1;
+    };
+    // edge weights w_AB from the fine edges, keyed by (min, max) expanded index
+    std::unordered_map<uint64_t, double> acc;
+    acc.reserve((size_t)P.lv[0].g.nnz() * L);
+    auto add = [&](int32_t a, int32_t b, double w) {
+        const uint64_t key = a < b ? ((uint64_t)a << 32) | (uint32_t)b : ((uint64_t)b << 32) | (uint32_t)a;
+        acc[key] += w;
+    };
+    const Adjacency& g = P.lv[0].g;
+    std::vector<int32_t> ai(L), bj(L);
+    for (int64_t i = 0; i < g.n; ++i)
+        for (int64_t q = g.ptr[i]; q < g.ptr[i + 1]; ++q) {
+            const int64_t j = g.col[q];
+            if (j < i) continue;
+            const double w = g.w[q];
+            ai[0] = P.inv[0][i];
+            bj[0] = P.inv[0][j];
+            for (int k = 0; k < T; ++k) {
+                ai[k + 1] = par[k][ai[k]];
+                bj[k + 1] = par[k][bj[k]];
+            }
+            int c = 0;                         // first common level
+            while (c < L && ai[c] != bj[c]) ++c;
+            // disjoint pairs (both below c), k + l even
+            for (int k = 0; k < c; ++k)
+                for (int l = k & 1; l < c; l += 2) add(out.off[k] + ai[k], out.off[l] + bj[l], w);
+            // nested pairs: B = level-l node, A = its level-k ancestor (l < k
+            // < c), k + l odd: the edge leaves A
+            for (int k = 1; k < c; ++k)
+                for (int l = 0; l < k; ++l)
+                    if ((k + l) & 1) {
+                        add(out.off[k] + ai[k], out.off[l] + ai[l], w);
+                        add(out.off[k] + bj[k], out.off[l] + bj[l], w);
+                    }
+        }
+    // S: off-diagonals -w_AB, diagonal sum_B mu^(l-k) w_AB
+    std::vector<std::vector<std::pair<int32_t, double>>> adj(nt);
+    std::vector<double> sdiag(nt, 0.0);
+    std::vector<uint64_t> keys;
+    keys.reserve(acc.size());
+    for (auto& kv : acc) keys.push_back(kv.first);
+    std::sort(keys.begin(), keys.end());
+    for (uint64_t key : keys) {
+        const double w = acc[key];
+        if (!(w > 0.0)) continue;
+        const int32_t a = (int32_t)(key >> 32), b = (int32_t)(key & 0xffffffffu);
+        const int ka = lev(a), kb = lev(b);
+        adj[a].push_back({b, -w});
+        adj[b].push_back({a, -w});
+        sdiag[a] += std::pow(mu, kb - ka) * w;
+        sdiag[b] += std::pow(mu, ka - kb) * w;
+    }
+    for (auto& r : adj) out.nnz_s += (int64_t)r.size();
+    out.ground = nt - 1;
+    // minimum-degree elimination on bitsets, numeric LDL^T on a dense copy
+    const int32_t m = nt - 1;                 // the grounded node is left out
+    if ((int64_t)m * m > (int64_t)400 * 1000 * 1000) return kUnsupported;
+    const int32_t words = (m + 63) / 64;
+    std::vector<uint64_t> bits((size_t)m * words, 0);
+    std::vector<double> A((size_t)m * m, 0.0);
+    for (int32_t a = 0; a < m; ++a) {
+        A[(size_t)a * m + a] = sdiag[a];
+        for (auto& e : adj[a])
+            if (e.first < m) {
+                A[(size_t)a * m + e.first] = e.second;
+                bits[(size_t)a * words + (e.first >> 6)] |= 1ull << (e.first & 63);
+            }
+    }
+    std::vector<char> gone(m, 0);
+    std::vector<int32_t> deg(m), order, pos(m);
+    for (int32_t a = 0; a < m; ++a) {
+        int d = 0;
+        for (int32_t wi = 0; wi < words; ++wi) d += __builtin_popcountll(bits[(size_t)a * words + wi]);
+        deg[a] = d;
+    }
+    std::vector<std::vector<std::pair<int32_t, double>>> colL(m);   // l_uv for later u
+    out.diag.assign(nt, 1.0);
+    std::vector<int32_t> nb;
+    for (int32_t step = 0; step < m; ++step) {
+        int32_t v = -1;
+        for (int32_t a = 0; a < m; ++a)
+            if (!gone[a] && (v < 0 || deg[a] < deg[v])) v = a;
+        gone[v] = 1;
+        pos[v] = step;
+        order.push_back(v);
+        nb.clear();
+        const uint64_t* bv = &bits[(size_t)v * words];
+        for (int32_t wi = 0; wi < words; ++wi)
+            for (uint64_t x = bv[wi]; x; x &= x - 1) {
+                const int32_t u = wi * 64 + __builtin_ctzll(x);
+                if (!gone[u]) nb.push_back(u);
+            }
+        const double dv = A[(size_t)v * m + v];
+        if (!(dv > 0.0)) return kInval;
+        out.diag[v] = dv;
+        for (int32_t u : nb) colL[v].push_back({u, A[(size_t)u * m + v] / dv});
+        for (size_t x = 0; x < nb.size(); ++x) {
+            const int32_t u = nb[x];
+            const double luv = A[(size_t)u * m + v] / dv;
+            double* Au = &A[(size_t)u * m];
+            for (size_t y = 0; y < nb.size(); ++y) {
+                const int32_t w2 = nb[y];
+                Au[w2] -= luv * A[(size_t)v * m + w2];
+            }
+            uint64_t* bu = &bits[(size_t)u * words];
+            for (int32_t wi = 0; wi < words; ++wi) bu[wi] |= bv[wi];
+            bu[u >> 6] &= ~(1ull << (u & 63));
+            bu[v >> 6] &= ~(1ull << (v & 63));
+        }
+        for (int32_t u : nb) {
+            int d = 0;
+            const uint64_t* bu = &bits[(size_t)u * words];
+            for (int32_t wi = 0; wi < words; ++wi) {
+                uint64_t x = bu[wi];
+                // count only nodes still present
+                while (x) {
+                    const int32_t z = wi * 64 + __builtin_ctzll(x);
+                    x &= x - 1;
+                    d += !gone[z];
+                }
+            }
+            deg[u] = d;
+        }
+    }
+    // rows of L (forward, gather) and columns (backward, gather), levels
+    std::vector<std::vector<std::pair<int32_t, double>>> rowL(m);
+    for (int32_t v = 0; v < m; ++v)
+        for (auto& e : colL[v]) rowL[e.first].push_back({v, e.second});
+    for (int32_t v = 0; v < m; ++v) out.nnz_l += (int64_t)colL[v].size();
+    std::vector<int32_t> lf(m, 0), lb(m, 0);
+    for (int32_t v : order) {
+        int d = 0;
+        for (auto& e : rowL[v]) d = std::max(d, lf[e.first] + 1);
+        lf[v] = d;
+    }
+    for (auto it = order.rbegin(); it != order.rend(); ++it) {
+        int d = 0;
+        for (auto& e : colL[*it]) d = std::max(d, lb[e.first] + 1);
+        lb[*it] = d;
+    }
+    auto schedule = [&](const std::vector<int32_t>& lv, const std::vector<std::vector<std::pair<int32_t, double>>>& ent,
+                        std::vector<int32_t>& levp, std::vector<int32_t>& rows, std::vector<int32_t>& ptr,
+                        std::vector<int32_t>& col, std::vector<double>& val) {
+        int nl = 0;
+        for (int32_t v = 0; v < m; ++v) nl = std::max(nl, lv[v] + 1);
+        levp.assign(nl + 1, 0);
+        for (int32_t v = 0; v < m; ++v) ++levp[lv[v] + 1];
+        for (int l = 0; l < nl; ++l) levp[l + 1] += levp[l];
+        rows.assign(m, 0);
+        std::vector<int32_t> fill(levp.begin(), levp.end() - 1);
+        for (int32_t v : order) rows[fill[lv[v]]++] = v;
+        ptr.assign(m + 1, 0);
+        col.clear();
+        val.clear();
+        for (int32_t r = 0; r < m; ++r) {
+            for (auto& e : ent[rows[r]]) {
+                col.push_back(e.first);
+                val.push_back(e.second);
+            }
+            ptr[r + 1] = (int32_t)col.size();
+        }
+    };
+    schedule(lf, rowL, out.flev, out.frow, out.fptr, out.fcol, out.fval);
+    schedule(lb, colL, out.blev, out.brow, out.bptr, out.bcol, out.bval);
+    return kOk;
 }
 
 }  // namespace lapgpu

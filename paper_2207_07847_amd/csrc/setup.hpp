@@ -79,6 +79,31 @@ struct HostPlan {
     int nlev() const { return (int)lv.size(); }
 };
 
+// PEGP (Sec. 3.1-3.2) as the factored grounded system S = D L_H~ D, D =
+// diag(mu^-k) on level k, over the expanded nodes in tree numbering (node t
+// of level k has expanded index off[k] + t).  L_H~ keeps the negative
+// off-diagonal entries of L_G~ = P(mu)^T L_G P(mu), whose magnitudes are
+// mu^(k+l) w_AB: w_AB = total fine weight between disjoint aggregates A, B
+// (kept when k + l is even) or, for B inside A, the weight from B to
+// outside A (kept when k + l is odd); so S(A,B) = -w_AB and S(A,A) =
+// sum_B mu^(l-k) w_AB.  The last expanded node is grounded; the rest is
+// factored S = L diag(d) L^T in a minimum-degree order, and both
+// triangular solves are level-scheduled.
+struct PegpPlan {
+    int32_t nt = 0;                          // expanded nodes
+    int32_t ground = 0;                      // grounded expanded node
+    std::vector<int32_t> off;                // level -> first expanded index (nlev+1)
+    std::vector<double> diag;                // d of each expanded node (ground: 1)
+    // forward: levels of rows, row v = sum over earlier-eliminated u of l_vu
+    std::vector<int32_t> flev, frow, fptr, fcol;
+    std::vector<double> fval;
+    // backward: levels of nodes, node v = sum over later-eliminated u of l_uv
+    std::vector<int32_t> blev, brow, bptr, bcol;
+    std::vector<double> bval;
+    int64_t nnz_s = 0, nnz_l = 0;            // off-diagonals of S (both halves), of L
+};
+int build_pegp(const HostPlan& plan, double mu, PegpPlan& out);
+
 int build_adjacency(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                     const double* w, Adjacency& out);
 bool is_connected(const Adjacency& g);
@@ -86,11 +111,12 @@ int64_t match_aggregate(const Adjacency& g, const std::vector<int64_t>* order,
                         std::vector<int64_t>& agg, std::vector<int8_t>& matched);
 void coarse_graph(const Adjacency& f, const std::vector<int64_t>& agg, int64_t nc,
                   Adjacency& c);
-// Full host setup; returns a Status.  host_only skips nothing here (the
-// device upload happens elsewhere) but allows tops larger than kTopMax.
+// Full host setup; returns a Status.  any_top allows top levels larger
+// than kTopMax (no on-chip dense top solve: host-only setups, PEGP, plain
+// CG); their top pseudo-inverse is then not formed.
 int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                const double* w, double mu, int max_levels, int64_t n_top,
-               uint64_t seed, bool host_only, HostPlan& plan);
+               uint64_t seed, bool any_top, HostPlan& plan);
 // The SpMV layout of the fine Laplacian g (part of build_plan).
 void build_sell(const Adjacency& g, HostPlan& plan);
 // Whether g is mesh-like for the SpMV: no row above kHeavyDeg and slices of

@@ -157,7 +157,7 @@ def test_disconnected_graph():
 
 @pytest.mark.parametrize("field,value,code", [
     ("mu", 0.0, 1), ("mu", 1.0, 1), ("mu", -0.5, 1), ("n_top", 1, 1),
-    ("precond", 9, 1), ("precond", 1, 7), ("precision", 3, 1), ("max_iter", -1, 1),
+    ("precond", 9, 1), ("precision", 3, 1), ("max_iter", -1, 1),
 ])
 def test_invalid_params(field, value, code):
     lap = _lap()
@@ -167,6 +167,31 @@ def test_invalid_params(field, value, code):
     with pytest.raises(lap.LapError) as e:
         lap.lap_setup(n, u, v, np.ones(len(u)), p)
     assert e.value.status == code
+
+
+def test_pegp_setup_limits():
+    """PEGP: FP64 single solves only; the expanded system must fit one
+    workgroup's LDS (host-only setups build and factor it)."""
+    lap = _lap()
+    n, u, v = W.grid2d(16)
+    w = np.ones(len(u))
+    p = lap.lap_default_params(flags=lap.LAP_FLAG_HOST_ONLY, precond=lap.LAP_PREC_PEGP,
+                               mu=1 / 16)
+    h = lap.lap_setup(n, u, v, w, p)
+    assert lap.lap_hierarchy_info(h)["ntilde"] == 510
+    lap.lap_free(h)
+    for extra in (dict(precision=lap.LAP_MIXED_FP32_FP64),
+                  dict(flags=lap.LAP_FLAG_HOST_ONLY | lap.LAP_FLAG_MULTI_RHS)):
+        q = lap.lap_default_params(flags=lap.LAP_FLAG_HOST_ONLY, precond=lap.LAP_PREC_PEGP)
+        for k, val in extra.items():
+            setattr(q, k, val)
+        with pytest.raises(lap.LapError) as e:
+            lap.lap_setup(n, u, v, w, q)
+        assert e.value.status == lap.LAP_EUNSUPPORTED
+    n, u, v = W.grid2d(128)        # 32766 expanded nodes: beyond the LDS solve
+    with pytest.raises(lap.LapError) as e:
+        lap.lap_setup(n, u, v, np.ones(len(u)), p)
+    assert e.value.status == lap.LAP_EUNSUPPORTED
 
 
 def test_host_only_refuses_device_calls():
