@@ -148,9 +148,9 @@ def measure(lap, h, bd, xd, n, tol, steps, warmup, sh, stream, capped, nrhs=1):
 
 
 def serve_pool(count, n_min, n_max, seed):
-    """Graphs of the serving stream: half 2D/3D grids (log-uniform weights),
-    half Chung-Lu (mean degree 16, exponent 2.1, U(0,1] weights), sizes
-    log-uniform in [n_min, n_max]."""
+    """Graphs of the serving stream: half 2D/3D grids (unit weights, as the
+    paper's grids), half Chung-Lu (mean degree 16, exponent 2.1, U(0,1]
+    weights), sizes log-uniform in [n_min, n_max]."""
     import numpy as np
 
     import workloads as W
@@ -165,7 +165,7 @@ def serve_pool(count, n_min, n_max, seed):
             else:
                 a = max(3, int(round(target ** (1 / 3))))
                 n, u, v = W.grid3d(a)
-            w = W.loguniform_weights(len(u), seed + i)
+            w = W.unit_weights(len(u))
             kind = "grid"
         else:
             n, u, v = W.chung_lu(max(64, int(target)), 16.0, 2.1, seed + i)
@@ -232,6 +232,9 @@ def serve(args):
     k = 0
     while len(res) < len(reqs):
         now = time.perf_counter() - t_start
+        if now > args.serve_limit_s:
+            log(f"time limit: {len(reqs) - len(res)} requests unfinished")
+            break
         if time.perf_counter() - t_log > 5.0:
             t_log = time.perf_counter()
             log(f"  {now:6.1f}s: submitted {k}, completed {len(res)}")
@@ -250,12 +253,14 @@ def serve(args):
     lap.lap_server_destroy(srv)
     for h in hs:
         lap.lap_free(h)
-    lat = np.array([res[i]["total_seconds"] for i in range(len(reqs))]) * 1e3
-    qlat = np.array([res[i]["queue_seconds"] for i in range(len(reqs))]) * 1e3
-    bad = [i for i in range(len(reqs)) if res[i]["status"] != 0]
-    ncols = sum(r["m"] for r in reqs)
-    worst = max(res[i]["relres_max"] / reqs[i]["tol"] for i in range(len(reqs)))
-    log(f"served {len(reqs)} requests ({ncols} right-hand sides) in {elapsed:.2f}s, "
+    done = sorted(res)
+    lat = np.array([res[i]["total_seconds"] for i in done]) * 1e3
+    qlat = np.array([res[i]["queue_seconds"] for i in done]) * 1e3
+    bad = [i for i in done if res[i]["status"] != 0]
+    ncols = sum(reqs[i]["m"] for i in done)
+    worst = max(res[i]["relres_max"] / reqs[i]["tol"] for i in done)
+    unfinished = len(reqs) - len(done)
+    log(f"served {len(done)} requests ({ncols} right-hand sides) in {elapsed:.2f}s, "
         f"p50 {np.percentile(lat, 50):.1f} ms, p99 {np.percentile(lat, 99):.1f} ms, "
         f"failed {len(bad)}, worst relres/tol {worst:.3f}")
     line = {
@@ -263,9 +268,9 @@ def serve(args):
         "value": ncols / elapsed,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": len(reqs),
+        "steps": len(done),
         "warmup": 0,
-        "ms_per_step": elapsed / len(reqs) * 1e3,
+        "ms_per_step": elapsed / max(1, len(done)) * 1e3,
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
@@ -274,16 +279,18 @@ def serve(args):
         "config": {
             "workload": f"serving stream: {len(reqs)} requests, Poisson arrivals at "
                         f"{args.serve_rate:g}/s, {len(pool)} graphs (half 2D/3D grids, half "
-                        f"Chung-Lu) of {args.serve_nmin}..{args.serve_nmax} vertices, 1-16 "
+                        f"Chung-Lu) of {args.serve_nmin}..{args.serve_nmax} vertices (grids: unit "
+                        f"weights; Chung-Lu: U(0,1]), 1-16 "
                         f"Gaussian RHS per request, tol 1e-6 or 1e-8, MSP mu=0.8, FP64",
             "right_hand_sides": ncols, "resident_gib": resident / 2**30,
-            "failed_requests": len(bad), "worst_relres_over_tol": worst,
+            "failed_requests": len(bad), "unfinished_requests": unfinished,
+            "worst_relres_over_tol": worst,
         },
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "queue_p50_ms": float(np.percentile(qlat, 50)),
         "queue_p99_ms": float(np.percentile(qlat, 99)),
-        "requests_per_s": len(reqs) / elapsed,
+        "requests_per_s": len(done) / elapsed,
         "fp64_same_gpu": {"value": single_rate, "unit": "solves/s",
                           "what": f"plain FP64 PCG, one right-hand side per solve, "
                                   f"{cols} columns of the first {len(sample)} requests"},
@@ -312,12 +319,14 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--serve", action="store_true",
                     help="the serving stream instead of single solves")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-rate", type=float, default=400.0, help="arrivals per second")
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-rate", type=float, default=15.0, help="arrivals per second")
     ap.add_argument("--serve-graphs", type=int, default=32)
     ap.add_argument("--serve-nmin", type=int, default=1000)
     ap.add_argument("--serve-nmax", type=int, default=1000000)
     ap.add_argument("--serve-budget-gib", type=float, default=0.0)
+    ap.add_argument("--serve-limit-s", type=float, default=240.0,
+                    help="stop waiting after this long; unfinished requests are reported")
     ap.add_argument("--serve-compare", type=int, default=20,
                     help="requests whose columns are also timed as single FP64 solves")
     ap.add_argument("--max-iter", type=int, default=200000,

@@ -263,8 +263,11 @@ lap_status lap_server_submit(lap_server *srv, int32_t graph, const double *b,
 lap_status lap_server_poll(lap_server *srv, lap_request_result *out,
                            int32_t max, int32_t wait_ms, int32_t *count);
 
-/* Finish every queued request, stop the server thread, release the
- * server's staging memory (not the hierarchies).  NULL is a no-op. */
+/* Stop the server: requests not yet admitted are dropped, running ones are
+ * abandoned once the chunk in flight ends (their results are not
+ * delivered), then the server thread ends and the server's staging memory
+ * is released (not the hierarchies).  Poll every result first to keep it.
+ * NULL is a no-op. */
 void lap_server_destroy(lap_server *srv);
 
 /* Release the hierarchy and its device memory (NULL is a no-op). */

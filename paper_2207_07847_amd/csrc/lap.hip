@@ -1589,6 +1589,7 @@ struct lap_server {
     int64_t inflight = 0;           // submitted and not yet polled out
     std::thread worker;
     std::atomic<bool> stop{false};
+    std::atomic<bool> cancel{false};
     std::atomic<bool> failed{false};
     PinPool pins;
 };
@@ -1746,6 +1747,34 @@ void srv_loop(lap_server* S) {
                     S->outbox.push_back(r);
                 }
                 S->cv_out.notify_all();
+            }
+            if (S->cancel.load()) {
+                // drop what has not started; let chunks and copies in flight
+                // finish, then retire their requests without results
+                bool inflight = !S->copying.empty();
+                for (SrvLane& L : S->lanes) {
+                    for (SrvRequest* r : L.pending) delete r;
+                    L.pending.clear();
+                    if (L.busy) {
+                        if (hipEventQuery(L.ev) != hipSuccess) {
+                            inflight = true;
+                            continue;
+                        }
+                        L.busy = false;
+                    }
+                    for (int c = 0; c < kCols; ++c) {
+                        SrvRequest* r = L.slot_req[c];
+                        if (!r) continue;
+                        for (int d = c; d < kCols; ++d)
+                            if (L.slot_req[d] == r) L.slot_req[d] = nullptr;
+                        (void)hipFreeAsync(r->db, L.s);
+                        S->pins.put(r->pin);
+                        delete r;
+                    }
+                }
+                if (!inflight) break;
+                std::this_thread::sleep_for(std::chrono::microseconds(50));
+                continue;
             }
             if (!work) {
                 if (S->stop.load()) {
@@ -2094,6 +2123,7 @@ lap_status lap_server_poll(lap_server* S, lap_request_result* out, int32_t max, 
 void lap_server_destroy(lap_server* S) {
     if (!S) return;
     S->stop.store(true);
+    S->cancel.store(true);
     if (S->worker.joinable()) S->worker.join();
     for (SrvLane& L : S->lanes) {
         if (L.s) {
