@@ -106,19 +106,39 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
     double v[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = 0.0;
-    const int nv = (OP == kFinRho) ? 3 : 1;
-    for (int i = 0; i < nv; ++i) {
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        int b = threadIdx.x;
-        for (; b + 3 * kFinThreads < G; b += 4 * kFinThreads) {
+    constexpr int nv = (OP == kFinRho) ? 3 : 1;
+    // up to kFinUnroll partials of every array per thread, all loads issued
+    // before the adds (one memory latency instead of one per partial)
+    constexpr int U = kFinUnroll;
+    const int tid = threadIdx.x;
+    if (G <= U * kFinThreads && G2 <= U * kFinThreads) {
+        double a[N][U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] += part[i * G + b + u * kFinThreads];
+        for (int i = 0; i < nv; ++i)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int b = tid + u * kFinThreads;
+                a[i][u] = b < G ? part[i * G + b] : 0.0;
+            }
+        if (OP == kFinRho)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int b = tid + u * kFinThreads;
+                a[N - 1][u] = b < G2 ? part2[b] : 0.0;
+            }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) t += a[i][u];
+            v[i] = t;
         }
-        for (; b < G; b += kFinThreads) a[0] += part[i * G + b];
-        v[i] = (a[0] + a[1]) + (a[2] + a[3]);
+    } else {
+        for (int i = 0; i < nv; ++i)
+            for (int b = tid; b < G; b += kFinThreads) v[i] += part[i * G + b];
+        if (OP == kFinRho)
+            for (int b = tid; b < G2; b += kFinThreads) v[N - 1] += part2[b];
     }
-    if (OP == kFinRho)
-        for (int b = threadIdx.x; b < G2; b += kFinThreads) v[N - 1] += part2[b];
     block_sum<N, kFinThreads>(v, lds);
     if (threadIdx.x != 0) return;
     if (OP == kFinPq) {
@@ -192,15 +212,32 @@ __device__ inline int spmv_block(int nhb) {
 // One light row of sliced ELL: sum over its slots of w * diff(j), where
 // diff(j) is the row's value minus the neighbour's, (L v)_i = sum_j
 // w_ij (v_i - v_j) (the Laplacian of Sec. 2.1 with no stored diagonal).
+// Slots are taken eight at a time: their column indices and weights are
+// loaded first, then the eight neighbour values, so a row costs two memory
+// latencies per eight entries instead of two per entry.  The width is the
+// same for the whole slice (a wavefront), so the bounds tests are uniform.
 template <class T, class F>
 __device__ inline T light_row(const Sell<T>& A, int slot, F diff) {
+    constexpr int U = 8;
     const int sl = slot >> 6;
     const int base = A.off[sl] + (slot & 63);
     const int W = A.width[sl];
     T acc = T(0);
-    for (int k = 0; k < W; ++k) {
-        const int j = A.col[base + k * 64];
-        acc += A.w[base + k * 64] * diff(j);
+    for (int k = 0; k < W; k += U) {
+        int j[U];
+        T w[U], d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k + u < W) {
+                j[u] = A.col[base + (k + u) * 64];
+                w[u] = A.w[base + (k + u) * 64];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k + u < W) d[u] = diff(j[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k + u < W) acc += w[u] * d[u];
     }
     return acc;
 }
@@ -884,7 +921,19 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restric
     __shared__ double red[3 * (kTailThreads / 64)];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int npack = D->pack, nsteps = D->nsteps;
-    for (int i = tid; i < npack; i += nth) sm[i] = pack[i];
+    {
+        // eight loads in flight per thread
+        constexpr int U = 8;
+        int i = tid;
+        for (; i + (U - 1) * kTailThreads < npack; i += U * kTailThreads) {
+            T t[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) t[u] = pack[i + u * kTailThreads];
+#pragma unroll
+            for (int u = 0; u < U; ++u) sm[i + u * kTailThreads] = t[u];
+        }
+        for (; i < npack; i += kTailThreads) sm[i] = pack[i];
+    }
     {
         const int n0 = nsteps > 0 ? D->st[0].nk : D->nt;
         T* r0 = sm + D->r[0];

@@ -16,6 +16,7 @@ namespace lapgpu {
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kTailThreads = 1024; // threads of the one-block coarse tail
 constexpr int kFinThreads = 1024;  // threads of the one-block reduction finish
+constexpr int kFinUnroll = 8;      // partials per thread loaded at once by a finish
 constexpr int kMaxGridPart = 3;    // values reduced per block
 constexpr int kAggPerBlock = 256;  // aggregates per block of a level kernel
 constexpr int kCapP = 2048;        // children per block staged in LDS; an
