@@ -653,6 +653,111 @@ __global__ __launch_bounds__(kBlock) void k_down0(LevelDev<T> s0, const int32_t*
     block_partial<3>(v, part);
 }
 
+// Levels 0 and 1 together.  Block b owns the level-2 nodes [A0, A1) =
+// [bst[b], bst[b+1]) of a partition aligned to level-1 aggregates: their
+// level-1 children [J0, J1) and level-0 grandchildren [t0, t1) are
+// contiguous and staged in LDS, so one launch does the update, the level-0
+// restriction and the level-1 restriction (and the down kernel both
+// prolongations).  Used when every block fits (kAggPerBlock level-1 nodes,
+// kCapP level-0 positions).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_update_up01(LevelDev<T> s0, LevelDev<T> s1,
+                                                        const int32_t* __restrict__ bst,
+                                                        const int32_t* __restrict__ perm,
+                                                        T* __restrict__ x, T* __restrict__ r,
+                                                        const T* __restrict__ p,
+                                                        const T* __restrict__ q,
+                                                        T* __restrict__ r2, Scal* S, double* part,
+                                                        int do_update) {
+    if (S->done) return;
+    __shared__ T rs[kCapP];
+    __shared__ T r1s[kAggPerBlock];
+    __shared__ int nbig, big[kAggPerBlock];
+    const T alpha = (T)S->alpha;
+    const int b = xcd_block();
+    const int A0 = bst[b], A1 = bst[b + 1];
+    const int J0 = s1.cptr[A0], J1 = s1.cptr[A1];
+    const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
+    double rr = 0.0;
+    if (threadIdx.x == 0) nbig = 0;
+    for (int i = threadIdx.x; i < len; i += kBlock) {
+        const int t = t0 + i;
+        T rt = r[t];
+        if (do_update) {
+            x[t] += alpha * p[t];
+            rt -= alpha * q[perm ? perm[t] : t];
+            r[t] = rt;
+            rr += (double)rt * rt;
+        }
+        rs[i] = rt;
+    }
+    __syncthreads();
+    // level 0 -> 1: restricted values to LDS (and to r1 for the down-sweep)
+    for (int J = J0 + threadIdx.x; J < J1; J += kBlock) {
+        if (s0.cptr[J + 1] - s0.cptr[J] > kWaveAgg) big[atomicAdd(&nbig, 1)] = J;
+        else agg_up(s0, rs, t0, s1.r, J);
+    }
+    __syncthreads();
+    {
+        const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int i = wid; i < nbig; i += kBlock / 64) agg_up_wave(s0, rs, t0, s1.r, big[i], lane);
+    }
+    __syncthreads();
+    for (int J = J0 + threadIdx.x; J < J1; J += kBlock) r1s[J - J0] = s1.r[J];
+    if (threadIdx.x == 0) nbig = 0;
+    __syncthreads();
+    // level 1 -> 2
+    up_aggregates(s1, r1s, J0, r2, A0, A1, &nbig, big);
+    if (!do_update) return;
+    double v[1] = {rr};
+    block_partial<1>(v, part);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_down01(LevelDev<T> s0, LevelDev<T> s1,
+                                                   const int32_t* __restrict__ bst,
+                                                   const int32_t* __restrict__ perm,
+                                                   const T* __restrict__ r, T* __restrict__ zn,
+                                                   const T* __restrict__ y2, Scal* S,
+                                                   double* part) {
+    if (S->done) return;
+    __shared__ DownBlock<T> D;
+    __shared__ T y1s[kAggPerBlock];
+    const int b = xcd_block();
+    const int A0 = bst[b], A1 = bst[b + 1];
+    const int J0 = s1.cptr[A0], J1 = s1.cptr[A1];
+    const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
+    // level 2 -> 1 into LDS
+    for (int A = A0 + threadIdx.x; A < A1; A += kBlock) {
+        const int c0 = s1.cptr[A], c1 = s1.cptr[A + 1];
+        const T yA = y2[A], ea = s1.ea[A], eb = s1.eb[A];
+        for (int J = c0; J < c1; ++J) y1s[J - J0] = child_down(s1, A, c0, J, s1.r[J], yA, ea, eb);
+    }
+    __syncthreads();
+    // level 1 -> 0, z with its reductions
+    for (int j = threadIdx.x; j < J1 - J0; j += kBlock) {
+        const int J = J0 + j;
+        const int c0 = s0.cptr[J], c1 = s0.cptr[J + 1];
+        D.b0[j] = c0;
+        D.yJ[j] = y1s[j];
+        D.ea[j] = s0.ea[J];
+        D.eb[j] = s0.eb[J];
+        for (int t = c0; t < c1; ++t) D.own[t - t0] = j;
+    }
+    __syncthreads();
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < len; i += kBlock) {
+        const int t = t0 + i, j = D.own[i];
+        const T rt = r[t];
+        const T zt = child_down(s0, J0 + j, D.b0[j], t, rt, D.yJ[j], D.ea[j], D.eb[j]);
+        zn[perm ? perm[t] : t] = zt;
+        v[0] += zt;
+        v[1] += (double)rt * zt;
+        v[2] += rt;
+    }
+    block_partial<3>(v, part);
+}
+
 // Without a hierarchy below the fine level: x and r update only.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_update_none(int n, const int32_t* __restrict__ perm,

@@ -86,6 +86,28 @@ std::vector<int32_t> block_partition(const std::vector<int32_t>& cptr) {
     return bst;
 }
 
+// Partition of the level-2 nodes for the fused level-0/1 kernels: runs of
+// level-1 aggregates whose level-1 children fit kAggPerBlock and level-0
+// grandchildren fit kCapP.  Empty when one aggregate alone does not fit.
+std::vector<int32_t> block_partition01(const std::vector<int32_t>& c0,
+                                       const std::vector<int32_t>& c1) {
+    const int32_t n2 = (int32_t)c1.size() - 1;
+    std::vector<int32_t> bst{0};
+    int32_t A0 = 0;
+    auto fits = [&](int32_t a, int32_t b) {
+        return b - a <= kAggPerBlock && c1[b] - c1[a] <= kAggPerBlock &&
+               c0[c1[b]] - c0[c1[a]] <= kCapP;
+    };
+    while (A0 < n2) {
+        if (!fits(A0, A0 + 1)) return {};
+        int32_t A1 = A0 + 1;
+        while (A1 < n2 && fits(A0, A1 + 1)) ++A1;
+        bst.push_back(A1);
+        A0 = A1;
+    }
+    return bst;
+}
+
 std::vector<int32_t> big_aggregates(const std::vector<int32_t>& cptr) {
     std::vector<int32_t> big;
     for (size_t J = 0; J + 1 < cptr.size(); ++J)
@@ -277,7 +299,10 @@ struct Engine {
         GroupDev<T> gd{};
         size_t lds_up = 0, lds_down = 0;   // bytes of dynamic LDS
     };
-    std::vector<Segment> segs;   // levels [1, kt), in order
+    std::vector<Segment> segs;   // levels [1, kt) ([2, kt) when fuse01), in order
+    bool fuse01 = false;         // levels 0 and 1 in the same kernels
+    const int32_t* bst01 = nullptr;
+    int nb01 = 0;
     // workspace: input order
     T *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *zn = nullptr;
     // workspace: tree order
@@ -522,11 +547,17 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
         return;
     }
     const LevelDev<T>& s0 = e.lv[0];
-    const int g0 = s0.nb;
-    launch_timed(k_update_up0<T>, dim3(g0), dim3(kBlock), 0, s,
-                 mk.kernel == LAP_KERNEL_PRECOND ? mk.e0 : mk.start(LAP_KERNEL_UPDATE),
-                 mk.stop(LAP_KERNEL_UPDATE), s0, h->t2s, e.x, e.r, pcur,
-                 (const T*)e.q, e.lv[1].r, S, h->part2, do_update);
+    const int g0 = e.fuse01 ? e.nb01 : s0.nb;
+    if (e.fuse01)
+        launch_timed(k_update_up01<T>, dim3(g0), dim3(kBlock), 0, s,
+                     mk.kernel == LAP_KERNEL_PRECOND ? mk.e0 : mk.start(LAP_KERNEL_UPDATE),
+                     mk.stop(LAP_KERNEL_UPDATE), s0, e.lv[1], e.bst01, h->t2s, e.x, e.r, pcur,
+                     (const T*)e.q, e.lv[2].r, S, h->part2, do_update);
+    else
+        launch_timed(k_update_up0<T>, dim3(g0), dim3(kBlock), 0, s,
+                     mk.kernel == LAP_KERNEL_PRECOND ? mk.e0 : mk.start(LAP_KERNEL_UPDATE),
+                     mk.stop(LAP_KERNEL_UPDATE), s0, h->t2s, e.x, e.r, pcur,
+                     (const T*)e.q, e.lv[1].r, S, h->part2, do_update);
     for (const auto& G : e.segs) {
         if (G.group)
             hipLaunchKernelGGL(k_up_grp<T>, dim3(G.gd.nblocks), dim3(kGrpThreads), G.lds_up, s,
@@ -548,9 +579,15 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
                                (const T*)e.lv[G.k0].r, e.lv[G.k0].y, (const T*)e.lv[G.k0 + 1].y,
                                (const Scal*)S);
     }
-    launch_timed(k_down0<T>, dim3(g0), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_DOWN0),
-                 mk.kernel == LAP_KERNEL_PRECOND ? mk.e1 : mk.stop(LAP_KERNEL_DOWN0), s0, h->t2s,
-                 (const T*)e.r, e.zn, (const T*)e.lv[1].y, S, h->part);
+    if (e.fuse01)
+        launch_timed(k_down01<T>, dim3(g0), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_DOWN0),
+                     mk.kernel == LAP_KERNEL_PRECOND ? mk.e1 : mk.stop(LAP_KERNEL_DOWN0), s0,
+                     e.lv[1], e.bst01, h->t2s, (const T*)e.r, e.zn, (const T*)e.lv[2].y, S,
+                     h->part);
+    else
+        launch_timed(k_down0<T>, dim3(g0), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_DOWN0),
+                     mk.kernel == LAP_KERNEL_PRECOND ? mk.e1 : mk.stop(LAP_KERNEL_DOWN0), s0,
+                     h->t2s, (const T*)e.r, e.zn, (const T*)e.lv[1].y, S, h->part);
     finish<kFinRho>(h, s, S, g0, do_update ? g0 : 0);
 }
 
@@ -686,14 +723,24 @@ void upload_engine(lap_hierarchy* h, Engine<T>& e, hipStream_t s, bool with_leve
     }
     e.top_pinv = h->upload(convert<T>(P.top_pinv), s);
     if (Tl == 0) return;
-    // middle levels [1, kt): groups of consecutive levels where whole
-    // subtrees fit a block, single per-level kernels elsewhere
+    e.fuse01 = false;
+    if (Tl >= 2 && e.kt >= 2 && env_int("LAPGPU_FUSE01", 1) != 0) {
+        const std::vector<int32_t> b01 = block_partition01(P.step[0].cptr, P.step[1].cptr);
+        if (!b01.empty()) {
+            e.fuse01 = true;
+            e.nb01 = (int)b01.size() - 1;
+            e.bst01 = h->upload(b01, s);
+        }
+    }
+    // middle levels [1, kt) (from 2 when levels 0 and 1 are fused): groups
+    // of consecutive levels where whole subtrees fit a block, single
+    // per-level kernels elsewhere
     e.segs.clear();
     const int cap = env_int("LAPGPU_GRP_CAP", 1024);
     const int maxlev = std::min(kMaxGroupLevels, env_int("LAPGPU_GRP_MAXLEV", kMaxGroupLevels));
     const int first_grouped = std::max(1, env_int("LAPGPU_GRP_FIRST", 2));
     const int32_t units = (int32_t)(kGrpLdsBytes / sizeof(T));
-    for (int k0 = 1; k0 < e.kt;) {
+    for (int k0 = e.fuse01 ? 2 : 1; k0 < e.kt;) {
         typename Engine<T>::Segment sg;
         bool placed = false;
         for (int m = std::min(maxlev, e.kt - k0); m >= 1 && !placed && k0 >= first_grouped; --m) {
@@ -798,6 +845,7 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     h->So = h->dalloc<Scal>(1);
     int gmax = std::max(nblk(n), h->e64.spmv_grid());
     for (int b : h->nb) gmax = std::max(gmax, b);
+    gmax = std::max(gmax, std::max(h->e64.nb01, h->e32.nb01));
     h->part = h->dalloc<double>((size_t)kMaxGridPart * gmax + 64);
     h->part2 = h->dalloc<double>((size_t)gmax + 64);
     HIPCHK(hipHostMalloc((void**)&h->stage, sizeof(Scal), hipHostMallocDefault));
@@ -1352,7 +1400,7 @@ void apply_precond(lap_hierarchy* h, Engine<T>& e, const double* r, double* z, h
 
 // Algorithmic bytes of one part of an iteration (lap_profile_kernel): the
 // data each kernel must move once, values of vb bytes, int32 indices.
-double part_bytes(const lap_hierarchy* h, int kernel, double vb, bool levels) {
+double part_bytes(const lap_hierarchy* h, int kernel, double vb, bool levels, bool fused01) {
     const int T = h->plan.nlev() - 1;
     const HostPlan& P = h->plan;
     const double n = (double)h->n;
@@ -1373,11 +1421,17 @@ double part_bytes(const lap_hierarchy* h, int kernel, double vb, bool levels) {
     // SpMV: z, p_old read, p, q written; col and w per stored entry (with
     // a separate p pass, p is read back once more by the SpMV)
     const double spmv = (h->fuse_p ? 4.0 : 5.0) * vb * n + (4.0 + vb) * nnz;
-    const double upd = levels ? 6.0 * vb * n + step_up(0) - vb * n : 6.0 * vb * n;
-    const double down0 =
-        levels ? step_down(0) - vb * (lvn(0) - 2.0 * lvn(1)) + vb * n : 3.0 * vb * n;
+    // fused levels 0 and 1: the update kernel also restricts level 1 (its r1
+    // stays in LDS but is written once for the down-sweep), down0 also
+    // prolongs level 1 (y1 stays in LDS)
+    double upd = levels ? 6.0 * vb * n + step_up(0) - vb * n : 6.0 * vb * n;
+    double down0 = levels ? step_down(0) - vb * (lvn(0) - 2.0 * lvn(1)) + vb * n : 3.0 * vb * n;
+    if (levels && fused01) {
+        upd += step_up(1) - vb * lvn(1);
+        down0 += step_down(1) - vb * lvn(1) - vb * lvn(1);
+    }
     double mid = 0.0;
-    for (int k = 1; levels && k < T; ++k) mid += step_up(k) + step_down(k);
+    for (int k = fused01 ? 2 : 1; levels && k < T; ++k) mid += step_up(k) + step_down(k);
     switch (kernel) {
         case LAP_KERNEL_SPMV: return spmv;
         case LAP_KERNEL_UPDATE: return upd;
@@ -1395,7 +1449,7 @@ lap_status profile(lap_hierarchy* h, Engine<T>& e, int32_t kernel, int32_t reps,
     if ((kernel == LAP_KERNEL_UPDATE || kernel == LAP_KERNEL_DOWN0 ||
          kernel == LAP_KERNEL_PRECOND) && !levels)
         return LAP_EUNSUPPORTED;
-    const double bytes = part_bytes(h, kernel, (double)sizeof(T), levels);
+    const double bytes = part_bytes(h, kernel, (double)sizeof(T), levels, e.fuse01);
     // ITER: two events around all timed iterations; a part: its own kernels'
     // timestamps in every timed iteration
     const bool whole = kernel == LAP_KERNEL_ITER;
