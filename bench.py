@@ -68,9 +68,10 @@ def pmc_traffic(workload_name, scale):
     try:
         text = open(path).read()
         h = hashlib.sha256()
-        for f in ("lap.hip", "kernels.hpp"):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+        for f in sorted(os.listdir(csrc)):
+            if f.endswith((".hip", ".hpp", ".cpp")):
+                with open(os.path.join(csrc, f), "rb") as fh:
+                    h.update(fh.read())
     except OSError:
         return None
     traffic, sha = None, None
