@@ -140,12 +140,13 @@ lap_status lap_setup(const lap_graph *g, const lap_params *p, void *stream,
  * ld < n, non-finite b), LAP_EDEVICE.
  *
  * Mixed precision (LAP_MIXED_FP32_FP64): x and r = b^ - L x are kept in
- * FP64; each refinement solves L d = r by PCG with FP32 vectors, FP32 SpMV
- * and FP32 preconditioner (inner products and the mean projection summed in
- * FP64) to a relative residual of max(1e-4, tol ||b^|| / (2 ||r||)), then
- * x += d and r is recomputed in FP64.  The stop test is on that FP64 r;
- * info->iterations counts inner iterations over all refinements,
- * info->refinements the refinements, info->relres_true the final FP64
+ * FP64; one PCG run with FP32 vectors, FP32 SpMV and FP32 preconditioner
+ * (inner products and the mean projection summed in FP64) produces the
+ * corrections.  Each time its residual has fallen 10x, a refinement step
+ * (reliable update) adds its correction to x, replaces its residual by the
+ * FP64 b^ - L x, and continues along the same search direction.  The stop
+ * test is on that FP64 residual; info->iterations counts FP32 iterations,
+ * info->refinements the refinement steps, info->relres_true the final FP64
  * ||b^ - L x|| / ||b^||. */
 lap_status lap_solve(lap_hierarchy *h, const double *b, double *x,
                      int32_t nrhs, int64_t ld, double tol,

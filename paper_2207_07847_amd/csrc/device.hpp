@@ -1327,6 +1327,26 @@ __global__ __launch_bounds__(kBlock) void k_pattern(int64_t count, double* __res
     if (i < count) dst[i] = (double)((uint64_t)(i * 2654435761ull) & 1023u) / 1024.0 - 0.5;
 }
 
+// x += d and d = 0 (FP64 += FP32 correction, solve order): the correction
+// accumulated by the FP32 run since the last reliable update moves into x.
+__global__ __launch_bounds__(kBlock) void k_move_corr(int n, double* __restrict__ x,
+                                                      float* __restrict__ d) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) {
+        x[t] += (double)d[t];
+        d[t] = 0.0f;
+    }
+}
+
+// r (tree order, FP32) = r64 (solve order, FP64) rounded; tree position t
+// is solve position perm[t] (perm null: the same).
+__global__ __launch_bounds__(kBlock) void k_residual_in(int n, const int32_t* __restrict__ perm,
+                                                        const double* __restrict__ r64,
+                                                        float* __restrict__ r) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) r[t] = (float)r64[perm ? perm[t] : t];
+}
+
 // x += d (FP64 += FP32 correction, solve order).
 __global__ __launch_bounds__(kBlock) void k_add_corr(int n, double* __restrict__ x,
                                                      const float* __restrict__ d) {

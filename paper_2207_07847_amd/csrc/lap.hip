@@ -63,6 +63,7 @@ double env_double(const char* name, double dflt) {
 
 constexpr size_t kTailLdsBytes = 152 * 1024;
 constexpr int kProfGroup = 10;          // timed iterations per fresh run (profiling)
+constexpr double kReliableDrop = 1e-2;  // ||r||^2 drop between reliable updates
 constexpr size_t kGrpLdsBytes = 64 * 1024;
 
 // int32 entries that fit one value slot of type T.
@@ -436,6 +437,7 @@ struct lap_hierarchy {
     Scal* stage = nullptr;       // pinned host copy of S or So
     int chunk = 8;
     double inner_tol = 1e-4;
+    bool reliable = true;        // mixed precision by reliable updates (else restarts)
 
     template <class T>
     T* dalloc(size_t count) {
@@ -856,6 +858,7 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     HIPCHK(hipGetLastError());
     h->chunk = std::max(2, env_int("LAPGPU_CHUNK", 8) & ~1);
     h->inner_tol = env_double("LAPGPU_INNER_TOL", 1e-4);
+    h->reliable = env_int("LAPGPU_MIXED_RESTART", 0) == 0;
     build_graph(h, h->e64);
     if (h->mixed) build_graph(h, h->e32);
     h->has_fp32 = h->mixed;
@@ -1370,6 +1373,98 @@ lap_status solve_block(lap_hierarchy* h, const double* b, double* x, int nrhs, i
         if (rank_status(st[c]) > rank_status(worst)) worst = st[c];
     }
     return worst;
+}
+
+// Mixed precision with reliable updates (van der Vorst and Ye's residual
+// replacement, as used for mixed-precision CG): one FP32 PCG run keeps its
+// search direction throughout; whenever its residual has fallen by
+// kReliableDrop since the last replacement (or it meets the tolerance),
+// the FP32 correction moves into the FP64 x, the residual is replaced by
+// the FP64 b^ - L x, z = M r and rho are recomputed, and beta is rescaled
+// to the new rho so the next direction stays consistent.  The stop test is
+// on that FP64 residual.
+lap_status solve_mixed_reliable(lap_hierarchy* h, const double* b, double* x, double tol,
+                                lap_solve_info* info, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int n = (int)h->n;
+    const Engine<double>& e = h->e64;
+    Engine<float>& f = h->e32;
+    begin_solve(h, b, true, s);
+    const double bn2 = read_scal(h, h->So, s).res2;
+    if (!std::isfinite(bn2)) return LAP_EINVAL;
+    // FP32 run from r = b^ (x32 = 0, p = 0)
+    std::memset(h->stage, 0, sizeof(Scal));
+    h->stage->tol2 = tol * tol;
+    h->stage->maxit = h->params.max_iter;
+    HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, (const double*)h->r64,
+                       h->part);
+    finish<kFinBsum>(h, s, h->S, nblk(n));
+    hipLaunchKernelGGL(k_init<float>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s,
+                       (const double*)h->r64, f.r, f.x, f.p[0], f.p[1], (const Scal*)h->S,
+                       h->part);
+    finish<kFinBn2>(h, s, h->S, nblk(n));
+    enqueue_precond(h, f, s, 0, (const float*)f.p[0]);
+    HIPCHK(hipGetLastError());
+    double res2 = bn2, rr_last = bn2;
+    int refs = 0;
+    lap_status st = LAP_ENOCONV;
+    while (true) {
+        HIPCHK(hipGraphLaunch(f.exec, s));
+        Scal S = read_scal(h, h->S, s);
+        const bool replace = S.done == 1 || (S.done == 0 && S.rr <= kReliableDrop * rr_last);
+        if (S.done != 0 && S.done != 1) {
+            st = to_status(S.done);
+            break;
+        }
+        if (!replace) continue;
+        // reliable update
+        hipLaunchKernelGGL(k_move_corr, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->x64, f.x);
+        hipLaunchKernelGGL(k_resid, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A,
+                           (const double*)h->x64, (const double*)h->bh, h->r64, h->part);
+        finish<kFinRes2>(h, s, h->So, e.spmv_grid());
+        HIPCHK(hipGetLastError());
+        const double nr2 = read_scal(h, h->So, s).res2;
+        ++refs;
+        if (!std::isfinite(nr2)) {
+            st = LAP_EBREAKDOWN;
+            break;
+        }
+        res2 = nr2;
+        if (res2 <= tol * tol * bn2) {
+            st = LAP_OK;
+            break;
+        }
+        if (S.iter >= h->params.max_iter) break;
+        hipLaunchKernelGGL(k_residual_in, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s,
+                           (const double*)h->r64, f.r);
+        // continue the run: beta_new = rho' / rho_prev with rho_prev =
+        // rho / beta (the finish divides the new rho by the stored one)
+        Scal& st2 = *h->stage;
+        st2 = S;
+        st2.done = 0;
+        st2.first = S.beta > 0.0 ? 0 : 1;
+        st2.rho = S.beta > 0.0 ? S.rho / S.beta : S.rho;
+        HIPCHK(hipMemcpyAsync(h->S, &st2, sizeof(Scal), hipMemcpyHostToDevice, s));
+        enqueue_precond(h, f, s, 0, (const float*)f.p[0]);
+        HIPCHK(hipGetLastError());
+        rr_last = res2;
+    }
+    const Scal R = read_scal(h, h->S, s);
+    finalize_x(h, h->x64, x, s);
+    const Scal O = read_scal(h, h->So, s);
+    if (st == LAP_OK && !(O.res2 <= tol * tol * bn2 * 1.0001)) st = LAP_ENOCONV;
+    if (info) {
+        const double bn = std::sqrt(bn2);
+        info->iterations = R.iter;
+        info->refinements = refs;
+        info->relres_true = bn > 0 ? std::sqrt(O.res2) / bn : 0.0;
+        info->relres_recursive = bn > 0 ? std::sqrt(res2) / bn : 0.0;
+        info->status = st;
+        info->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
 }
 
 int rank_status(lap_status s) {
@@ -1965,8 +2060,10 @@ lap_status lap_solve(lap_hierarchy* h, const double* b, double* x, int32_t nrhs,
             const double* bc = b + (int64_t)c * ld;
             double* xc = x + (int64_t)c * ld;
             lap_solve_info* ic = info ? info + c : nullptr;
-            const lap_status st = h->mixed ? solve_mixed(h, bc, xc, tol, ic, (hipStream_t)stream)
-                                           : solve_fp64(h, bc, xc, tol, ic, (hipStream_t)stream);
+            const lap_status st =
+                !h->mixed ? solve_fp64(h, bc, xc, tol, ic, (hipStream_t)stream)
+                : h->reliable ? solve_mixed_reliable(h, bc, xc, tol, ic, (hipStream_t)stream)
+                              : solve_mixed(h, bc, xc, tol, ic, (hipStream_t)stream);
             if (rank_status(st) > rank_status(worst)) worst = st;
         }
     } catch (const HipErr&) {
