@@ -207,6 +207,12 @@ __device__ inline int spmv_block(int nhb) {
     return xcd_map(b - nhb, gridDim.x - nhb);
 }
 
+// Data read once per iteration and not again before the next (the matrix,
+// the pair coefficients, the packed coefficients of level groups) is loaded
+// non-temporally, so it does not evict the vectors the next kernels re-read.
+template <class V>
+__device__ inline V ld_nt(const V* p) { return __builtin_nontemporal_load(p); }
+
 // -------------------------------------------------------- Laplacian rows
 
 // One light row of sliced ELL: sum over its slots of w * diff(j), where
@@ -229,8 +235,10 @@ __device__ inline T light_row(const Sell<T>& A, int slot, F diff) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (k + u < W) {
-                j[u] = A.col[base + (k + u) * 64];
-                w[u] = A.w[base + (k + u) * 64];
+                // the matrix streams through once per product: non-temporal,
+                // so it does not evict the vectors the next kernels re-read
+                j[u] = ld_nt(A.col + base + (k + u) * 64);
+                w[u] = ld_nt(A.w + base + (k + u) * 64);
             }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -247,7 +255,8 @@ __device__ inline T light_row(const Sell<T>& A, int slot, F diff) {
 template <class T, class F>
 __device__ inline T heavy_share(const Sell<T>& A, int h, int t, int nt, F diff) {
     T acc = T(0);
-    for (int q = A.hptr[h] + t; q < A.hptr[h + 1]; q += nt) acc += A.hw[q] * diff(A.hcol[q]);
+    for (int q = A.hptr[h] + t; q < A.hptr[h + 1]; q += nt)
+        acc += ld_nt(A.hw + q) * diff(ld_nt(A.hcol + q));
     return acc;
 }
 
@@ -877,19 +886,20 @@ __global__ __launch_bounds__(kBlock) void k_down(LevelDev<T> s, const T* __restr
 
 // ------------------------------------------------------- grouped levels
 
-// Flat copy global -> LDS with eight loads in flight per thread.
-template <class T>
+// Flat copy global -> LDS with eight loads in flight per thread (NT:
+// non-temporal loads, for data read once per iteration).
+template <class T, bool NT = false>
 __device__ inline void stage_copy(T* __restrict__ dst, const T* __restrict__ src, int len) {
     constexpr int U = 8, B = kGrpThreads;
     int i = threadIdx.x;
     for (; i + (U - 1) * B < len; i += U * B) {
         T t[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) t[u] = src[i + u * B];
+        for (int u = 0; u < U; ++u) t[u] = NT ? ld_nt(src + i + u * B) : src[i + u * B];
 #pragma unroll
         for (int u = 0; u < U; ++u) dst[i + u * B] = t[u];
     }
-    for (; i < len; i += B) dst[i] = src[i];
+    for (; i < len; i += B) dst[i] = NT ? ld_nt(src + i) : src[i];
 }
 
 // Per-block bookkeeping of a group (level ranges and LDS layout) lives in
@@ -928,7 +938,7 @@ __global__ __launch_bounds__(kGrpThreads) void k_up_grp(GroupDev<T> G, const Sca
     const int32_t* st = B.st;
     const int32_t* cnt = B.cnt;
     const GrpLayout& L = B.L;
-    stage_copy(sm, G.upack + G.uoff[blockIdx.x], L.ulen);
+    stage_copy<T, true>(sm, G.upack + G.uoff[blockIdx.x], L.ulen);
     stage_copy(sm + L.ur[0], G.r_in + st[0], cnt[0]);
     __syncthreads();
     T* scr = G.scr + G.xoff[blockIdx.x];
@@ -975,7 +985,7 @@ __global__ __launch_bounds__(kGrpThreads) void k_down_grp(GroupDev<T> G, const S
     const int32_t* st = B.st;
     const int32_t* cnt = B.cnt;
     const GrpLayout& L = B.L;
-    stage_copy(sm, G.dpack + G.doff[blockIdx.x], L.dlen);
+    stage_copy<T, true>(sm, G.dpack + G.doff[blockIdx.x], L.dlen);
     stage_copy(sm + L.dx, G.scr + G.xoff[blockIdx.x], L.xlen);
     stage_copy(sm + L.dr0, G.r_in + st[0], cnt[0]);
     stage_copy(sm + L.dy[m], G.y_top + st[m], cnt[m]);
