@@ -225,6 +225,11 @@ __global__ __launch_bounds__(kMmWaves * 64) void k_mm_pupd(int n, const T* __res
                                                            const ScalM* S) {
     if (S->all_done) return;
     const int c = threadIdx.x & 63;
+    // A stopped column keeps its last direction: repeating the update with
+    // its final beta would grow p geometrically whenever beta > 1 and
+    // overflow while the other columns run on (then alpha = 0 times an
+    // infinite p puts NaN into x).  Admission zeroes both directions.
+    if (S->done[c] != 0) return;
     const T zb = (T)S->zbar[c], be = (T)S->beta[c];
     MM_FOR(i, n) {
         const size_t o = (size_t)i * kCols + c;
@@ -250,12 +255,19 @@ __global__ __launch_bounds__(kMmWaves * 64) void k_mm_spmm(Csr<T> A, Chunks C,
         const T pi = p[(size_t)row * kCols + c];
         T acc = T(0);
         int k = k0;
-        for (; k + 3 < k1; k += 4) {
-            const int j0 = A.col[k], j1 = A.col[k + 1], j2 = A.col[k + 2], j3 = A.col[k + 3];
-            const T p0 = p[(size_t)j0 * kCols + c], p1 = p[(size_t)j1 * kCols + c];
-            const T p2 = p[(size_t)j2 * kCols + c], p3 = p[(size_t)j3 * kCols + c];
-            acc += A.w[k] * (pi - p0) + A.w[k + 1] * (pi - p1) + A.w[k + 2] * (pi - p2) +
-                   A.w[k + 3] * (pi - p3);
+        // eight entries' gathers in flight per wavefront
+        for (; k + 7 < k1; k += 8) {
+            int j[8];
+            T wv[8], pv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                j[u] = A.col[k + u];
+                wv[u] = A.w[k + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) pv[u] = p[(size_t)j[u] * kCols + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += wv[u] * (pi - pv[u]);
         }
         for (; k < k1; ++k) acc += A.w[k] * (pi - p[(size_t)A.col[k] * kCols + c]);
         const int sl = C.slot[it];
