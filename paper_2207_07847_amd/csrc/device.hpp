@@ -101,7 +101,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
                                                         Scal* S) {
     constexpr int N = (OP == kFinRho) ? 4 : 1;
     constexpr bool loop = OP == kFinPq || OP == kFinRr || OP == kFinRho;
-    if (loop && S->done) return;
+    // the state read below, and the stop flag, are loaded together with the
+    // partials: one memory latency for all of them
+    const int done = S->done, iter = S->iter, maxit = S->maxit, first = S->first;
+    const double rho0 = S->rho, tol2 = S->tol2, bn2 = S->bn2;
     __shared__ double lds[N * (kFinThreads / 64)];
     double v[N];
 #pragma unroll
@@ -126,11 +129,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
                 const int b = tid + u * kFinThreads;
                 a[N - 1][u] = b < G2 ? part2[b] : 0.0;
             }
+        // (starting the sum from the first partial rather than from 0.0
+        // keeps the compiler from waiting on that load before issuing the
+        // others)
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            double t = 0.0;
+            double t = a[i][0];
 #pragma unroll
-            for (int u = 0; u < U; ++u) t += a[i][u];
+            for (int u = 1; u < U; ++u) t += a[i][u];
             v[i] = t;
         }
     } else {
@@ -139,32 +145,33 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
         if (OP == kFinRho)
             for (int b = tid; b < G2; b += kFinThreads) v[N - 1] += part2[b];
     }
+    if (loop && done) return;
     block_sum<N, kFinThreads>(v, lds);
     if (threadIdx.x != 0) return;
     if (OP == kFinPq) {
         const double pq = v[0];
         S->pq = pq;
-        S->iter += 1;
+        S->iter = iter + 1;
         if (!(pq > 0.0) || !isfinite(pq)) S->done = 3;
-        else S->alpha = S->rho / pq;
+        else S->alpha = rho0 / pq;
     } else if (OP == kFinRr) {
         S->rr = v[0];
         if (!isfinite(v[0])) S->done = 3;
-        else if (v[0] <= S->tol2 * S->bn2) S->done = 1;
-        else if (S->iter >= S->maxit) S->done = 2;
+        else if (v[0] <= tol2 * bn2) S->done = 1;
+        else if (iter >= maxit) S->done = 2;
     } else if (OP == kFinRho) {
         const double zbar = v[0] / (double)n;
         const double rho = v[1] - zbar * v[2];
         S->zbar = zbar;
         if (!isfinite(rho)) S->done = 3;
-        S->beta = S->first ? 0.0 : rho / S->rho;
+        S->beta = first ? 0.0 : rho / rho0;
         S->first = 0;
         S->rho = rho;
         if (G2 > 0) {
             S->rr = v[3];
             if (!isfinite(v[3])) S->done = 3;
-            else if (v[3] <= S->tol2 * S->bn2) S->done = 1;
-            else if (S->iter >= S->maxit) S->done = 2;
+            else if (v[3] <= tol2 * bn2) S->done = 1;
+            else if (iter >= maxit) S->done = 2;
         }
     } else if (OP == kFinBsum) {
         S->bsum = v[0];
@@ -178,7 +185,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
         S->rr = v[0];
         if (!isfinite(v[0])) S->done = 4;
         else if (v[0] == 0.0) S->done = 1;
-        else if (S->maxit <= 0) S->done = 2;
+        else if (maxit <= 0) S->done = 2;
         else S->done = 0;
     } else if (OP == kFinXsum) {
         S->xsum = v[0];
@@ -297,8 +304,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* 
                                                    const T* __restrict__ pold,
                                                    T* __restrict__ pnew, T* __restrict__ q,
                                                    Scal* S, double* part) {
-    if (S->done) return;
+    // the stop flag is loaded with the scalars the kernel needs (one
+    // memory latency before the first data loads, not two)
+    const int done = S->done;
     const T beta = (T)S->beta, zbar = (T)S->zbar;
+    if (done) return;
     const int lb = spmv_block(A.nheavyblk);
     double v[1] = {0.0};
     if (lb >= 0) {
@@ -336,8 +346,9 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_pupd(int n, const T* __restrict__ zn,
                                                  const T* __restrict__ pold, T* __restrict__ pnew,
                                                  const Scal* S) {
-    if (S->done) return;
+    const int done = S->done;
     const T beta = (T)S->beta, zbar = (T)S->zbar;
+    if (done) return;
     const int t = xcd_block() * kBlock + threadIdx.x;
     if (t < n) pnew[t] = (zn[t] - zbar) + beta * pold[t];
 }
@@ -575,13 +586,14 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev<T> s0,
                                                        const T* __restrict__ q,
                                                        T* __restrict__ r1, Scal* S, double* part,
                                                        int do_update) {
-    if (S->done) return;
     __shared__ T rs[kCapP];
     __shared__ double red[4 * (kBlock / 64)];
     __shared__ int nbig, big[kAggPerBlock];
+    const int done = S->done;
     const T alpha = (T)S->alpha;
     const int b = xcd_block();
     const int J0 = s0.bst[b], J1 = s0.bst[b + 1];
+    if (done) return;
     const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
     double rr = 0.0;
     if (len <= kCapP) {
@@ -631,10 +643,11 @@ __global__ __launch_bounds__(kBlock) void k_down0(LevelDev<T> s0, const int32_t*
                                                   const T* __restrict__ r, T* __restrict__ zn,
                                                   const T* __restrict__ y1, Scal* S,
                                                   double* part) {
-    if (S->done) return;
     __shared__ DownBlock<T> D;
+    const int done = S->done;
     const int b = xcd_block();
     const int J0 = s0.bst[b], J1 = s0.bst[b + 1];
+    if (done) return;
     const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
     double v[3] = {0.0, 0.0, 0.0};
     if (down_stage(s0, y1, J0, J1, t0, len, D)) {
@@ -678,13 +691,14 @@ __global__ __launch_bounds__(kBlock) void k_update_up01(LevelDev<T> s0, LevelDev
                                                         const T* __restrict__ q,
                                                         T* __restrict__ r2, Scal* S, double* part,
                                                         int do_update) {
-    if (S->done) return;
     __shared__ T rs[kCapP];
     __shared__ T r1s[kAggPerBlock];
     __shared__ int nbig, big[kAggPerBlock];
+    const int done = S->done;
     const T alpha = (T)S->alpha;
     const int b = xcd_block();
     const int A0 = bst[b], A1 = bst[b + 1];
+    if (done) return;
     const int J0 = s1.cptr[A0], J1 = s1.cptr[A1];
     const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
     double rr = 0.0;
@@ -729,11 +743,12 @@ __global__ __launch_bounds__(kBlock) void k_down01(LevelDev<T> s0, LevelDev<T> s
                                                    const T* __restrict__ r, T* __restrict__ zn,
                                                    const T* __restrict__ y2, Scal* S,
                                                    double* part) {
-    if (S->done) return;
     __shared__ DownBlock<T> D;
     __shared__ T y1s[kAggPerBlock];
+    const int done = S->done;
     const int b = xcd_block();
     const int A0 = bst[b], A1 = bst[b + 1];
+    if (done) return;
     const int J0 = s1.cptr[A0], J1 = s1.cptr[A1];
     const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
     // level 2 -> 1 into LDS
@@ -843,12 +858,13 @@ __global__ __launch_bounds__(kBlock) void k_top_only(int n, const int32_t* __res
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_up(LevelDev<T> s, const T* __restrict__ rk,
                                                T* __restrict__ rk1, const Scal* S) {
-    if (S->done) return;
     __shared__ T rs[kCapP];
     __shared__ double red[3 * (kBlock / 64)];
     __shared__ int nbig, big[kAggPerBlock];
+    const int done = S->done;
     const int b = xcd_block();
     const int J0 = s.bst[b], J1 = s.bst[b + 1];
+    if (done) return;
     const int t0 = s.cptr[J0], len = s.cptr[J1] - t0;
     if (len <= kCapP) {
         if (threadIdx.x == 0) nbig = 0;
@@ -867,10 +883,11 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_down(LevelDev<T> s, const T* __restrict__ rk,
                                                  T* __restrict__ yk, const T* __restrict__ yk1,
                                                  const Scal* S) {
-    if (S->done) return;
     __shared__ DownBlock<T> D;
+    const int done = S->done;
     const int b = xcd_block();
     const int J0 = s.bst[b], J1 = s.bst[b + 1];
+    if (done) return;
     const int t0 = s.cptr[J0], len = s.cptr[J1] - t0;
     if (down_stage(s, yk1, J0, J1, t0, len, D)) {
         for (int i = threadIdx.x; i < len; i += kBlock) {
@@ -908,20 +925,45 @@ __device__ inline void stage_copy(T* __restrict__ dst, const T* __restrict__ src
 struct GrpBlock {
     int32_t st[kMaxGroupLevels + 1];
     int32_t cnt[kMaxGroupLevels + 1];
+    int32_t off[2];  // pack and scratch offsets of the block
     GrpLayout L;
 };
 
+// The block's level ranges and its pack and scratch offsets are loaded by
+// the lanes of wavefront 0 in one load instruction (lane j <= m: first node
+// of level j; lane m+1+j: its end; lanes 62, 63: pack and scratch offsets),
+// together with the stop flag; false: the solve has stopped.  (Everything
+// lands in GrpBlock: static LDS stays small, and with it the occupancy.)
 template <class T>
-__device__ inline void grp_setup(const GroupDev<T>& G, int m, GrpBlock& B) {
-    if (threadIdx.x == 0) {
-        const int b = blockIdx.x, nb1 = G.nblocks + 1;
-        for (int j = 0; j <= m; ++j) {
-            B.st[j] = G.D[j * nb1 + b];
-            B.cnt[j] = G.D[j * nb1 + b + 1] - B.st[j];
+__device__ inline bool grp_setup(const GroupDev<T>& G, int m, GrpBlock& B,
+                                 const int32_t* pack_off, const Scal* S) {
+    static_assert(kGrpThreads > 64 && 2 * kMaxGroupLevels + 1 < 62, "setup lanes");
+    const int done = S->done;
+    const int b = blockIdx.x, nb1 = G.nblocks + 1, tid = threadIdx.x;
+    if (tid < 64) {
+        const int32_t* src = G.D;
+        int32_t* dst = nullptr;
+        if (tid <= m) {
+            src = G.D + tid * nb1 + b;
+            dst = B.st + tid;
+        } else if (tid <= 2 * m + 1) {
+            src = G.D + (tid - m - 1) * nb1 + b + 1;
+            dst = B.cnt + (tid - m - 1);
+        } else if (tid >= 62) {
+            src = (tid == 62 ? pack_off : G.xoff) + b;
+            dst = B.off + (tid - 62);
         }
+        const int32_t v = *src;
+        if (dst) *dst = v;
+    }
+    if (done) return false;
+    __syncthreads();
+    if (tid == 0) {
+        for (int j = 0; j <= m; ++j) B.cnt[j] -= B.st[j];
         grp_layout(m, B.cnt, (int)(sizeof(T) / sizeof(int32_t)), B.L);
     }
     __syncthreads();
+    return true;
 }
 
 // Up-sweep of a level group [k0, k1): level-k0 residuals in, level-k1
@@ -929,19 +971,19 @@ __device__ inline void grp_setup(const GroupDev<T>& G, int m, GrpBlock& B) {
 // block's scratch chunk for the down-sweep.
 template <class T>
 __global__ __launch_bounds__(kGrpThreads) void k_up_grp(GroupDev<T> G, const Scal* S) {
-    if (S->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     T* sm = reinterpret_cast<T*>(smem);
     const int m = G.k1 - G.k0, tid = threadIdx.x, nth = blockDim.x;
     __shared__ GrpBlock B;
-    grp_setup(G, m, B);
+    if (!grp_setup(G, m, B, G.uoff, S)) return;
+    const int32_t* off = B.off;
     const int32_t* st = B.st;
     const int32_t* cnt = B.cnt;
     const GrpLayout& L = B.L;
-    stage_copy<T, true>(sm, G.upack + G.uoff[blockIdx.x], L.ulen);
+    stage_copy<T, true>(sm, G.upack + off[0], L.ulen);
     stage_copy(sm + L.ur[0], G.r_in + st[0], cnt[0]);
     __syncthreads();
-    T* scr = G.scr + G.xoff[blockIdx.x];
+    T* scr = G.scr + off[1];
     for (int j = 0; j < m; ++j) {
         const int na = cnt[j + 1], nl = cnt[j] - 2 * na;
         const int* cp = reinterpret_cast<const int*>(sm + L.ucp[j]);
@@ -976,17 +1018,17 @@ __global__ __launch_bounds__(kGrpThreads) void k_up_grp(GroupDev<T> G, const Sca
 // Down-sweep of a level group: level-k1 corrections in, level-k0 out.
 template <class T>
 __global__ __launch_bounds__(kGrpThreads) void k_down_grp(GroupDev<T> G, const Scal* S) {
-    if (S->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     T* sm = reinterpret_cast<T*>(smem);
     const int m = G.k1 - G.k0, tid = threadIdx.x, nth = blockDim.x;
     __shared__ GrpBlock B;
-    grp_setup(G, m, B);
+    if (!grp_setup(G, m, B, G.doff, S)) return;
+    const int32_t* off = B.off;
     const int32_t* st = B.st;
     const int32_t* cnt = B.cnt;
     const GrpLayout& L = B.L;
-    stage_copy<T, true>(sm, G.dpack + G.doff[blockIdx.x], L.dlen);
-    stage_copy(sm + L.dx, G.scr + G.xoff[blockIdx.x], L.xlen);
+    stage_copy<T, true>(sm, G.dpack + off[0], L.dlen);
+    stage_copy(sm + L.dx, G.scr + off[1], L.xlen);
     stage_copy(sm + L.dr0, G.r_in + st[0], cnt[0]);
     stage_copy(sm + L.dy[m], G.y_top + st[m], cnt[m]);
     __syncthreads();
@@ -1026,16 +1068,22 @@ __global__ __launch_bounds__(kGrpThreads) void k_down_grp(GroupDev<T> G, const S
 // aggregate with many children (a hub of a power-law graph) is reduced by
 // the whole workgroup after the others of its level.
 template <class T>
-__global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restrict__ D,
+__global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restrict__ Dg, TailArgs ta,
                                                        const T* __restrict__ pack,
                                                        const T* __restrict__ r_kt,
                                                        T* __restrict__ y_kt, const Scal* S) {
-    if (S->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     T* sm = reinterpret_cast<T*>(smem);
     __shared__ double red[3 * (kTailThreads / 64)];
+    // the descriptor is read at every level: one copy into LDS up front
+    // instead of a dependent global load per step
+    __shared__ TailDesc Dl;
+    const TailDesc* D = &Dl;
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int npack = D->pack, nsteps = D->nsteps;
+    const int npack = ta.npack, nsteps = ta.nsteps;
+    // the stop flag is tested after the staging loads are issued, so its
+    // latency overlaps theirs (a stopped solve stages for nothing)
+    const int done = S->done;
     {
         // eight loads in flight per thread
         constexpr int U = 8;
@@ -1050,10 +1098,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restric
         for (; i < npack; i += kTailThreads) sm[i] = pack[i];
     }
     {
-        const int n0 = nsteps > 0 ? D->st[0].nk : D->nt;
-        T* r0 = sm + D->r[0];
-        for (int i = tid; i < n0; i += nth) r0[i] = r_kt[i];
+        constexpr int W = (int)(sizeof(TailDesc) / sizeof(int32_t));
+        static_assert(W <= kTailThreads, "one word per thread");
+        const int32_t w = reinterpret_cast<const int32_t*>(Dg)[tid < W ? tid : W - 1];
+        if (tid < W) reinterpret_cast<int32_t*>(&Dl)[tid] = w;
+        T* r0 = sm + ta.r0;
+        for (int i = tid; i < ta.n0; i += nth) r0[i] = r_kt[i];
     }
+    if (done) return;
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
         const TailStep t = D->st[s];

@@ -91,6 +91,15 @@ struct TailDesc {
     TailStep st[kMaxTailSteps];
 };
 
+// The descriptor fields the tail needs before anything else, passed by
+// value so its first loads do not wait for them.
+struct TailArgs {
+    int32_t npack;   // TailDesc::pack
+    int32_t nsteps;  // TailDesc::nsteps
+    int32_t n0;      // nodes on level kt
+    int32_t r0;      // TailDesc::r[0]
+};
+
 // A group of consecutive levels [k0, k1) processed block-locally: block b
 // owns the level-k1 nodes [D[m][b], D[m][b+1]) (m = k1 - k0) and, on every
 // level j = k0 + i, their descendants [D[i][b], D[i][b+1]), contiguous in the
@@ -98,7 +107,7 @@ struct TailDesc {
 // the order of its LDS carve, so staging is one flat copy; the up-sweep
 // leaves its intermediate values in a per-block scratch chunk laid out for
 // the down-sweep's carve.
-constexpr int kGrpThreads = 256;
+constexpr int kGrpThreads = 512;
 constexpr int kMaxGroupLevels = 12;
 template <class T>
 struct GroupDev {

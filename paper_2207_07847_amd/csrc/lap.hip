@@ -62,6 +62,10 @@ double env_double(const char* name, double dflt) {
 }
 
 constexpr size_t kTailLdsBytes = 152 * 1024;
+// dynamic LDS + the tail's static descriptor copy and reduction space fit a CU
+static_assert(kTailLdsBytes + sizeof(TailDesc) + 3 * (kTailThreads / 64) * sizeof(double) <=
+                  160 * 1024,
+              "tail LDS");
 constexpr int kProfGroup = 10;          // timed iterations per fresh run (profiling)
 constexpr double kReliableDrop = 1e-2;  // ||r||^2 drop between reliable updates
 constexpr size_t kGrpLdsBytes = 64 * 1024;
@@ -294,6 +298,7 @@ struct Engine {
     TailDesc* d_tail = nullptr;
     T* tail_pack = nullptr;
     size_t tail_lds = 0;         // bytes
+    TailArgs tail_args{};
     struct Segment {
         bool group = false;
         int k0 = 0, k1 = 1;
@@ -569,7 +574,8 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
                                (const T*)e.lv[G.k0].r, e.lv[G.k0 + 1].r, (const Scal*)S);
     }
     hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(kTailThreads), e.tail_lds, s,
-                       (const TailDesc*)e.d_tail, (const T*)e.tail_pack, (const T*)e.lv[e.kt].r,
+                       (const TailDesc*)e.d_tail, e.tail_args, (const T*)e.tail_pack,
+                       (const T*)e.lv[e.kt].r,
                        e.lv[e.kt].y, (const Scal*)S);
     for (auto it = e.segs.rbegin(); it != e.segs.rend(); ++it) {
         const auto& G = *it;
@@ -790,6 +796,10 @@ void upload_engine(lap_hierarchy* h, Engine<T>& e, hipStream_t s, bool with_leve
     HIPCHK(hipMemcpyAsync(e.d_tail, &desc, sizeof(desc), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     e.tail_lds = (size_t)desc.total * sizeof(T);
+    e.tail_args.npack = desc.pack;
+    e.tail_args.nsteps = desc.nsteps;
+    e.tail_args.n0 = desc.nsteps > 0 ? desc.st[0].nk : desc.nt;
+    e.tail_args.r0 = desc.r[0];
     HIPCHK(hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kTailLdsBytes));
     HIPCHK(hipFuncSetAttribute((const void*)k_up_grp<T>,
