@@ -919,6 +919,53 @@ __device__ inline void stage_copy(T* __restrict__ dst, const T* __restrict__ src
     for (; i < len; i += B) dst[i] = NT ? ld_nt(src + i) : src[i];
 }
 
+// Staging of up to four global ranges into LDS at once: segment k copies
+// len[k] values from src[k] to dst[k] (the first nnt segments with
+// non-temporal loads).  The ranges are walked as one concatenated index
+// space, U loads in flight per thread, so every load of every segment is
+// issued before the first LDS write waits for data: one memory latency
+// instead of one per range.
+template <class T, int U, int NTH>
+struct StageSet {
+    const T* src[4];
+    T* dst[4];
+    int end[4];  // running ends of the segments in the concatenated space
+    int nnt;
+};
+template <class T, int U, int NTH>
+__device__ inline void stage_set(const StageSet<T, U, NTH>& S) {
+    // segment selection by comparisons and selects only: an array indexed
+    // at run time would be placed in scratch memory
+    const int e0 = S.end[0], e1 = S.end[1], e2 = S.end[2], total = S.end[3];
+    const int nnt = S.nnt;
+    for (int base = threadIdx.x; base < total; base += U * NTH) {
+        T t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * NTH;
+            if (i < total) {
+                const int k = i < e0 ? 0 : i < e1 ? 1 : i < e2 ? 2 : 3;
+                const T* p = k == 0 ? S.src[0] + i
+                           : k == 1 ? S.src[1] + (i - e0)
+                           : k == 2 ? S.src[2] + (i - e1)
+                                    : S.src[3] + (i - e2);
+                t[u] = k < nnt ? ld_nt(p) : *p;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * NTH;
+            if (i < total) {
+                T* d = i < e0 ? S.dst[0] + i
+                     : i < e1 ? S.dst[1] + (i - e0)
+                     : i < e2 ? S.dst[2] + (i - e1)
+                              : S.dst[3] + (i - e2);
+                *d = t[u];
+            }
+        }
+    }
+}
+
 // Per-block bookkeeping of a group (level ranges and LDS layout) lives in
 // LDS: it is indexed by the level inside loops, and a runtime-indexed
 // private array would be placed in scratch memory.
@@ -980,8 +1027,19 @@ __global__ __launch_bounds__(kGrpThreads) void k_up_grp(GroupDev<T> G, const Sca
     const int32_t* st = B.st;
     const int32_t* cnt = B.cnt;
     const GrpLayout& L = B.L;
-    stage_copy<T, true>(sm, G.upack + off[0], L.ulen);
-    stage_copy(sm + L.ur[0], G.r_in + st[0], cnt[0]);
+    {
+        StageSet<T, 16, kGrpThreads> ss;
+        ss.src[0] = G.upack + off[0];
+        ss.dst[0] = sm;
+        ss.end[0] = L.ulen;
+        ss.src[1] = G.r_in + st[0];
+        ss.dst[1] = sm + L.ur[0];
+        ss.end[1] = ss.end[2] = ss.end[3] = L.ulen + cnt[0];
+        ss.src[2] = ss.src[3] = ss.src[1];
+        ss.dst[2] = ss.dst[3] = ss.dst[1];
+        ss.nnt = 1;
+        stage_set(ss);
+    }
     __syncthreads();
     T* scr = G.scr + off[1];
     for (int j = 0; j < m; ++j) {
@@ -1027,10 +1085,23 @@ __global__ __launch_bounds__(kGrpThreads) void k_down_grp(GroupDev<T> G, const S
     const int32_t* st = B.st;
     const int32_t* cnt = B.cnt;
     const GrpLayout& L = B.L;
-    stage_copy<T, true>(sm, G.dpack + off[0], L.dlen);
-    stage_copy(sm + L.dx, G.scr + off[1], L.xlen);
-    stage_copy(sm + L.dr0, G.r_in + st[0], cnt[0]);
-    stage_copy(sm + L.dy[m], G.y_top + st[m], cnt[m]);
+    {
+        StageSet<T, 16, kGrpThreads> ss;
+        ss.src[0] = G.dpack + off[0];
+        ss.dst[0] = sm;
+        ss.end[0] = L.dlen;
+        ss.src[1] = G.scr + off[1];
+        ss.dst[1] = sm + L.dx;
+        ss.end[1] = ss.end[0] + L.xlen;
+        ss.src[2] = G.r_in + st[0];
+        ss.dst[2] = sm + L.dr0;
+        ss.end[2] = ss.end[1] + cnt[0];
+        ss.src[3] = G.y_top + st[m];
+        ss.dst[3] = sm + L.dy[m];
+        ss.end[3] = ss.end[2] + cnt[m];
+        ss.nnt = 1;
+        stage_set(ss);
+    }
     __syncthreads();
     for (int j = m - 1; j >= 0; --j) {
         const int na = cnt[j + 1], nl = cnt[j] - 2 * na;
@@ -1085,25 +1156,19 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restric
     // latency overlaps theirs (a stopped solve stages for nothing)
     const int done = S->done;
     {
-        // eight loads in flight per thread
-        constexpr int U = 8;
-        int i = tid;
-        for (; i + (U - 1) * kTailThreads < npack; i += U * kTailThreads) {
-            T t[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) t[u] = pack[i + u * kTailThreads];
-#pragma unroll
-            for (int u = 0; u < U; ++u) sm[i + u * kTailThreads] = t[u];
-        }
-        for (; i < npack; i += kTailThreads) sm[i] = pack[i];
-    }
-    {
         constexpr int W = (int)(sizeof(TailDesc) / sizeof(int32_t));
         static_assert(W <= kTailThreads, "one word per thread");
         const int32_t w = reinterpret_cast<const int32_t*>(Dg)[tid < W ? tid : W - 1];
+        StageSet<T, 16, kTailThreads> ss;
+        ss.src[0] = pack;
+        ss.dst[0] = sm;
+        ss.end[0] = npack;
+        ss.src[1] = ss.src[2] = ss.src[3] = r_kt;
+        ss.dst[1] = ss.dst[2] = ss.dst[3] = sm + ta.r0;
+        ss.end[1] = ss.end[2] = ss.end[3] = npack + ta.n0;
+        ss.nnt = 0;
+        stage_set(ss);
         if (tid < W) reinterpret_cast<int32_t*>(&Dl)[tid] = w;
-        T* r0 = sm + ta.r0;
-        for (int i = tid; i < ta.n0; i += nth) r0[i] = r_kt[i];
     }
     if (done) return;
     __syncthreads();
