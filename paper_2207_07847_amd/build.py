@@ -17,8 +17,12 @@ LIB = os.path.join(HERE, "liblapgpu.so")
 ARCH = os.environ.get("LAPGPU_ARCH", "gfx950")
 
 # Packed FP32 instructions stay off on this target (see the design notes).
+# Kernel arguments are preloaded into SGPRs (up to 16 dwords): a kernel's
+# first loads then do not wait for a load of its own arguments.  The
+# compiler keeps a prologue that loads them for firmware without preload.
 HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-kernarg-preload-count=16",
              "-Wall", "-Wno-unused-result"]
 
 
