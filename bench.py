@@ -465,6 +465,12 @@ def main():
             "traffic": pmc_traffic(args.workload, args.scale) if args.precision == "fp64" else None,
         },
     }
+    if args.nrhs > 1:
+        k = 1 if args.precision != "fp64" else 0
+        line["autotuned"] = {"spmm_entries_per_item": info["mm_chunk"][k],
+                             "spmm_workgroups": info["mm_grid"][k],
+                             "level_children_per_item": info["mm_seg"][k],
+                             "tune_s": info["mm_tune_seconds"]}
     if base is not None:
         bi = base["info"]
         line["fp64_same_gpu"] = {

@@ -104,6 +104,16 @@ typedef struct {
     int64_t nnz;                  /* stored adjacency entries of L_G (2m) */
     int64_t device_bytes;         /* device memory held by the hierarchy */
     double setup_seconds;         /* host time spent in lap_setup */
+    /* Block solve (LAP_FLAG_MULTI_RHS), index 0 FP64, 1 the FP32 inner
+     * solve of mixed precision; 0 where absent.  Sizes picked at set-up by
+     * timing candidates on the device (the autotuner):
+     *   mm_chunk: matrix entries per SpMM work item (longer rows are split);
+     *   mm_grid:  workgroups of the SpMM launch;
+     *   mm_seg:   children per work item of restriction and prolongation. */
+    int32_t mm_chunk[2];
+    int32_t mm_grid[2];
+    int32_t mm_seg[2];
+    double mm_tune_seconds;       /* host time of the autotuner in lap_setup */
 } lap_hierarchy_desc;
 
 typedef struct lap_hierarchy lap_hierarchy;

@@ -52,7 +52,9 @@ class lap_solve_info(C.Structure):
 class lap_hierarchy_desc(C.Structure):
     _fields_ = [("nlev", C.c_int32), ("tail_level", C.c_int32),
                 ("sizes", C.c_int64 * LAP_MAX_LEVELS), ("ntilde", C.c_int64),
-                ("nnz", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double)]
+                ("nnz", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double),
+                ("mm_chunk", C.c_int32 * 2), ("mm_grid", C.c_int32 * 2),
+                ("mm_seg", C.c_int32 * 2), ("mm_tune_seconds", C.c_double)]
 
 
 class lap_request_result(C.Structure):
@@ -182,7 +184,9 @@ def lap_hierarchy_info(h) -> dict:
         raise LapError(st, "lap_hierarchy_info")
     return dict(nlev=d.nlev, tail_level=d.tail_level, sizes=list(d.sizes[:d.nlev]),
                 ntilde=d.ntilde, nnz=d.nnz, device_bytes=d.device_bytes,
-                setup_seconds=d.setup_seconds)
+                setup_seconds=d.setup_seconds, mm_chunk=list(d.mm_chunk),
+                mm_grid=list(d.mm_grid), mm_seg=list(d.mm_seg),
+                mm_tune_seconds=d.mm_tune_seconds)
 
 
 def lap_export_level(h, level: int, size: int):

@@ -14,9 +14,11 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <new>
+#include <stdexcept>
 #include <thread>
 #include <type_traits>
 #include <vector>
@@ -364,6 +366,10 @@ struct ChunkHost {
 template <class T>
 struct EngineM {
     bool on = false;
+    // sizes picked by the autotuner: matrix entries per SpMM work item (rows
+    // above it are split), workgroups of the SpMM, children per work item of
+    // the restriction and prolongation
+    int chunk = kMmChunk, grid = kMmMaxGrid, seg = kMmChunk;
     Csr<T> A{};
     Chunks CA{};
     T* scrA = nullptr;           // partial rows of split SpMM rows
@@ -385,9 +391,8 @@ struct EngineM {
     }
 };
 
-inline int mm_grid(int64_t items) {
-    return (int)std::max<int64_t>(1, std::min<int64_t>((items + kMmWaves - 1) / kMmWaves,
-                                                       kMmMaxGrid));
+inline int mm_grid(int64_t items, int cap = kMmMaxGrid) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((items + kMmWaves - 1) / kMmWaves, cap));
 }
 
 }  // namespace
@@ -408,6 +413,7 @@ struct lap_hierarchy {
     double setup_seconds = 0.0;
     int64_t dev_bytes = 0;
     std::vector<void*> allocs;
+    std::vector<size_t> alloc_bytes;
     // integer data shared by both engines
     int32_t* perm0 = nullptr;    // tree position -> input vertex
     // The solve order (x, p, q, the SpMV's copy of z, bh) is the input order
@@ -441,6 +447,7 @@ struct lap_hierarchy {
     double* part2 = nullptr;     // per-block ||r||^2 of the update kernel
     Scal* stage = nullptr;       // pinned host copy of S or So
     int chunk = 8;
+    double mm_tune_seconds = 0.0;  // block-solve autotuner time in lap_setup
     double inner_tol = 1e-4;
     bool reliable = true;        // mixed precision by reliable updates (else restarts)
 
@@ -450,8 +457,20 @@ struct lap_hierarchy {
         const size_t bytes = (count ? count : 1) * sizeof(T);
         if (hipMalloc(&ptr, bytes) != hipSuccess) throw std::bad_alloc();
         allocs.push_back(ptr);
+        alloc_bytes.push_back(bytes);
         dev_bytes += (int64_t)bytes;
         return static_cast<T*>(ptr);
+    }
+    // Frees every allocation made after mark() returned `mk` (the caller has
+    // synchronized the work that used them).
+    size_t mark() const { return allocs.size(); }
+    void release_to(size_t mk) {
+        while (allocs.size() > mk) {
+            (void)hipFree(allocs.back());
+            dev_bytes -= (int64_t)alloc_bytes.back();
+            allocs.pop_back();
+            alloc_bytes.pop_back();
+        }
     }
     // Uploads complete before return (host vectors may be temporaries).
     template <class T>
@@ -890,10 +909,6 @@ void upload_block_engine(lap_hierarchy* h, EngineM<T>& m, const Engine<T>& e, hi
         m.A.ptr = h->upload(g.ptr, s);
         m.A.col = h->upload(g.col, s);
         m.A.w = h->upload(convert<T>(g.w), s);
-        ChunkHost<int64_t> ch;
-        ch.build(g.ptr, kMmChunk);
-        m.CA = h->upload_chunks(ch, s);
-        m.scrA = h->dalloc<T>((size_t)std::max(1, ch.nslots()) * K);
     }
     m.x = h->dalloc<T>(n * K);
     m.q = h->dalloc<T>(n * K);
@@ -921,14 +936,42 @@ void upload_block_engine(lap_hierarchy* h, EngineM<T>& m, const Engine<T>& e, hi
             d.l2 = c.l2;
             d.ea = h->dalloc<T>((size_t)d.nc * K);
             d.eb = h->dalloc<T>((size_t)d.nc * K);
-            ChunkHost<int32_t> ch;
-            ch.build(P.step[k].cptr, kMmChunk);
-            m.up[k] = h->upload_chunks(ch, s);
-            m.down[k] = m.up[k];
-            m.scrU[k] = h->dalloc<T>((size_t)std::max(1, ch.nslots()) * 3 * K);
         }
     }
     if (h->with_msp) m.top_pinv = e.top_pinv;
+}
+
+// Work lists of the block SpMM (entries per item `chunk`) and of the
+// restriction / prolongation (children per item `seg`), with their scratch.
+// Returns false (nothing built) when the split rows' scratch would exceed
+// `max_scratch` bytes.
+template <class T>
+bool build_spmm_chunks(lap_hierarchy* h, EngineM<T>& m, int chunk, size_t max_scratch,
+                       hipStream_t s) {
+    ChunkHost<int64_t> ch;
+    ch.build(h->plan.solve_graph().ptr, chunk);
+    const size_t scr = (size_t)std::max(1, ch.nslots()) * kCols * sizeof(T);
+    if (scr > max_scratch) return false;
+    m.CA = h->upload_chunks(ch, s);
+    m.scrA = h->dalloc<T>(scr / sizeof(T));
+    m.chunk = chunk;
+    return true;
+}
+
+template <class T>
+void build_level_chunks(lap_hierarchy* h, EngineM<T>& m, int seg, hipStream_t s) {
+    const HostPlan& P = h->plan;
+    const int Tl = P.nlev() - 1;
+    const size_t K = kCols;
+    m.seg = seg;
+    if (!h->with_msp) return;
+    for (int k = 0; k < Tl; ++k) {
+        ChunkHost<int32_t> cu;
+        cu.build(P.step[k].cptr, seg);
+        m.up[k] = h->upload_chunks(cu, s);
+        m.down[k] = m.up[k];
+        m.scrU[k] = h->dalloc<T>((size_t)std::max(1, cu.nslots()) * 3 * K);
+    }
 }
 
 void upload_block(lap_hierarchy* h, hipStream_t s) {
@@ -937,8 +980,6 @@ void upload_block(lap_hierarchy* h, hipStream_t s) {
     if (h->has_fp32) upload_block_engine(h, h->m32, h->e32, s);
     upload_block_engine(h, h->m64, h->e64, s);
     h->A64m = h->m64.A;
-    h->CA64 = h->m64.CA;
-    h->scrA64 = h->m64.scrA;
     h->bhm = h->dalloc<double>(n * K);
     h->xm = h->dalloc<double>(n * K);
     h->rm = h->dalloc<double>(n * K);
@@ -1009,7 +1050,7 @@ void enqueue_mm_iteration(lap_hierarchy* h, EngineM<T>& m, hipStream_t s, int pa
     ScalM* S = h->Sm;
     hipLaunchKernelGGL(k_mm_pupd<T>, dim3(mm_grid(n)), dim3(kMmWaves * 64), 0, s, n,
                        (const T*)m.zn, (const T*)m.p[par], m.p[1 - par], (const ScalM*)S);
-    const int ga = mm_grid(m.CA.nitems);
+    const int ga = mm_grid(m.CA.nitems, m.grid);
     launch_timed(k_mm_spmm<T>, dim3(ga), dim3(kMmWaves * 64), 0, s, e0, e1, m.A, m.CA,
                  (const T*)m.p[1 - par], m.q, m.scrA, (const ScalM*)S, h->partm);
     int gc = 0;
@@ -1034,8 +1075,124 @@ void build_mm_graph(lap_hierarchy* h, EngineM<T>& m) {
     HIPCHK(hipGraphInstantiate(&m.exec, m.graph, nullptr, nullptr, 0));
 }
 
+// ------------------------------------------------------------ autotuner
+//
+// The block solve's work decomposition is picked per hierarchy and value
+// type by timing candidates on the device at set-up, on the hierarchy's own
+// matrix and levels:
+//   - SpMM: matrix entries per work item (rows with more are split into
+//     chunks whose partial rows a combine pass adds) x workgroups of the
+//     launch (each takes a contiguous range of items): the pair with the
+//     shortest SpMM (+ combine) time;
+//   - restriction / prolongation: children per work item, by the time of
+//     one block preconditioner application.
+// Environment: LAPGPU_MM_TUNE=0 keeps the defaults untimed;
+// LAPGPU_MM_CHUNK, LAPGPU_MM_GRID, LAPGPU_MM_SEG pin one size each.
+constexpr int kTuneChunks[] = {32, 64, 128, 256, 512};
+constexpr int kTuneGrids[] = {256, 512, 1024, 2048};
+constexpr int kTuneSegs[] = {32, 64, 128, 256};
+constexpr int kTuneReps = 3;
+constexpr size_t kTuneMaxScratch = size_t(512) << 20;  // split-row scratch of a candidate
+static_assert(2048 <= 3 * kMmMaxGrid, "the SpMM's partials fit the partial buffer");
+
+// Average time per call of `launch` over kTuneReps calls after one warm-up.
+template <class F>
+double tune_time_us(hipStream_t s, F&& launch) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    launch();
+    HIPCHK(hipEventRecord(a, s));
+    for (int i = 0; i < kTuneReps; ++i) launch();
+    HIPCHK(hipEventRecord(b, s));
+    HIPCHK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    HIPCHK(hipGetLastError());
+    return 1e3 * ms / kTuneReps;
+}
+
+template <class T>
+void tune_block(lap_hierarchy* h, EngineM<T>& m, hipStream_t s) {
+    const int n = (int)h->n;
+    const size_t K = kCols;
+    const bool tune = env_int("LAPGPU_MM_TUNE", 1) != 0;
+    const int pin_c = env_int("LAPGPU_MM_CHUNK", 0), pin_g = env_int("LAPGPU_MM_GRID", 0),
+              pin_s = env_int("LAPGPU_MM_SEG", 0);
+    std::vector<int> cs, gs, ss;
+    auto pick = [&](std::vector<int>& out, int pin, int dflt, const int* cand, int nc) {
+        if (pin > 0) out = {pin};
+        else if (!tune) out = {dflt};
+        else out.assign(cand, cand + nc);
+    };
+    pick(cs, pin_c, kMmChunk, kTuneChunks, (int)std::size(kTuneChunks));
+    pick(gs, pin_g, kMmMaxGrid, kTuneGrids, (int)std::size(kTuneGrids));
+    pick(ss, pin_s, kMmChunk, kTuneSegs, (int)std::size(kTuneSegs));
+    for (int g : gs)
+        if (g < 1 || g > 2048) throw std::invalid_argument("LAPGPU_MM_GRID outside 1..2048");
+    int bc = cs[0], bg = gs[0], bs = ss[0];
+    if (cs.size() * gs.size() > 1 || ss.size() > 1) {
+        // timed on zero vectors with every column running
+        HIPCHK(hipMemsetAsync(h->Sm, 0, sizeof(ScalM), s));
+        HIPCHK(hipMemsetAsync(m.p[0], 0, (size_t)n * K * sizeof(T), s));
+        HIPCHK(hipMemsetAsync(m.lv[0].r, 0, (size_t)n * K * sizeof(T), s));
+        double best = 1e300;
+        for (int c : cs) {
+            const size_t mk = h->mark();
+            if (!build_spmm_chunks(h, m, c, kTuneMaxScratch, s)) continue;
+            for (int g : gs) {
+                const double t = tune_time_us(s, [&]() {
+                    hipLaunchKernelGGL(k_mm_spmm<T>, dim3(mm_grid(m.CA.nitems, g)),
+                                       dim3(kMmWaves * 64), 0, s, m.A, m.CA, (const T*)m.p[0],
+                                       m.q, m.scrA, (const ScalM*)h->Sm, h->partm);
+                    if (m.CA.nmulti > 0)
+                        hipLaunchKernelGGL(k_mm_spmm_combine<T>, dim3(mm_grid(m.CA.nmulti)),
+                                           dim3(kMmWaves * 64), 0, s, m.CA, (const T*)m.p[0],
+                                           m.q, (const T*)m.scrA, (const ScalM*)h->Sm,
+                                           h->partm2);
+                });
+                if (t < best) {
+                    best = t;
+                    bc = c;
+                    bg = g;
+                }
+            }
+            HIPCHK(hipStreamSynchronize(s));
+            h->release_to(mk);
+        }
+        best = 1e300;
+        for (int sg : ss) {
+            if (ss.size() == 1) break;
+            const size_t mk = h->mark();
+            build_level_chunks(h, m, sg, s);
+            const double t = tune_time_us(s, [&]() {
+                enqueue_mm_precond(h, m, s, 0, (const T*)m.p[0]);
+            });
+            if (t < best) {
+                best = t;
+                bs = sg;
+            }
+            HIPCHK(hipStreamSynchronize(s));
+            h->release_to(mk);
+        }
+    }
+    if (!build_spmm_chunks(h, m, bc, SIZE_MAX, s))
+        throw std::runtime_error("block SpMM chunk list");
+    build_level_chunks(h, m, bs, s);
+    m.grid = bg;
+}
+
 void setup_block(lap_hierarchy* h, hipStream_t s) {
     upload_block(h, s);
+    const auto t0 = std::chrono::steady_clock::now();
+    if (h->m32.on) tune_block(h, h->m32, s);
+    tune_block(h, h->m64, s);
+    h->mm_tune_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    h->CA64 = h->m64.CA;
+    h->scrA64 = h->m64.scrA;
     build_mm_graph(h, h->m64);
     if (h->m32.on) build_mm_graph(h, h->m32);
 }
@@ -1263,7 +1420,7 @@ ScalM run_mm_pcg(lap_hierarchy* h, EngineM<T>& m, const double* rhs, const bool*
 // r = bh - L x for the block (FP64), per-column ||r||^2 into So->res2.
 void block_residual(lap_hierarchy* h, const double* x, hipStream_t s) {
     const Chunks& C = h->CA64;
-    const int ga = mm_grid(C.nitems);
+    const int ga = mm_grid(C.nitems, h->m64.grid);
     hipLaunchKernelGGL(k_mm_resid, dim3(ga), dim3(kMmWaves * 64), 0, s, h->A64m, C, x,
                        (const double*)h->bhm, h->rm, h->scrA64, h->partm);
     int gc = 0;
@@ -2042,6 +2199,14 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
     } catch (const HipErr&) {
         delete h;
         return LAP_EDEVICE;
+    } catch (const std::invalid_argument& ex) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "%s", ex.what());
+        delete h;
+        return LAP_EINVAL;
+    } catch (const std::exception& ex) {
+        std::snprintf(g_last_error, sizeof(g_last_error), "%s", ex.what());
+        delete h;
+        return LAP_EDEVICE;
     }
     h->setup_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -2157,6 +2322,17 @@ lap_status lap_hierarchy_info(const lap_hierarchy* h, lap_hierarchy_desc* d) {
     d->nnz = h->plan.lv[0].g.nnz();
     d->device_bytes = h->dev_bytes;
     d->setup_seconds = h->setup_seconds;
+    if (h->has_block) {
+        d->mm_chunk[0] = h->m64.chunk;
+        d->mm_grid[0] = h->m64.grid;
+        d->mm_seg[0] = h->m64.seg;
+        if (h->m32.on) {
+            d->mm_chunk[1] = h->m32.chunk;
+            d->mm_grid[1] = h->m32.grid;
+            d->mm_seg[1] = h->m32.seg;
+        }
+        d->mm_tune_seconds = h->mm_tune_seconds;
+    }
     return LAP_OK;
 }
 

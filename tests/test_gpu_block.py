@@ -145,3 +145,72 @@ def test_block_nonfinite_column_rejected(oracle_lib):
         G.close()
     assert st == lap.LAP_EINVAL and info[3]["status"] == lap.LAP_EINVAL
     assert all(info[c]["status"] == 0 for c in range(8) if c != 3)
+
+
+def _hub_case():
+    n, u, v = W.hub_graph(20000, 6000, 3000, 7)
+    return n, u, v, W.uniform01_weights(len(u), 71)
+
+
+def test_block_autotuner_choice(oracle_lib):
+    """The set-up autotuner picks, for the FP64 block engine and the FP32
+    inner one, sizes among its candidates; a block solve with them meets the
+    residual bar (a hub graph: rows long enough to be split)."""
+    import paper_2207_07847_amd as lap
+    from oracle import Graph
+    n, u, v, w = _hub_case()
+    B = W.gaussian_rhs(n, 52, 64).reshape(64, n)
+    G = GpuLap(n, u, v, w, mu=0.8, precision=lap.LAP_MIXED_FP32_FP64, max_iter=20000,
+               flags=lap.LAP_FLAG_MULTI_RHS)
+    try:
+        d = G.info
+        st, X, info = G.solve_many(B, 1e-8)
+    finally:
+        G.close()
+    say("autotuner: chunk", d["mm_chunk"], "grid", d["mm_grid"], "seg", d["mm_seg"],
+        "seconds", d["mm_tune_seconds"])
+    for k in (0, 1):
+        assert d["mm_chunk"][k] in (32, 64, 128, 256, 512)
+        assert d["mm_grid"][k] in (256, 512, 1024, 2048)
+        assert d["mm_seg"][k] in (32, 64, 128, 256)
+    assert d["mm_tune_seconds"] > 0.0
+    rel = _host_relres(Graph(n, u, v, w), B, X)
+    assert st == 0 and rel.max() <= 1.01e-8
+
+
+@pytest.mark.parametrize("sizes", [(32, 256, 32), (512, 2048, 256)])
+def test_block_pinned_sizes(oracle_lib, monkeypatch, sizes):
+    """Sizes pinned through the environment are used as given (no tuning)
+    and the solve meets the bar with either extreme decomposition."""
+    import paper_2207_07847_amd as lap
+    from oracle import Graph
+    c, g, s = sizes
+    monkeypatch.setenv("LAPGPU_MM_CHUNK", str(c))
+    monkeypatch.setenv("LAPGPU_MM_GRID", str(g))
+    monkeypatch.setenv("LAPGPU_MM_SEG", str(s))
+    n, u, v, w = _hub_case()
+    B = W.pair_rhs(n, 64, 53)
+    G = GpuLap(n, u, v, w, mu=0.8, max_iter=20000, flags=lap.LAP_FLAG_MULTI_RHS)
+    try:
+        d = G.info
+        st, X, info = G.solve_many(B, 1e-8)
+    finally:
+        G.close()
+    say("pinned", sizes, "reported", d["mm_chunk"][0], d["mm_grid"][0], d["mm_seg"][0])
+    assert (d["mm_chunk"][0], d["mm_grid"][0], d["mm_seg"][0]) == (c, g, s)
+    assert d["mm_chunk"][1] == 0
+    rel = _host_relres(Graph(n, u, v, w), B, X)
+    assert st == 0 and rel.max() <= 1.01e-8
+
+
+def test_block_bad_pinned_grid(monkeypatch):
+    """A pinned workgroup count outside 1..2048 is rejected by lap_setup."""
+    import paper_2207_07847_amd as lap
+    from gpu_util import torch_cuda
+    torch = torch_cuda()
+    monkeypatch.setenv("LAPGPU_MM_GRID", "4096")
+    n, u, v, w = W.config_graph("grid2d_64")
+    p = lap.lap_default_params(flags=lap.LAP_FLAG_MULTI_RHS)
+    with pytest.raises(lap.LapError) as ei:
+        lap.lap_setup(n, u, v, w, p, torch.cuda.current_stream().cuda_stream)
+    assert ei.value.status == lap.LAP_EINVAL
