@@ -675,8 +675,8 @@ __global__ __launch_bounds__(kBlock) void k_down0(LevelDev<T> s0, const int32_t*
     block_partial<3>(v, part);
 }
 
-// Levels 0 and 1 together.  Block b owns the level-2 nodes [A0, A1) =
-// [bst[b], bst[b+1]) of a partition aligned to level-1 aggregates: their
+// Levels 0 and 1 together.  Block b owns the level-2 nodes [A0, A1) of a
+// partition aligned to level-1 aggregates (Blk01): their
 // level-1 children [J0, J1) and level-0 grandchildren [t0, t1) are
 // contiguous and staged in LDS, so one launch does the update, the level-0
 // restriction and the level-1 restriction (and the down kernel both
@@ -684,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_down0(LevelDev<T> s0, const int32_t*
 // kCapP level-0 positions).
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_update_up01(LevelDev<T> s0, LevelDev<T> s1,
-                                                        const int32_t* __restrict__ bst,
+                                                        const Blk01* __restrict__ blk,
                                                         const int32_t* __restrict__ perm,
                                                         T* __restrict__ x, T* __restrict__ r,
                                                         const T* __restrict__ p,
@@ -696,11 +696,9 @@ __global__ __launch_bounds__(kBlock) void k_update_up01(LevelDev<T> s0, LevelDev
     __shared__ int nbig, big[kAggPerBlock];
     const int done = S->done;
     const T alpha = (T)S->alpha;
-    const int b = xcd_block();
-    const int A0 = bst[b], A1 = bst[b + 1];
+    const Blk01 bd = blk[xcd_block()];
     if (done) return;
-    const int J0 = s1.cptr[A0], J1 = s1.cptr[A1];
-    const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
+    const int A0 = bd.A0, A1 = bd.A1, J0 = bd.J0, J1 = bd.J1, t0 = bd.t0, len = bd.t1 - bd.t0;
     double rr = 0.0;
     if (threadIdx.x == 0) nbig = 0;
     for (int i = threadIdx.x; i < len; i += kBlock) {
@@ -738,46 +736,60 @@ __global__ __launch_bounds__(kBlock) void k_update_up01(LevelDev<T> s0, LevelDev
 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_down01(LevelDev<T> s0, LevelDev<T> s1,
-                                                   const int32_t* __restrict__ bst,
+                                                   const Blk01* __restrict__ blk,
                                                    const int32_t* __restrict__ perm,
                                                    const T* __restrict__ r, T* __restrict__ zn,
                                                    const T* __restrict__ y2, Scal* S,
                                                    double* part) {
+    static_assert(kAggPerBlock <= kBlock && kCapP % kBlock == 0, "one level-1 node per thread");
+    constexpr int R = kCapP / kBlock;
     __shared__ DownBlock<T> D;
     __shared__ T y1s[kAggPerBlock];
     const int done = S->done;
-    const int b = xcd_block();
-    const int A0 = bst[b], A1 = bst[b + 1];
+    const Blk01 bd = blk[xcd_block()];
     if (done) return;
-    const int J0 = s1.cptr[A0], J1 = s1.cptr[A1];
-    const int t0 = s0.cptr[J0], len = s0.cptr[J1] - t0;
+    const int A0 = bd.A0, A1 = bd.A1, J0 = bd.J0, J1 = bd.J1, t0 = bd.t0, len = bd.t1 - bd.t0;
+    const int tid = threadIdx.x;
+    // The loads of each level-1 node's children range and pair corrections
+    // do not depend on the level-2 -> 1 step: issued first, they overlap it.
+    const bool has1 = tid < J1 - J0;
+    int c0 = 0, c1 = 0;
+    T ea0 = T(0), eb0 = T(0);
+    if (has1) {
+        c0 = s0.cptr[J0 + tid];
+        c1 = s0.cptr[J0 + tid + 1];
+        ea0 = s0.ea[J0 + tid];
+        eb0 = s0.eb[J0 + tid];
+    }
     // level 2 -> 1 into LDS
-    for (int A = A0 + threadIdx.x; A < A1; A += kBlock) {
-        const int c0 = s1.cptr[A], c1 = s1.cptr[A + 1];
+    for (int A = A0 + tid; A < A1; A += kBlock) {
+        const int a0 = s1.cptr[A], a1 = s1.cptr[A + 1];
         const T yA = y2[A], ea = s1.ea[A], eb = s1.eb[A];
-        for (int J = c0; J < c1; ++J) y1s[J - J0] = child_down(s1, A, c0, J, s1.r[J], yA, ea, eb);
+        for (int J = a0; J < a1; ++J) y1s[J - J0] = child_down(s1, A, a0, J, s1.r[J], yA, ea, eb);
     }
     __syncthreads();
     // level 1 -> 0, z with its reductions
-    for (int j = threadIdx.x; j < J1 - J0; j += kBlock) {
-        const int J = J0 + j;
-        const int c0 = s0.cptr[J], c1 = s0.cptr[J + 1];
-        D.b0[j] = c0;
-        D.yJ[j] = y1s[j];
-        D.ea[j] = s0.ea[J];
-        D.eb[j] = s0.eb[J];
-        for (int t = c0; t < c1; ++t) D.own[t - t0] = j;
+    if (has1) {
+        D.b0[tid] = c0;
+        D.yJ[tid] = y1s[tid];
+        D.ea[tid] = ea0;
+        D.eb[tid] = eb0;
+        for (int t = c0; t < c1; ++t) D.own[t - t0] = tid;
     }
     __syncthreads();
     double v[3] = {0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < len; i += kBlock) {
-        const int t = t0 + i, j = D.own[i];
-        const T rt = r[t];
-        const T zt = child_down(s0, J0 + j, D.b0[j], t, rt, D.yJ[j], D.ea[j], D.eb[j]);
-        zn[perm ? perm[t] : t] = zt;
-        v[0] += zt;
-        v[1] += (double)rt * zt;
-        v[2] += rt;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int i = tid + u * kBlock;
+        if (i < len) {
+            const int t = t0 + i, j = D.own[i];
+            const T rt = r[t];
+            const T zt = child_down(s0, J0 + j, D.b0[j], t, rt, D.yJ[j], D.ea[j], D.eb[j]);
+            zn[perm ? perm[t] : t] = zt;
+            v[0] += zt;
+            v[1] += (double)rt * zt;
+            v[2] += rt;
+        }
     }
     block_partial<3>(v, part);
 }

@@ -91,6 +91,13 @@ struct TailDesc {
     TailStep st[kMaxTailSteps];
 };
 
+// Block b of the fused level-0/1 kernels: its level-2 nodes [A0, A1), their
+// level-1 children [J0, J1) and level-0 grandchildren [t0, t1), computed on
+// the host so a block reads all three ranges with one load.
+struct Blk01 {
+    int32_t A0, A1, J0, J1, t0, t1, pad0, pad1;
+};
+
 // The descriptor fields the tail needs before anything else, passed by
 // value so its first loads do not wait for them.
 struct TailArgs {

@@ -309,7 +309,7 @@ struct Engine {
     };
     std::vector<Segment> segs;   // levels [1, kt) ([2, kt) when fuse01), in order
     bool fuse01 = false;         // levels 0 and 1 in the same kernels
-    const int32_t* bst01 = nullptr;
+    Blk01* blk01 = nullptr;      // fused level-0/1 block ranges
     int nb01 = 0;
     // workspace: input order
     T *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *zn = nullptr;
@@ -449,6 +449,7 @@ struct lap_hierarchy {
     int chunk = 8;
     double mm_tune_seconds = 0.0;  // block-solve autotuner time in lap_setup
     double inner_tol = 1e-4;
+    double reliable_drop = kReliableDrop;
     bool reliable = true;        // mixed precision by reliable updates (else restarts)
 
     template <class T>
@@ -577,7 +578,8 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
     if (e.fuse01)
         launch_timed(k_update_up01<T>, dim3(g0), dim3(kBlock), 0, s,
                      mk.kernel == LAP_KERNEL_PRECOND ? mk.e0 : mk.start(LAP_KERNEL_UPDATE),
-                     mk.stop(LAP_KERNEL_UPDATE), s0, e.lv[1], e.bst01, h->t2s, e.x, e.r, pcur,
+                     mk.stop(LAP_KERNEL_UPDATE), s0, e.lv[1], (const Blk01*)e.blk01, h->t2s,
+                     e.x, e.r, pcur,
                      (const T*)e.q, e.lv[2].r, S, h->part2, do_update);
     else
         launch_timed(k_update_up0<T>, dim3(g0), dim3(kBlock), 0, s,
@@ -609,7 +611,8 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
     if (e.fuse01)
         launch_timed(k_down01<T>, dim3(g0), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_DOWN0),
                      mk.kernel == LAP_KERNEL_PRECOND ? mk.e1 : mk.stop(LAP_KERNEL_DOWN0), s0,
-                     e.lv[1], e.bst01, h->t2s, (const T*)e.r, e.zn, (const T*)e.lv[2].y, S,
+                     e.lv[1], (const Blk01*)e.blk01, h->t2s, (const T*)e.r, e.zn,
+                     (const T*)e.lv[2].y, S,
                      h->part);
     else
         launch_timed(k_down0<T>, dim3(g0), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_DOWN0),
@@ -756,7 +759,18 @@ void upload_engine(lap_hierarchy* h, Engine<T>& e, hipStream_t s, bool with_leve
         if (!b01.empty()) {
             e.fuse01 = true;
             e.nb01 = (int)b01.size() - 1;
-            e.bst01 = h->upload(b01, s);
+            std::vector<Blk01> d01(e.nb01);
+            for (int b = 0; b < e.nb01; ++b) {
+                Blk01& d = d01[b];
+                d.A0 = b01[b];
+                d.A1 = b01[b + 1];
+                d.J0 = P.step[1].cptr[d.A0];
+                d.J1 = P.step[1].cptr[d.A1];
+                d.t0 = P.step[0].cptr[d.J0];
+                d.t1 = P.step[0].cptr[d.J1];
+                d.pad0 = d.pad1 = 0;
+            }
+            e.blk01 = h->upload(d01, s);
         }
     }
     // middle levels [1, kt) (from 2 when levels 0 and 1 are fused): groups
@@ -887,6 +901,7 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     HIPCHK(hipGetLastError());
     h->chunk = std::max(2, env_int("LAPGPU_CHUNK", 8) & ~1);
     h->inner_tol = env_double("LAPGPU_INNER_TOL", 1e-4);
+    h->reliable_drop = env_double("LAPGPU_RELIABLE_DROP", kReliableDrop);
     h->reliable = env_int("LAPGPU_MIXED_RESTART", 0) == 0;
     build_graph(h, h->e64);
     if (h->mixed) build_graph(h, h->e32);
@@ -1579,7 +1594,7 @@ lap_status solve_mixed_reliable(lap_hierarchy* h, const double* b, double* x, do
     while (true) {
         HIPCHK(hipGraphLaunch(f.exec, s));
         Scal S = read_scal(h, h->S, s);
-        const bool replace = S.done == 1 || (S.done == 0 && S.rr <= kReliableDrop * rr_last);
+        const bool replace = S.done == 1 || (S.done == 0 && S.rr <= h->reliable_drop * rr_last);
         if (S.done != 0 && S.done != 1) {
             st = to_status(S.done);
             break;
