@@ -152,8 +152,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finish(int G, int n,
         const double pq = v[0];
         S->pq = pq;
         S->iter = iter + 1;
-        if (!(pq > 0.0) || !isfinite(pq)) S->done = 3;
-        else S->alpha = rho0 / pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            S->done = 3;
+            S->alpha = 0.0;  // the step is not taken (x gets no alpha p)
+        } else {
+            S->alpha = rho0 / pq;
+        }
     } else if (OP == kFinRr) {
         S->rr = v[0];
         if (!isfinite(v[0])) S->done = 3;
@@ -303,11 +307,11 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* __restrict__ zn,
                                                    const T* __restrict__ pold,
                                                    T* __restrict__ pnew, T* __restrict__ q,
-                                                   Scal* S, double* part) {
+                                                   T* __restrict__ x, Scal* S, double* part) {
     // the stop flag is loaded with the scalars the kernel needs (one
     // memory latency before the first data loads, not two)
     const int done = S->done;
-    const T beta = (T)S->beta, zbar = (T)S->zbar;
+    const T beta = (T)S->beta, zbar = (T)S->zbar, alpha = (T)S->alpha;
     if (done) return;
     const int lb = spmv_block(A.nheavyblk);
     double v[1] = {0.0};
@@ -322,6 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* 
             });
             pnew[row] = pi;
             q[row] = acc;
+            x[row] += alpha * poi;
             v[0] = (double)pi * (double)acc;
         }
     } else {
@@ -332,25 +337,50 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* 
                 return [=](int j) { return (zi - zn[j]) + beta * (poi - pold[j]); };
             },
             [&](int row, T acc) {
-                const T pi = (zn[row] - zbar) + beta * pold[row];
+                const T po = pold[row];
+                const T pi = (zn[row] - zbar) + beta * po;
                 pnew[row] = pi;
                 q[row] = acc;
+                x[row] += alpha * po;
                 v[0] = (double)pi * (double)acc;
             });
     }
     block_partial<1>(v, part);
 }
 
-// p = zn - zbar + beta p_old (solve order), for the SpMV below.
+// p = zn - zbar + beta p_old (solve order), for the SpMV below, and the
+// previous step x += alpha p_old.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_pupd(int n, const T* __restrict__ zn,
                                                  const T* __restrict__ pold, T* __restrict__ pnew,
-                                                 const Scal* S) {
+                                                 T* __restrict__ x, const Scal* S) {
     const int done = S->done;
-    const T beta = (T)S->beta, zbar = (T)S->zbar;
+    const T beta = (T)S->beta, zbar = (T)S->zbar, alpha = (T)S->alpha;
     if (done) return;
     const int t = xcd_block() * kBlock + threadIdx.x;
-    if (t < n) pnew[t] = (zn[t] - zbar) + beta * pold[t];
+    if (t < n) {
+        const T po = pold[t];
+        pnew[t] = (zn[t] - zbar) + beta * po;
+        x[t] += alpha * po;
+    }
+}
+
+// The step of the last iteration of a run, x += alpha p_last: each product
+// adds the previous iteration's step (it reads that p anyway), so a run that
+// stops still owes its last one.  With pcopy, p_last is also copied there
+// (a run that continues from a chunk boundary reads its p_old from p[0]).
+// Runs after the stop flag is set, so it does not test it.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_last_step(int n, T* __restrict__ x,
+                                                      const T* __restrict__ plast,
+                                                      T* __restrict__ pcopy, const Scal* S) {
+    const T alpha = (T)S->alpha;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) {
+        const T p = plast[t];
+        x[t] += alpha * p;
+        if (pcopy) pcopy[t] = p;
+    }
 }
 
 // q = L p with p already formed (one gathered vector per neighbour instead
@@ -572,17 +602,16 @@ __device__ inline bool down_stage(const LevelDev<T>& s, const T* __restrict__ yk
     return true;
 }
 
-// x += alpha p (input order); r -= alpha q (tree order, q read through the
-// permutation); partial ||r||^2; restriction of r to level 1 fused with the
-// local solves of the level-0 aggregates.  The children ranges of all
-// aggregates partition [0, n), so the same ranges index x and p.  The
-// element-wise part runs over the block's children with coalesced accesses
-// and leaves the new residuals in LDS for the per-aggregate part.
+// r -= alpha q (tree order, q read through the permutation); partial
+// ||r||^2; restriction of r to level 1 fused with the local solves of the
+// level-0 aggregates.  (x += alpha p is taken by the next product, which
+// reads p anyway.)  The element-wise part runs over the block's children
+// with coalesced accesses and leaves the new residuals in LDS for the
+// per-aggregate part.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev<T> s0,
                                                        const int32_t* __restrict__ perm,
-                                                       T* __restrict__ x, T* __restrict__ r,
-                                                       const T* __restrict__ p,
+                                                       T* __restrict__ r,
                                                        const T* __restrict__ q,
                                                        T* __restrict__ r1, Scal* S, double* part,
                                                        int do_update) {
@@ -602,7 +631,6 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev<T> s0,
             const int t = t0 + i;
             T rt = r[t];
             if (do_update) {
-                x[t] += alpha * p[t];
                 rt -= alpha * q[perm ? perm[t] : t];
                 r[t] = rt;
                 rr += (double)rt * rt;
@@ -622,7 +650,6 @@ __global__ __launch_bounds__(kBlock) void k_update_up0(LevelDev<T> s0,
         const int t = t0 + i;
         T rt = r[t];
         if (do_update) {
-            x[t] += alpha * p[t];
             rt -= alpha * q[perm ? perm[t] : t];
             r[t] = rt;
             v[3] += (double)rt * rt;
@@ -686,8 +713,7 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_update_up01(LevelDev<T> s0, LevelDev<T> s1,
                                                         const Blk01* __restrict__ blk,
                                                         const int32_t* __restrict__ perm,
-                                                        T* __restrict__ x, T* __restrict__ r,
-                                                        const T* __restrict__ p,
+                                                        T* __restrict__ r,
                                                         const T* __restrict__ q,
                                                         T* __restrict__ r2, Scal* S, double* part,
                                                         int do_update) {
@@ -705,7 +731,6 @@ __global__ __launch_bounds__(kBlock) void k_update_up01(LevelDev<T> s0, LevelDev
         const int t = t0 + i;
         T rt = r[t];
         if (do_update) {
-            x[t] += alpha * p[t];
             rt -= alpha * q[perm ? perm[t] : t];
             r[t] = rt;
             rr += (double)rt * rt;
@@ -794,11 +819,10 @@ __global__ __launch_bounds__(kBlock) void k_down01(LevelDev<T> s0, LevelDev<T> s
     block_partial<3>(v, part);
 }
 
-// Without a hierarchy below the fine level: x and r update only.
+// Without a hierarchy below the fine level: the r update only.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_update_none(int n, const int32_t* __restrict__ perm,
-                                                        T* __restrict__ x, T* __restrict__ r,
-                                                        const T* __restrict__ p,
+                                                        T* __restrict__ r,
                                                         const T* __restrict__ q, Scal* S,
                                                         double* part) {
     if (S->done) return;
@@ -806,7 +830,6 @@ __global__ __launch_bounds__(kBlock) void k_update_none(int n, const int32_t* __
     const int t = xcd_block() * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (t < n) {
-        x[t] += alpha * p[t];
         const T rt = r[t] - alpha * q[perm ? perm[t] : t];
         r[t] = rt;
         v[0] = (double)rt * rt;

@@ -540,7 +540,7 @@ void launch_timed(F kern, dim3 grid, dim3 block, uint32_t lds, hipStream_t s, hi
 // The preconditioner: level-0 restriction (with the x, r update when
 // do_update), the middle levels, the tail and back, z with its reductions.
 template <class T>
-void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_update, const T* pcur,
+void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_update,
                      const Marks& mk = Marks{}) {
     const int Tl = h->plan.nlev() - 1;
     const int n = (int)h->n;
@@ -549,7 +549,7 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
         if (h->pegp) {
             if (do_update) {
                 hipLaunchKernelGGL(k_update_none<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n,
-                                   h->t2s, e.x, e.r, pcur, (const T*)e.q, S, h->part2);
+                                   h->t2s, e.r, (const T*)e.q, S, h->part2);
                 finish<kFinRr>(h, s, S, nblk(n), 0, h->part2);
             }
             hipLaunchKernelGGL(k_pegp, dim3(1), dim3(kPegpThreads), h->pegp_lds, s, h->pegp_dev,
@@ -560,7 +560,7 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
     if (!h->with_msp || Tl == 0) {
         if (do_update) {
             hipLaunchKernelGGL(k_update_none<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s,
-                               e.x, e.r, pcur, (const T*)e.q, S, h->part2);
+                               e.r, (const T*)e.q, S, h->part2);
             if (h->with_msp) finish<kFinRr>(h, s, S, nblk(n), 0, h->part2);
         }
         if (!h->with_msp) {
@@ -579,13 +579,11 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
         launch_timed(k_update_up01<T>, dim3(g0), dim3(kBlock), 0, s,
                      mk.kernel == LAP_KERNEL_PRECOND ? mk.e0 : mk.start(LAP_KERNEL_UPDATE),
                      mk.stop(LAP_KERNEL_UPDATE), s0, e.lv[1], (const Blk01*)e.blk01, h->t2s,
-                     e.x, e.r, pcur,
-                     (const T*)e.q, e.lv[2].r, S, h->part2, do_update);
+                     e.r, (const T*)e.q, e.lv[2].r, S, h->part2, do_update);
     else
         launch_timed(k_update_up0<T>, dim3(g0), dim3(kBlock), 0, s,
                      mk.kernel == LAP_KERNEL_PRECOND ? mk.e0 : mk.start(LAP_KERNEL_UPDATE),
-                     mk.stop(LAP_KERNEL_UPDATE), s0, h->t2s, e.x, e.r, pcur,
-                     (const T*)e.q, e.lv[1].r, S, h->part2, do_update);
+                     mk.stop(LAP_KERNEL_UPDATE), s0, h->t2s, e.r, (const T*)e.q, e.lv[1].r, S, h->part2, do_update);
     for (const auto& G : e.segs) {
         if (G.group)
             hipLaunchKernelGGL(k_up_grp<T>, dim3(G.gd.nblocks), dim3(kGrpThreads), G.lds_up, s,
@@ -628,18 +626,19 @@ void enqueue_iteration(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int par,
     if (h->fuse_p) {
         launch_timed(k_spmv_p<T>, dim3(e.spmv_grid()), dim3(kBlock), 0, s,
                      mk.start(LAP_KERNEL_SPMV), mk.stop(LAP_KERNEL_SPMV), e.nlb, e.A,
-                     (const T*)e.zn, (const T*)e.p[par], e.p[1 - par], e.q, h->S, h->part);
+                     (const T*)e.zn, (const T*)e.p[par], e.p[1 - par], e.q, e.x, h->S,
+                     h->part);
     } else {
         const int n = (int)h->n;
         launch_timed(k_pupd<T>, dim3(nblk(n)), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_SPMV),
                      (hipEvent_t) nullptr, n, (const T*)e.zn, (const T*)e.p[par], e.p[1 - par],
-                     (const Scal*)h->S);
+                     e.x, (const Scal*)h->S);
         launch_timed(k_spmv_q<T>, dim3(e.spmv_grid()), dim3(kBlock), 0, s, (hipEvent_t) nullptr,
                      mk.stop(LAP_KERNEL_SPMV), e.nlb, e.A, (const T*)e.p[1 - par], e.q, h->S,
                      h->part);
     }
     finish<kFinPq>(h, s, h->S, e.spmv_grid());
-    enqueue_precond(h, e, s, 1, e.p[1 - par], mk);
+    enqueue_precond(h, e, s, 1, mk);
 }
 
 template <class T>
@@ -1244,7 +1243,7 @@ Scal run_pcg(lap_hierarchy* h, Engine<T>& e, const double* rhs, double tol, int 
     hipLaunchKernelGGL(k_init<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s, rhs, e.r, e.x,
                        e.p[0], e.p[1], (const Scal*)h->S, h->part);
     finish<kFinBn2>(h, s, h->S, nblk(n));
-    enqueue_precond(h, e, s, 0, (const T*)e.p[0]);
+    enqueue_precond(h, e, s, 0);
     HIPCHK(hipGetLastError());
     // chunks of iterations; one chunk in flight beyond the one being checked
     hipEvent_t ev;
@@ -1264,7 +1263,13 @@ Scal run_pcg(lap_hierarchy* h, Engine<T>& e, const double* rhs, double tol, int 
         throw;
     }
     (void)hipEventDestroy(ev);
-    return read_scal(h, h->S, s);
+    const Scal R = read_scal(h, h->S, s);
+    // the last iteration's step (iteration k wrote its p to p[k & 1])
+    if (R.iter > 0)
+        hipLaunchKernelGGL(k_last_step<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, e.x,
+                           (const T*)e.p[R.iter & 1], (T*)nullptr, (const Scal*)h->S);
+    HIPCHK(hipGetLastError());
+    return R;
 }
 
 // Mean-free x (solve order) into the caller's buffer (input order) and the
@@ -1586,7 +1591,7 @@ lap_status solve_mixed_reliable(lap_hierarchy* h, const double* b, double* x, do
                        (const double*)h->r64, f.r, f.x, f.p[0], f.p[1], (const Scal*)h->S,
                        h->part);
     finish<kFinBn2>(h, s, h->S, nblk(n));
-    enqueue_precond(h, f, s, 0, (const float*)f.p[0]);
+    enqueue_precond(h, f, s, 0);
     HIPCHK(hipGetLastError());
     double res2 = bn2, rr_last = bn2;
     int refs = 0;
@@ -1600,7 +1605,12 @@ lap_status solve_mixed_reliable(lap_hierarchy* h, const double* b, double* x, do
             break;
         }
         if (!replace) continue;
-        // reliable update
+        // reliable update: the run's last step into its x first (and its p
+        // into p[0], where the next chunk reads p_old)
+        if (S.iter > 0)
+            hipLaunchKernelGGL(k_last_step<float>, dim3(nblk(n)), dim3(kBlock), 0, s, n, f.x,
+                               (const float*)f.p[S.iter & 1], (S.iter & 1) ? f.p[0] : nullptr,
+                               (const Scal*)h->S);
         hipLaunchKernelGGL(k_move_corr, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->x64, f.x);
         hipLaunchKernelGGL(k_resid, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A,
                            (const double*)h->x64, (const double*)h->bh, h->r64, h->part);
@@ -1627,8 +1637,9 @@ lap_status solve_mixed_reliable(lap_hierarchy* h, const double* b, double* x, do
         st2.done = 0;
         st2.first = S.beta > 0.0 ? 0 : 1;
         st2.rho = S.beta > 0.0 ? S.rho / S.beta : S.rho;
+        st2.alpha = 0.0;  // the last step is in x already
         HIPCHK(hipMemcpyAsync(h->S, &st2, sizeof(Scal), hipMemcpyHostToDevice, s));
-        enqueue_precond(h, f, s, 0, (const float*)f.p[0]);
+        enqueue_precond(h, f, s, 0);
         HIPCHK(hipGetLastError());
         rr_last = res2;
     }
@@ -1668,7 +1679,7 @@ void apply_precond(lap_hierarchy* h, Engine<T>& e, const double* r, double* z, h
     HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_gather<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n,
                        (const int32_t*)h->perm0, r, e.r);
-    enqueue_precond(h, e, s, 0, (const T*)e.p[0]);
+    enqueue_precond(h, e, s, 0);
     hipLaunchKernelGGL(k_shift_out<T>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm,
                        (const T*)e.zn, z, (const Scal*)h->S);
     HIPCHK(hipGetLastError());
@@ -1695,13 +1706,15 @@ double part_bytes(const lap_hierarchy* h, int kernel, double vb, bool levels, bo
         const double nc = lvn(k + 1), nl = lvn(k) - 2.0 * lvn(k + 1);
         return 4.0 * nc + 2.0 * vb * nc + vb * nc + 3.0 * vb * nl + vb * nl + vb * lvn(k);
     };
-    // SpMV: z, p_old read, p, q written; col and w per stored entry (with
-    // a separate p pass, p is read back once more by the SpMV)
-    const double spmv = (h->fuse_p ? 4.0 : 5.0) * vb * n + (4.0 + vb) * nnz;
+    // SpMV: z, p_old, x read, p, q, x written (the previous step x +=
+    // alpha p_old rides along); col and w per stored entry (with a separate
+    // p pass, p is read back once more by the SpMV)
+    const double spmv = (h->fuse_p ? 6.0 : 7.0) * vb * n + (4.0 + vb) * nnz;
     // fused levels 0 and 1: the update kernel also restricts level 1 (its r1
     // stays in LDS but is written once for the down-sweep), down0 also
     // prolongs level 1 (y1 stays in LDS)
-    double upd = levels ? 6.0 * vb * n + step_up(0) - vb * n : 6.0 * vb * n;
+    // update: q, r read, r written
+    double upd = levels ? 3.0 * vb * n + step_up(0) - vb * n : 3.0 * vb * n;
     double down0 = levels ? step_down(0) - vb * (lvn(0) - 2.0 * lvn(1)) + vb * n : 3.0 * vb * n;
     if (levels && fused01) {
         upd += step_up(1) - vb * lvn(1);
@@ -1714,7 +1727,7 @@ double part_bytes(const lap_hierarchy* h, int kernel, double vb, bool levels, bo
         case LAP_KERNEL_UPDATE: return upd;
         case LAP_KERNEL_DOWN0: return down0;
         case LAP_KERNEL_PRECOND: return upd + mid + down0;
-        default: return spmv + (levels ? upd + mid + down0 : 12.0 * vb * n);
+        default: return spmv + upd + mid + down0;
     }
 }
 
@@ -1753,7 +1766,7 @@ lap_status profile(lap_hierarchy* h, Engine<T>& e, int32_t kernel, int32_t reps,
                                (const double*)h->xc, e.r, e.x, e.p[0], e.p[1], (const Scal*)h->S,
                                h->part);
             finish<kFinBn2>(h, s, h->S, nblk(n));
-            enqueue_precond(h, e, s, 0, (const T*)e.p[0]);
+            enqueue_precond(h, e, s, 0);
             const int i1 = std::min(reps, i0 + kProfGroup);
             if (whole) HIPCHK(hipEventRecord(ev[2 * (i0 / kProfGroup)], s));
             for (int i = i0; i < i1; ++i) {
