@@ -93,6 +93,8 @@ def lib():
     L.lr_msp_fill.argtypes = [vp]
     L.lr_msp_fill.restype = C.c_int64
     L.lr_msp_apply.argtypes = [vp, _f64p, _f64p]
+    L.lr_msp_solve_expanded.argtypes = [vp, _f64p, _f64p]
+    L.lr_msp_solve_expanded.restype = None
     L.lr_pcg.argtypes = [vp, vp, vp, _f64p, C.c_double, C.c_int32, _f64p,
                          C.POINTER(_PcgInfo), vp]
     L.lr_pcg.restype = C.c_int
@@ -253,6 +255,12 @@ class MSP:
         z = np.empty(self.n)
         lib().lr_msp_apply(self._f, np.ascontiguousarray(r, dtype=np.float64), z)
         return z
+
+    def solve_expanded(self, bt):
+        """Grounded solve of L_T~ y~ = b~ in the expanded space (Sec. 3.3)."""
+        y = np.empty(self.h.ntilde)
+        lib().lr_msp_solve_expanded(self._f, np.ascontiguousarray(bt, dtype=np.float64), y)
+        return y
 
 
 def iteration_band(g: Graph, b, tol, maxit, precond, seeds=8, noise=4e-16):

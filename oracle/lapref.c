@@ -642,6 +642,32 @@ int64_t lr_msp_fill(const lr_msp *f) { return f->fill; }
 
 /* z = P(mu) y with L_T~ y = P(mu)^T r (grounded solution; any other solution
  * differs by a constant, which P(mu) maps to a constant), mean removed. */
+/* y~ = the grounded solve of L_T~ y~ = b~ in the expanded space (Sec. 3.3):
+ * elimination with the factor of lr_msp_factor, y~ = 0 on the ground node.
+ * This is the preconditioner of the expanded system (Sec. 4); b~ and y~
+ * hold ntilde values. */
+void lr_msp_solve_expanded(const lr_msp *f, const double *bt, double *y)
+{
+    int64_t nt = f->nt;
+    double *b = (double *)malloc(sizeof(double) * (size_t)nt);
+    memcpy(b, bt, sizeof(double) * (size_t)nt);
+    for (int64_t pos = 0; pos < f->neli; ++pos) {
+        int64_t p = f->order[pos];
+        double bp = b[p] / f->piv[pos];
+        for (int64_t q = f->cptr[pos]; q < f->cptr[pos + 1]; ++q)
+            b[f->cidx[q]] -= f->cval[q] * bp;
+    }
+    y[f->ground] = 0.0;
+    for (int64_t pos = f->neli - 1; pos >= 0; --pos) {
+        int64_t p = f->order[pos];
+        double s = b[p];
+        for (int64_t q = f->cptr[pos]; q < f->cptr[pos + 1]; ++q)
+            s -= f->cval[q] * y[f->cidx[q]];
+        y[p] = s / f->piv[pos];
+    }
+    free(b);
+}
+
 void lr_msp_apply(void *ctx, const double *r, double *z)
 {
     const lr_msp *f = (const lr_msp *)ctx;

@@ -93,6 +93,8 @@ void lr_msp_free(lr_msp *f);
 int64_t lr_msp_fill(const lr_msp *f);   /* entries created by elimination */
 /* z = P(mu) L_T~^+ P(mu)^T r with the mean of z removed. */
 void lr_msp_apply(void *f, const double *r, double *z);
+/* grounded solve of L_T~ y~ = b~ in the expanded space (ntilde values) */
+void lr_msp_solve_expanded(const lr_msp *f, const double *bt, double *y);
 
 /* Preconditioned CG on L_G x = b (see lr_pcg for the exact steps). */
 typedef void (*lr_precond_fn)(void *ctx, const double *r, double *z);

@@ -76,6 +76,13 @@ class PEGP:
     def nnz_ht(self):
         return self.Ht.nnz
 
+    def solve_expanded(self, bt):
+        """Grounded solve of L_H~ y~ = b~ in the expanded space: the scaled
+        system D L_H~ D (D y~') = D b~ with the last node grounded."""
+        y = np.zeros(self.nt)
+        y[:-1] = self._lu.solve((self.d * np.asarray(bt, dtype=np.float64))[:-1])
+        return y * self.d
+
     def apply(self, r):
         rt = self.Pmu.T @ np.asarray(r, dtype=np.float64)
         y = np.zeros(self.nt)
