@@ -34,6 +34,8 @@ def log(*a):
 
 
 WORKLOADS = {
+    "grid2d_64": "grid2d 64x64 5-point, unit weights, PEGP mu=1/64 level=max, 1 Gaussian RHS, "
+                 "tol 1e-8",
     "grid3d_128": "grid3d_128^3 7-point, w=10^U(-3,3), MSP mu=0.8 level=max, 1 Gaussian RHS, tol 1e-8",
     "chunglu_4m": "Chung-Lu 4M ids (LCC), mean degree 16, gamma 2.1, w=U(0,1], MSP mu=0.8 "
                   "level=max, 1 Gaussian RHS, tol 1e-8",
@@ -45,6 +47,8 @@ WORKLOADS = {
 def workload(name, scale, nrhs=1):
     """Graph, right-hand side(s) and solver settings.  nrhs > 1: columns
     e_i - e_j for seeded random pairs (shape (nrhs, n))."""
+    import numpy as np
+
     import workloads as W
     if name not in WORKLOADS:
         raise SystemExit(f"unknown workload {name}")
@@ -52,8 +56,11 @@ def workload(name, scale, nrhs=1):
     if nrhs > 1:
         b = W.pair_rhs(n, nrhs, W.MASTER_SEED + 6)
     else:
-        b = W.gaussian_rhs(n, W.MASTER_SEED + 3)
-    return dict(n=n, u=u, v=v, w=w, b=b, mu=0.8, tol=1e-8)
+        b = W.gaussian_rhs(n, W.MASTER_SEED + (1 if name == "grid2d_64" else 3))
+    if name == "grid2d_64":
+        # the paper's grid workload: PEGP with mu = 1/sqrt(n)
+        return dict(n=n, u=u, v=v, w=w, b=b, mu=1.0 / np.sqrt(n), tol=1e-8, precond="pegp")
+    return dict(n=n, u=u, v=v, w=w, b=b, mu=0.8, tol=1e-8, precond="msp")
 
 
 def pmc_traffic(workload_name, scale):
@@ -81,6 +88,35 @@ def pmc_traffic(workload_name, scale):
         elif line.startswith("kernel source sha256[:16]"):
             sha = line.split(":")[-1].strip()
     return traffic if sha == h.hexdigest()[:16] else None
+
+
+def cpu_baseline_fgmres(wl, budget_s):
+    """The oracle's FGMRES on the expanded system (PEGP), whole solves
+    repeated for about budget_s seconds."""
+    from oracle import Graph, Hierarchy
+    from oracle.fgmres import fgmres_expanded
+    from oracle.pegp import PEGP
+    t0 = time.time()
+    h = Hierarchy(Graph(wl["n"], wl["u"], wl["v"], wl["w"]))
+    M = PEGP(wl["n"], wl["u"], wl["v"], wl["w"], h.aggs(), wl["mu"])
+    setup_s = time.time() - t0
+    t0 = time.time()
+    k = 0
+    while True:
+        res = fgmres_expanded(wl["n"], wl["u"], wl["v"], wl["w"], h.aggs(), wl["mu"], wl["b"],
+                              M.solve_expanded, tol=wl["tol"])
+        k += 1
+        if time.time() - t0 >= budget_s or k >= 1000:
+            break
+    dt = time.time() - t0
+    return {
+        "value": k / dt,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{k} whole FGMRES solves ({res.iterations} steps each) in {dt:.1f} s, "
+                   f"setup {setup_s:.1f} s untimed"),
+    }
 
 
 def cpu_baseline(wl, gpu_iters, budget_s):
@@ -306,6 +342,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid3d_128", choices=sorted(WORKLOADS))
+    ap.add_argument("--solver", default="pcg", choices=["pcg", "fgmres"],
+                    help="pcg on the original system, or FGMRES on the expanded system "
+                         "(the paper's solver; FP64)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"],
                     help="both: mixed precision timed, plain FP64 timed beside it")
     ap.add_argument("--scale", type=float, default=1.0)
@@ -357,9 +396,12 @@ def main():
     prec = lap.LAP_FP64 if args.precision == "fp64" else lap.LAP_MIXED_FP32_FP64
     t0 = time.time()
     flags = lap.LAP_FLAG_MULTI_RHS if args.nrhs > 1 else 0
+    if args.solver == "fgmres":
+        flags |= lap.LAP_FLAG_FGMRES
+    pc = lap.LAP_PREC_PEGP if wl["precond"] == "pegp" else lap.LAP_PREC_MSP
     h = lap.lap_setup(n, wl["u"], wl["v"], wl["w"],
                       lap.lap_default_params(mu=wl["mu"], max_iter=args.max_iter,
-                                             precision=prec, flags=flags), sh)
+                                             precision=prec, flags=flags, precond=pc), sh)
     setup_s = time.time() - t0
     info = lap.lap_hierarchy_info(h)
     log(f"setup {setup_s:.2f}s levels={info['nlev']} tail={info['tail_level']} "
@@ -408,10 +450,13 @@ def main():
     # kernels timed inside iterations on the solve stream (the engine the
     # timed solves used: FP32 for mixed precision)
     kern = {}
-    for kid, name in [(lap.LAP_KERNEL_SPMV, "spmv_p"), (lap.LAP_KERNEL_UPDATE, "update_up0"),
-                      (lap.LAP_KERNEL_DOWN0, "down0"),
-                      (lap.LAP_KERNEL_PRECOND, "update_precond"),
-                      (lap.LAP_KERNEL_ITER, "iteration")]:
+    parts = [(lap.LAP_KERNEL_SPMV, "spmv_p"), (lap.LAP_KERNEL_UPDATE, "update_up0"),
+             (lap.LAP_KERNEL_DOWN0, "down0"), (lap.LAP_KERNEL_PRECOND, "update_precond"),
+             (lap.LAP_KERNEL_ITER, "iteration")]
+    if wl["precond"] == "pegp":
+        # the PEGP solve is one kernel: no level parts to time
+        parts = [parts[0], parts[-1]]
+    for kid, name in parts:
         ms, by = lap.lap_profile_kernel(h, kid, args.profile_reps, sh)
         kern[name] = {"avg_us": ms * 1e3, "alg_bytes": by, "gbs": by / (ms * 1e-3) / 1e9}
         log(f"kernel {name}: {ms * 1e3:.1f} us, {by / 1e6:.1f} MB, {kern[name]['gbs']:.0f} GB/s")
@@ -445,6 +490,8 @@ def main():
             if args.scale != 1.0 else WORKLOADS[args.workload],
             "precision": "FP64" if args.precision == "fp64" else
                          "FP32 SpMV/preconditioner inside FP64 iterative refinement",
+            "solver": "FGMRES on the expanded system" if args.solver == "fgmres" else
+                      "PCG on the original system",
             "n": n, "edges": int(len(wl["u"])), "levels": info["nlev"], "nrhs": args.nrhs,
             "iterations": inf["iterations"], "refinements": inf["refinements"],
             "relres_true": inf["relres_true"],
@@ -485,9 +532,12 @@ def main():
         line["speedup_vs_fp64"] = (base["elapsed"] / res["elapsed"]) if args.nrhs == 1 else \
             (base["elapsed"] / (res["elapsed"] / args.steps))
     if not args.no_cpu:
-        if args.workload == "grid3d_128" and args.scale == 1.0:
+        if args.workload == "grid3d_128" and args.scale == 1.0 and args.solver == "pcg":
             log("cpu baseline (oracle) ...")
             line["cpu_baseline"] = cpu_baseline(wl, inf["iterations"], args.cpu_seconds)
+        elif args.workload == "grid2d_64" and args.solver == "fgmres":
+            log("cpu baseline (oracle FGMRES) ...")
+            line["cpu_baseline"] = cpu_baseline_fgmres(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

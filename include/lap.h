@@ -62,6 +62,18 @@ typedef enum {
 #define LAP_FLAG_MULTI_RHS 2u  /* lap_setup also builds the block solve: calls
                                   with nrhs > 1 advance up to 64 columns
                                   together (see lap_solve) */
+#define LAP_FLAG_FGMRES 4u     /* lap_solve runs FGMRES on the expanded system
+                                  L_G~ x~ = P(mu)^T b^ (Sec. 2.2, the solver of
+                                  Sec. 4) instead of PCG: right-preconditioned
+                                  by the MSP or PEGP solve, no restart before
+                                  LAPGPU_FGMRES_RESTART (default 1000) steps
+                                  or an 8 GiB basis; tol applies to the
+                                  expanded residual.  FP64, one right-hand
+                                  side at a time; LAP_EUNSUPPORTED with
+                                  LAP_PREC_NONE or mixed precision.
+                                  info.iterations counts products with L_G~,
+                                  info.relres_recursive is the expanded
+                                  residual estimate. */
 
 /* Undirected weighted graph, host memory, edges (u[e], v[e], w[e]).
  * Requirements: n >= 2; 0 <= u, v < n; u != v; w finite and > 0.

@@ -1307,6 +1307,79 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailDesc* __restric
     }
 }
 
+// ------------------------------------------ FGMRES on the expanded system
+//
+// Expanded vectors (Sec. 2.2) hold the levels one after the other, each in
+// its tree numbering: level 0 has n values, level k+1 follows level k.
+// P(mu)^T y has level 0 = y and level k+1 = -mu times the sums of level k
+// over each aggregate's children.
+
+// Level 0 of P(mu)^T y: y (solve order) into tree order.
+__global__ __launch_bounds__(kBlock) void k_fg_level0(int n, const int32_t* __restrict__ t2s,
+                                                      const double* __restrict__ y,
+                                                      double* __restrict__ w) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) w[t] = y[t2s ? t2s[t] : t];
+}
+
+// Level k+1 from level k: out[J] = scale * sum over children c of J of in[c].
+__global__ __launch_bounds__(kBlock) void k_fg_restrict(int nc, const int32_t* __restrict__ cptr,
+                                                        const double* __restrict__ in,
+                                                        double* __restrict__ out,
+                                                        double scale) {
+    const int J = blockIdx.x * kBlock + threadIdx.x;
+    if (J >= nc) return;
+    double s = 0.0;
+    for (int c = cptr[J]; c < cptr[J + 1]; ++c) s += in[c];
+    out[J] = scale * s;
+}
+
+// Partial dot products of w with k basis vectors: block (x, i) adds the
+// rows x*kBlock + tid + j*gridDim.x*kBlock of V_i . w into part[i*G + x].
+__global__ __launch_bounds__(kBlock) void k_fg_mdot(int64_t nt, const double* __restrict__ V,
+                                                    int64_t ldv, const double* __restrict__ w,
+                                                    double* __restrict__ part) {
+    __shared__ double lds[kBlock / 64];
+    const int i = blockIdx.y, G = gridDim.x;
+    const double* v = V + (int64_t)i * ldv;
+    double acc[1] = {0.0};
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < nt; r += (int64_t)G * kBlock)
+        acc[0] += v[r] * w[r];
+    block_sum<1, kBlock>(acc, lds);
+    if (threadIdx.x == 0) part[(int64_t)i * G + blockIdx.x] = acc[0];
+}
+
+// out[i] = sum of the G partials of dot i, in block order (block i).
+__global__ __launch_bounds__(kBlock) void k_fg_dot_finish(int G, const double* __restrict__ part,
+                                                          double* __restrict__ out) {
+    __shared__ double lds[kBlock / 64];
+    const int i = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int b = threadIdx.x; b < G; b += kBlock) acc[0] += part[(int64_t)i * G + b];
+    block_sum<1, kBlock>(acc, lds);
+    if (threadIdx.x == 0) out[i] = acc[0];
+}
+
+// w += sign * sum_i h[i] V_i (k vectors, coefficients on the device).
+__global__ __launch_bounds__(kBlock) void k_fg_maxpy(int64_t nt, int k,
+                                                     const double* __restrict__ V, int64_t ldv,
+                                                     const double* __restrict__ h, double sign,
+                                                     double* __restrict__ w) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nt) return;
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += h[i] * V[(int64_t)i * ldv + r];
+    w[r] += sign * s;
+}
+
+// y = a * x + c * y (c = 0: y = a * x, whatever y held)
+__global__ __launch_bounds__(kBlock) void k_fg_axpby(int64_t nt, double a,
+                                                     const double* __restrict__ x, double c,
+                                                     double* __restrict__ y) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r < nt) y[r] = c == 0.0 ? a * x[r] : a * x[r] + c * y[r];
+}
+
 // ------------------------------------------------- solve set-up and finish
 
 __global__ __launch_bounds__(kBlock) void k_sum(int n, const double* __restrict__ a,
@@ -1363,62 +1436,124 @@ __global__ __launch_bounds__(kBlock) void k_init_outer(int n, const int32_t* __r
 
 // ------------------------------------------------------------------ PEGP
 
-// Rows [r0, r1) of one level of a level-scheduled triangular solve on the
-// LDS vector f: f[v] = f[v] * (scale ? 1/d_v : 1) - sum_k val[k] f[col[k]]
-// over row v's entries.  Many rows: a thread each; few rows: a wavefront
-// each; one long row: the whole block.
-__device__ inline void pegp_rows(double* f, const int32_t* __restrict__ rows,
+// sum over k = k0 + first, k0 + first + S, ... < k1 of val[k] * f[col[k]],
+// in rounds of eight entries whose loads are all issued before the first
+// product (the last round's missing entries are masked off)
+template <int S>
+__device__ inline double sparse_dot(const double* __restrict__ val,
+                                    const int32_t* __restrict__ col, int k0, int k1, int first,
+                                    const double* f) {
+    constexpr int U = 8;
+    double acc = 0.0;
+    for (int k = k0 + first; k < k1; k += U * S) {
+        double a[U];
+        int c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = k + u * S < k1;
+            a[u] = ok ? val[k + u * S] : 0.0;
+            c[u] = ok ? col[k + u * S] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k + u * S < k1) acc += a[u] * f[c[u]];
+    }
+    return acc;
+}
+
+// Rows [r0, r1) of one pass of a triangular solve on the LDS vector f: for
+// each row r, f[rows[r]] -= sum_k val[k] f[col[k]] over the row's entries
+// (no row of the pass reads another's node).  Groups of G lanes share a
+// row, rows dealt round-robin to the groups.
+template <int G>
+__device__ inline void pegp_rows_g(double* f, const int32_t* __restrict__ rows,
+                                   const int32_t* __restrict__ ptr,
+                                   const int32_t* __restrict__ col,
+                                   const double* __restrict__ val, int r0, int r1) {
+    constexpr int NG = kPegpThreads / G;
+    const int tid = threadIdx.x, q = tid & (G - 1);
+    for (int r = r0 + tid / G; r < r1; r += NG) {
+        double acc = sparse_dot<G>(val, col, ptr[r], ptr[r + 1], q, f);
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (q == 0) f[rows[r]] -= acc;
+    }
+}
+
+// One pass with 2^g lanes per row (g == kPegpWholeBlock: the single row
+// r0 takes the whole workgroup), then a barrier.
+__device__ __forceinline__ void pegp_rows(double* f, const int32_t* __restrict__ rows,
                                  const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                 const double* __restrict__ val, int r0, int r1, double* red) {
-    const int nr = r1 - r0, tid = threadIdx.x;
-    const int wid = tid >> 6, lane = tid & 63;
-    constexpr int NW = kPegpThreads / 64;
-    if (nr == 1 && ptr[r0 + 1] - ptr[r0] > 256) {
-        const int v = rows[r0];
-        double acc = 0.0;
-        for (int k = ptr[r0] + tid; k < ptr[r0 + 1]; k += kPegpThreads) acc += val[k] * f[col[k]];
+                                 const double* __restrict__ val, int r0, int r1, int g,
+                                 double* red) {
+    switch (g) {
+    case 0: pegp_rows_g<1>(f, rows, ptr, col, val, r0, r1); break;
+    case 1: pegp_rows_g<2>(f, rows, ptr, col, val, r0, r1); break;
+    case 2: pegp_rows_g<4>(f, rows, ptr, col, val, r0, r1); break;
+    case 3: pegp_rows_g<8>(f, rows, ptr, col, val, r0, r1); break;
+    case 4: pegp_rows_g<16>(f, rows, ptr, col, val, r0, r1); break;
+    case 5: pegp_rows_g<32>(f, rows, ptr, col, val, r0, r1); break;
+    case 6: pegp_rows_g<64>(f, rows, ptr, col, val, r0, r1); break;
+    default: {
+        constexpr int NW = kPegpThreads / 64;
+        const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+        double acc = sparse_dot<kPegpThreads>(val, col, ptr[r0], ptr[r0 + 1], tid, f);
         acc = wave_sum1(acc);
         if (lane == 0) red[wid] = acc;
         __syncthreads();
         if (tid == 0) {
             double t = 0.0;
             for (int w = 0; w < NW; ++w) t += red[w];
-            f[v] -= t;
+            f[rows[r0]] -= t;
         }
-    } else if (nr <= NW) {
-        if (wid < nr) {
-            const int r = r0 + wid, v = rows[r];
-            double acc = 0.0;
-            for (int k = ptr[r] + lane; k < ptr[r + 1]; k += 64) acc += val[k] * f[col[k]];
-            acc = wave_sum1(acc);
-            if (lane == 0) f[v] -= acc;
-        }
-    } else {
-        for (int r = r0 + tid; r < r1; r += kPegpThreads) {
-            const int v = rows[r];
-            double acc = 0.0;
-            for (int k = ptr[r]; k < ptr[r + 1]; ++k) acc += val[k] * f[col[k]];
-            f[v] -= acc;
-        }
+    }
     }
     __syncthreads();
 }
 
+// The levels of a level-scheduled triangular solve, one pass each; the next
+// level's bounds are loaded while the current one runs.
+__device__ __forceinline__ void pegp_levels(double* f, const int32_t* __restrict__ lev,
+                                   const int32_t* __restrict__ lg,
+                                   const int32_t* __restrict__ rows,
+                                   const int32_t* __restrict__ ptr,
+                                   const int32_t* __restrict__ col,
+                                   const double* __restrict__ val, int nl, double* red) {
+    if (nl <= 0) return;
+    int r0 = lev[0], r1 = lev[1], g = lg[0];
+    for (int l = 0; l < nl; ++l) {
+        const int ln = min(l + 1, nl - 1);
+        const int r2 = lev[ln + 1], g2 = lg[ln];
+        pegp_rows(f, rows, ptr, col, val, r0, r1, g, red);
+        r0 = r1;
+        r1 = r2;
+        g = g2;
+    }
+}
+
 // z = P(mu) S^-1 D P(mu)^T r with S = D L_H~ D grounded (Sec. 3.1-3.2),
-// then mean removed, in one workgroup: restriction sums up the tree, signs
-// (-1)^k (D P(mu)^T = (-1)^k times the plain sums on level k), forward
-// solve, diagonal, backward solve, signs, prolongation down the tree.  Writes
-// z (tree order) and zn (solve order, tree position t at perm[t]) and does
-// the finish step of the rho / zbar / beta reductions itself.
-__global__ __launch_bounds__(kPegpThreads) void k_pegp(PegpDev P,
-                                                       const int32_t* __restrict__ perm,
-                                                       const double* __restrict__ r,
-                                                       double* __restrict__ z,
-                                                       double* __restrict__ zn, Scal* S) {
+// then mean removed.  S = L D L^T is factored on the host; an apply runs
+// restriction sums up the tree, signs (-1)^k (D P(mu)^T is (-1)^k times the
+// plain sums on level k), the forward solve, the diagonal, the backward
+// solve, the signs again and prolongation down the tree.  The level-scheduled
+// parts run in one workgroup on an LDS copy of the expanded vector; the
+// dense tail of the factor (the last-eliminated nodes) is applied between
+// them by kernels over the whole device:
+//   k_pegp_fwd        restriction, signs, forward levels -> fg
+//   k_pegp_tail_rhs   y = f_tail - (tail rows' entries on the others) f
+//   k_pegp_tail_fwd   y = L_tt^-1 y, a kernel per block of the tail
+//   k_pegp_tail_bwd   y = L_tt^-T D_t^-1 y, the same
+//   k_pegp_tail_back  the other rows' entries on the tail times y
+//   k_pegp_bwd        diagonal, backward levels, signs, prolongation, z
+//                     and the rho / zbar / beta reductions
+
+__global__ __launch_bounds__(kPegpThreads) void k_pegp_fwd(PegpDev P,
+                                                           const double* __restrict__ r,
+                                                           const Scal* S) {
     if (S->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double* f = reinterpret_cast<double*>(smem);
-    __shared__ double red[3 * (kPegpThreads / 64)];
+    __shared__ double red[kPegpThreads / 64];
     const int tid = threadIdx.x, nth = kPegpThreads;
     const int n0 = P.off[1] - P.off[0], T = P.nlev - 1;
     for (int t = tid; t < n0; t += nth) f[t] = r[t];
@@ -1440,13 +1575,173 @@ __global__ __launch_bounds__(kPegpThreads) void k_pegp(PegpDev P,
     __syncthreads();
     if (tid == 0) f[P.ground] = 0.0;
     __syncthreads();
-    for (int l = 0; l < P.nflev; ++l)
-        pegp_rows(f, P.frow, P.fptr, P.fcol, P.fval, P.flev[l], P.flev[l + 1], red);
-    for (int e = tid; e < P.nt; e += nth)
-        if (e != P.ground) f[e] /= P.diag[e];
+    pegp_levels(f, P.flev, P.flg, P.frow, P.fptr, P.fcol, P.fval, P.nflev, red);
+    for (int e = tid; e < P.nt; e += nth) P.fg[e] = f[e];
+}
+
+// y[p] = f[drow[p]] - sum over tail row p's entries on the other nodes, a
+// wavefront per tail row.
+__global__ __launch_bounds__(kBlock) void k_pegp_tail_rhs(PegpDev P, const Scal* S) {
+    if (S->done) return;
+    const int p = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (p >= P.nd) return;
+    double acc = sparse_dot<64>(P.dcval, P.dccol, P.dcptr[p], P.dcptr[p + 1], lane, P.fg);
+    acc = wave_sum1(acc);
+    if (lane == 0) P.ty[p] = P.fg[P.drow[p]] - acc;
+}
+
+// The dense tail solves, y = L_tt^-1 y, y = D_t^-1 y and y = L_tt^-T y in
+// place on the tail vector, by blocks of kTailB rows with a kernel per block
+// (the kernels' order on the stream carries the dependencies).  In the
+// kernel for block b, the first wavefront of workgroup 0 brings the rows of
+// the next block up to date with block b's values and solves that block's
+// unit triangle, a lane per row holding its row of the block in registers
+// (coalesced loads of the factor's other orientation) and taking the solved
+// values from the lanes before it; the other workgroups apply block b's
+// values to all rows past the next block, a wavefront per row.
+constexpr int kTailB = 64;
+
+// v broadcast from lane j (j uniform)
+__device__ inline double lane_bcast(double v, int j) {
+    const unsigned long long u = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, j);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), j);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// sum over j < n (n <= kTailB) of a[j * stride] * x[j], the loads issued in
+// two batches of half a block each (the terms past n load entry n - 1 and
+// count 0: no load is masked, so none is waited for on its own)
+__device__ inline double tail_dot(const double* __restrict__ a, int stride,
+                                  const double* __restrict__ x, int n) {
+    constexpr int H = kTailB / 2;
+    double acc = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        double v[H], w[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const int jj = min(h * H + j, n - 1);
+            v[j] = a[(size_t)jj * stride];
+            w[j] = x[jj];
+        }
+#pragma unroll
+        for (int j = 0; j < H; ++j) acc += (h * H + j < n ? v[j] : 0.0) * w[j];
+    }
+    return acc;
+}
+
+// forward, block b solved (b = -1: none yet); solves block b + 1
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pegp_tail_fwd(PegpDev P, int b, const Scal* S) {
+    if (S->done) return;
+    const int nd = P.nd, b0 = b * kTailB, b1 = (b + 1) * kTailB, nb1 = min(kTailB, nd - b1);
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    constexpr int NW = kBlock / 64;
+    double* y = P.ty;
+    if (blockIdx.x == 0) {
+        if (wid != 0) return;
+        // Lanes past the block's end repeat its last row: they are never
+        // broadcast or stored, so no load needs a mask (a masked load would
+        // be waited for on its own).
+        const int row = b1 + min(lane, nb1 - 1);
+        // L[j] = L_tt[row][b1 + j], used for j < lane
+        double L[kTailB];
+#pragma unroll
+        for (int j = 0; j < kTailB; ++j) L[j] = P.dlc[(size_t)(b1 + min(j, nb1 - 1)) * nd + row];
+        double yi = y[row];
+        if (b >= 0) yi -= tail_dot(P.dlc + (size_t)b0 * nd + row, nd, y + b0, kTailB);
+#pragma unroll
+        for (int j = 0; j + 1 < kTailB; ++j) {
+            if (j + 1 >= nb1) continue;
+            const double xj = lane_bcast(yi, j);
+            if (lane > j) yi -= L[j] * xj;
+        }
+        if (lane < nb1) y[row] = yi;
+        return;
+    }
+    const int r = b1 + kTailB + (blockIdx.x - 1) * NW + wid;
+    if (b < 0 || r >= nd) return;
+    double a = P.dlr[(size_t)r * nd + b0 + lane] * y[b0 + lane];
+    a = wave_sum1(a);
+    if (lane == 0) y[r] -= a;
+}
+
+// backward, block b solved (b = nblk: none yet; then the diagonal D_t^-1 is
+// applied to every tail row first); solves block b - 1
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pegp_tail_bwd(PegpDev P, int b, int nblk,
+                                                          const Scal* S) {
+    if (S->done) return;
+    const int nd = P.nd, c0 = (b - 1) * kTailB, nc = min(kTailB, nd - c0);
+    const int b0 = b * kTailB, nb = b < nblk ? min(kTailB, nd - b0) : 0;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    constexpr int NW = kBlock / 64;
+    double* y = P.ty;
+    if (blockIdx.x == 0) {
+        if (wid != 0) return;
+        // (lanes past the block's end as in the forward kernel)
+        const int row = c0 + min(lane, nc - 1);
+        // L[j] = L_tt[c0 + j][row], used for lane < j < nc
+        double L[kTailB];
+#pragma unroll
+        for (int j = 0; j < kTailB; ++j) L[j] = P.dlr[(size_t)(c0 + min(j, nc - 1)) * nd + row];
+        double yi = y[row];
+        if (b == nblk) {
+            yi /= P.diag[P.drow[row]];
+        } else {
+            yi -= tail_dot(P.dlr + (size_t)b0 * nd + row, nd, y + b0, nb);
+        }
+#pragma unroll
+        for (int j = kTailB - 1; j > 0; --j) {
+            if (j >= nc) continue;
+            const double xj = lane_bcast(yi, j);
+            if (lane < j) yi -= L[j] * xj;
+        }
+        if (lane < nc) y[row] = yi;
+        return;
+    }
+    if (b == nblk) {
+        const int r = (blockIdx.x - 1) * kBlock + tid;
+        if (r < c0) y[r] /= P.diag[P.drow[r]];
+        return;
+    }
+    const int r = (blockIdx.x - 1) * NW + wid;
+    if (r >= c0) return;
+    double a = lane < nb ? P.dlc[(size_t)r * nd + b0 + lane] * y[b0 + lane] : 0.0;
+    a = wave_sum1(a);
+    if (lane == 0) y[r] -= a;
+}
+
+// cpl[i] = sum over row bcrow[i]'s entries on the tail of l * y_tail, a
+// wavefront per row.
+__global__ __launch_bounds__(kBlock) void k_pegp_tail_back(PegpDev P, const Scal* S) {
+    if (S->done) return;
+    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= P.nbc) return;
+    double acc = sparse_dot<64>(P.bcval, P.bccol, P.bcptr[i], P.bcptr[i + 1], lane, P.ty);
+    acc = wave_sum1(acc);
+    if (lane == 0) P.cpl[i] = acc;
+}
+
+// Writes z (tree order) and zn (solve order, tree position t at perm[t]) and
+// does the finish step of the rho / zbar / beta reductions itself.
+__global__ __launch_bounds__(kPegpThreads) void k_pegp_bwd(PegpDev P,
+                                                           const int32_t* __restrict__ perm,
+                                                           const double* __restrict__ r,
+                                                           double* __restrict__ z,
+                                                           double* __restrict__ zn, Scal* S) {
+    if (S->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* f = reinterpret_cast<double*>(smem);
+    __shared__ double red[3 * (kPegpThreads / 64)];
+    const int tid = threadIdx.x, nth = kPegpThreads;
+    const int n0 = P.off[1] - P.off[0], T = P.nlev - 1;
+    for (int e = tid; e < P.nt; e += nth) f[e] = e != P.ground ? P.fg[e] / P.diag[e] : 0.0;
     __syncthreads();
-    for (int l = 0; l < P.nblev; ++l)
-        pegp_rows(f, P.brow, P.bptr, P.bcol, P.bval, P.blev[l], P.blev[l + 1], red);
+    // the tail's values, and its contributions to the other rows
+    for (int p = tid; p < P.nd; p += nth) f[P.drow[p]] = P.ty[p];
+    for (int i = tid; i < P.nbc; i += nth) f[P.bcrow[i]] -= P.cpl[i];
+    __syncthreads();
+    pegp_levels(f, P.blev, P.blg, P.brow, P.bptr, P.bcol, P.bval, P.nblev, red);
     for (int k = 1; k <= T; k += 2)
         for (int e = P.off[k] + tid; e < P.off[k + 1]; e += nth) f[e] = -f[e];
     __syncthreads();

@@ -205,10 +205,22 @@ struct PegpDev {
     int32_t off[kPegpMaxLevels + 1];     // level -> first expanded index
     const int32_t* cptr[kPegpMaxLevels]; // children ranges of level k+1 nodes
     const double* diag;
-    const int32_t *flev, *frow, *fptr, *fcol;
+    // level lists: level -> first row, log2 of the lanes per row, row ->
+    // node, the row's entries (CSR)
+    const int32_t *flev, *flg, *frow, *fptr, *fcol;
     const double* fval;
-    const int32_t *blev, *brow, *bptr, *bcol;
+    const int32_t *blev, *blg, *brow, *bptr, *bcol;
     const double* bval;
+    // dense tail (nd rows, 0: none): tail position -> node, the strict lower
+    // factor of the tail row-major (forward) and column-major (backward), the
+    // forward coupling (CSR by tail position, columns are nodes), the
+    // backward coupling (nbc rows bcrow, columns are tail positions)
+    int32_t nd, nbc;
+    const int32_t *drow, *dcptr, *dccol, *bcrow, *bcptr, *bccol;
+    const double *dlr, *dlc, *dcval, *bcval;
+    // device scratch of one apply: the expanded vector between the
+    // single-workgroup kernels, the tail's values, the backward coupling sums
+    double *fg, *ty, *cpl;
 };
 
 }  // namespace lapgpu

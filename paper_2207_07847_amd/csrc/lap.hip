@@ -441,6 +441,17 @@ struct lap_hierarchy {
     double* partm2 = nullptr;
     // FP64 vectors in input order
     double *bh = nullptr, *xc = nullptr, *x64 = nullptr, *r64 = nullptr;
+    // FGMRES on the expanded system (LAP_FLAG_FGMRES), allocated by the first
+    // such solve: a basis of fg_m + 1 expanded vectors of fg_nt values
+    int fg_m = 0;
+    int64_t fg_nt = 0;
+    std::vector<int64_t> fg_off;         // level offsets in an expanded vector
+    double* fg_V = nullptr;
+    double* fg_w = nullptr;
+    double *fg_y = nullptr, *fg_x = nullptr, *fg_r = nullptr;   // n each, solve order
+    double* fg_part = nullptr;           // partial dot products
+    double* fg_h = nullptr;              // dot results / coefficients on the device
+    double* fg_hh = nullptr;             // pinned host copy
     Scal* S = nullptr;           // scalars of the PCG run
     Scal* So = nullptr;          // scalars of the outer refinement loop
     double* part = nullptr;      // per-block partial sums of the last producer
@@ -491,6 +502,7 @@ struct lap_hierarchy {
         for (void* ptr : allocs) (void)hipFree(ptr);
         if (stage) (void)hipHostFree(stage);
         if (stagem) (void)hipHostFree(stagem);
+        if (fg_hh) (void)hipHostFree(fg_hh);
     }
     template <class P>
     Chunks upload_chunks(const ChunkHost<P>& c, hipStream_t s) {
@@ -552,7 +564,35 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
                                    h->t2s, e.r, (const T*)e.q, S, h->part2);
                 finish<kFinRr>(h, s, S, nblk(n), 0, h->part2);
             }
-            hipLaunchKernelGGL(k_pegp, dim3(1), dim3(kPegpThreads), h->pegp_lds, s, h->pegp_dev,
+            const PegpDev& P = h->pegp_dev;
+            hipLaunchKernelGGL(k_pegp_fwd, dim3(1), dim3(kPegpThreads), h->pegp_lds, s, P,
+                               (const double*)e.r, (const Scal*)S);
+            if (P.nd > 0) {
+                const int per = kBlock / 64;   // a wavefront per row
+                hipLaunchKernelGGL(k_pegp_tail_rhs, dim3((P.nd + per - 1) / per), dim3(kBlock), 0,
+                                   s, P, (const Scal*)S);
+                const int nblk = (P.nd + kTailB - 1) / kTailB;
+                for (int b = -1; b + 1 < nblk; ++b) {
+                    // workgroup 0, and a wavefront per row past the next block
+                    const int rest = std::max(0, P.nd - (b + 2) * kTailB);
+                    const int grid = 1 + (b >= 0 ? (rest + per - 1) / per : 0);
+                    hipLaunchKernelGGL(k_pegp_tail_fwd, dim3(grid), dim3(kBlock), 0, s, P, b,
+                                       (const Scal*)S);
+                }
+                for (int b = nblk; b > 0; --b) {
+                    // workgroup 0, and the rows before the block being solved:
+                    // a thread each for the diagonal, then a wavefront each
+                    const int before = (b - 1) * kTailB;
+                    const int grid = 1 + (b == nblk ? (before + kBlock - 1) / kBlock
+                                                    : (before + per - 1) / per);
+                    hipLaunchKernelGGL(k_pegp_tail_bwd, dim3(grid), dim3(kBlock), 0, s, P, b,
+                                       nblk, (const Scal*)S);
+                }
+                if (P.nbc > 0)
+                    hipLaunchKernelGGL(k_pegp_tail_back, dim3((P.nbc + per - 1) / per),
+                                       dim3(kBlock), 0, s, P, (const Scal*)S);
+            }
+            hipLaunchKernelGGL(k_pegp_bwd, dim3(1), dim3(kPegpThreads), h->pegp_lds, s, P,
                                h->t2s, (const double*)e.r, e.z, e.zn, S);
             return;
         }
@@ -853,18 +893,37 @@ void upload_pegp(lap_hierarchy* h, hipStream_t s) {
     d.diag = h->upload(G.diag, s);
     d.nflev = (int32_t)G.flev.size() - 1;
     d.flev = h->upload(G.flev, s);
+    d.flg = h->upload(G.flg, s);
     d.frow = h->upload(G.frow, s);
     d.fptr = h->upload(G.fptr, s);
     d.fcol = h->upload(G.fcol, s);
     d.fval = h->upload(G.fval, s);
     d.nblev = (int32_t)G.blev.size() - 1;
     d.blev = h->upload(G.blev, s);
+    d.blg = h->upload(G.blg, s);
     d.brow = h->upload(G.brow, s);
     d.bptr = h->upload(G.bptr, s);
     d.bcol = h->upload(G.bcol, s);
     d.bval = h->upload(G.bval, s);
+    d.nd = G.nd;
+    d.nbc = (int32_t)G.bcrow.size();
+    d.drow = h->upload(G.drow, s);
+    d.dlr = h->upload(G.dlr, s);
+    d.dlc = h->upload(G.dlc, s);
+    d.dcptr = h->upload(G.dcptr, s);
+    d.dccol = h->upload(G.dccol, s);
+    d.dcval = h->upload(G.dcval, s);
+    d.bcrow = h->upload(G.bcrow, s);
+    d.bcptr = h->upload(G.bcptr, s);
+    d.bccol = h->upload(G.bccol, s);
+    d.bcval = h->upload(G.bcval, s);
+    d.fg = h->dalloc<double>(G.nt);
+    d.ty = h->dalloc<double>(G.nd);
+    d.cpl = h->dalloc<double>(G.bcrow.size());
     h->pegp_lds = (size_t)G.nt * sizeof(double);
-    HIPCHK(hipFuncSetAttribute((const void*)k_pegp, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIPCHK(hipFuncSetAttribute((const void*)k_pegp_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)h->pegp_lds));
+    HIPCHK(hipFuncSetAttribute((const void*)k_pegp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)h->pegp_lds));
 }
 
@@ -1108,6 +1167,7 @@ constexpr int kTuneSegs[] = {32, 64, 128, 256};
 constexpr int kTuneReps = 3;
 constexpr size_t kTuneMaxScratch = size_t(512) << 20;  // split-row scratch of a candidate
 static_assert(2048 <= 3 * kMmMaxGrid, "the SpMM's partials fit the partial buffer");
+static_assert(kPegpThreads == kPegpSolveThreads, "the PEGP plan is made for the solve's workgroup");
 
 // Average time per call of `launch` over kTuneReps calls after one warm-up.
 template <class F>
@@ -1300,6 +1360,211 @@ void begin_solve(lap_hierarchy* h, const double* b, bool outer, hipStream_t s) {
                        h->part);
     finish<kFinRes2>(h, s, h->So, nblk(n));
     HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------ FGMRES
+//
+// FGMRES on the expanded system L_G~ x~ = P(mu)^T b^ (Sec. 2.2; the solver
+// of Sec. 4), right-preconditioned by the grounded inverse of L_T~ (MSP) or
+// L_H~ (PEGP), without restarts up to the basis size.  Every basis vector
+// lies in the range of P(mu)^T (b~ does, and so does every L_G~ M~ v~), so
+// v~ = P(mu)^T u with u its level-0 block, and
+//   L_G~ M~ v~ = P(mu)^T L_G (P(mu) M~ P(mu)^T) u = P(mu)^T L_G (M u),
+// M the preconditioner of the PCG path (up to a constant, which L_G
+// removes).  A step is: M on the level-0 block, the product with L_G, the
+// expansion P(mu)^T (level sums), classical Gram-Schmidt twice against the
+// basis; the Givens rotations of the small Hessenberg matrix run on the
+// host.  At the end x = P(mu) M~ V y = M (sum_i y_i u_i).  A step is one
+// product with L_G~, as in the paper's step counts.
+
+constexpr int kFgDotBlocks = 128;       // row blocks of a dot product
+constexpr size_t kFgMaxBasisBytes = size_t(8) << 30;
+
+void fg_alloc(lap_hierarchy* h, int m_req) {
+    const HostPlan& P = h->plan;
+    const int L = P.nlev();
+    std::vector<int64_t> off(L + 1, 0);
+    for (int k = 0; k < L; ++k) off[k + 1] = off[k] + P.lv[k].g.n;
+    const int64_t nt = off[L];
+    const int m_mem = (int)std::max<int64_t>(1, (int64_t)(kFgMaxBasisBytes / (8 * nt)) - 1);
+    const int m = std::max(1, std::min(m_req, m_mem));
+    if (h->fg_V && h->fg_m == m) return;
+    if (h->fg_V) throw std::runtime_error("FGMRES basis size changed");
+    h->fg_m = m;
+    h->fg_nt = nt;
+    h->fg_off = off;
+    h->fg_V = h->dalloc<double>((size_t)(m + 1) * nt);
+    h->fg_w = h->dalloc<double>(nt);
+    h->fg_y = h->dalloc<double>(h->n);
+    h->fg_x = h->dalloc<double>(h->n);
+    h->fg_r = h->dalloc<double>(h->n);
+    h->fg_part = h->dalloc<double>((size_t)(m + 1) * kFgDotBlocks);
+    h->fg_h = h->dalloc<double>(2 * (size_t)(m + 1) + 2);
+    HIPCHK(hipHostMalloc((void**)&h->fg_hh, sizeof(double) * (2 * (size_t)(m + 1) + 2),
+                         hipHostMallocDefault));
+}
+
+// w = P(mu)^T y (y in solve order)
+void fg_expand(lap_hierarchy* h, const double* y, double* w, hipStream_t s) {
+    const int n = (int)h->n, L = h->plan.nlev();
+    hipLaunchKernelGGL(k_fg_level0, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s, y, w);
+    for (int k = 0; k + 1 < L; ++k) {
+        const int nc = (int)h->plan.lv[k + 1].g.n;
+        hipLaunchKernelGGL(k_fg_restrict, dim3(nblk(nc)), dim3(kBlock), 0, s, nc,
+                           (const int32_t*)h->cptr[k], (const double*)(w + h->fg_off[k]),
+                           w + h->fg_off[k + 1], -h->params.mu);
+    }
+}
+
+// out[0..k) = V_i . w for the first k basis vectors (device)
+void fg_dots(lap_hierarchy* h, int k, const double* V, const double* w, double* out,
+             hipStream_t s) {
+    const int64_t nt = h->fg_nt;
+    const int G = (int)std::min<int64_t>(kFgDotBlocks, (nt + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_fg_mdot, dim3(G, k), dim3(kBlock), 0, s, nt, V, nt, w, h->fg_part);
+    hipLaunchKernelGGL(k_fg_dot_finish, dim3(k), dim3(kBlock), 0, s, G,
+                       (const double*)h->fg_part, out);
+}
+
+lap_status solve_fgmres(lap_hierarchy* h, const double* b, double* x, double tol,
+                        lap_solve_info* info, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!h->with_msp && !h->pegp) return LAP_EUNSUPPORTED;
+    fg_alloc(h, env_int("LAPGPU_FGMRES_RESTART", 1000));
+    const int n = (int)h->n, m = h->fg_m;
+    const int64_t nt = h->fg_nt;
+    Engine<double>& e = h->e64;
+    begin_solve(h, b, false, s);
+    const double bn2 = read_scal(h, h->So, s).res2;
+    if (!std::isfinite(bn2)) return LAP_EINVAL;
+    // the preconditioner kernels run while S->done is 0
+    std::memset(h->stage, 0, sizeof(Scal));
+    HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(h->fg_x, 0, sizeof(double) * n, s));
+    double* V = h->fg_V;
+    double* w = h->fg_w;
+    double* hh = h->fg_hh;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto Hc = [&](int i, int j) -> double& { return H[(size_t)j * (m + 1) + i]; };
+    auto norm2 = [&](const double* v) {
+        fg_dots(h, 1, v, v, h->fg_h, s);
+        HIPCHK(hipMemcpyAsync(hh, h->fg_h, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return hh[0];
+    };
+    const int maxit = h->params.max_iter;
+    int total = 0;
+    double beta0 = 0.0, est = 1.0;
+    lap_status st = LAP_ENOCONV;
+    const double* rsrc = h->bh;   // residual of the current cycle (solve order)
+    for (bool first = true; total < maxit; first = false) {
+        fg_expand(h, rsrc, V, s);
+        const double beta = std::sqrt(norm2(V));
+        if (first) beta0 = beta;
+        if (!(beta0 > 0.0) || beta <= tol * beta0) {
+            est = beta0 > 0.0 ? beta / beta0 : 0.0;
+            st = LAP_OK;
+            break;
+        }
+        hipLaunchKernelGGL(k_fg_axpby, dim3(nblk(nt)), dim3(kBlock), 0, s, nt, 1.0 / beta,
+                           (const double*)V, 0.0, V);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool conv = false;
+        for (int j = 0; j < m && total < maxit; ++j) {
+            double* vj = V + (size_t)j * nt;
+            // z = M u_j (u_j: level 0 of v_j, tree order), then L z, expanded
+            HIPCHK(hipMemcpyAsync(e.r, vj, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            enqueue_precond(h, e, s, 0);
+            hipLaunchKernelGGL(k_spmv_plain, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb,
+                               e.A, (const double*)e.zn, h->fg_y);
+            fg_expand(h, h->fg_y, w, s);
+            // classical Gram-Schmidt, twice
+            double* h1 = h->fg_h;
+            double* h2 = h->fg_h + (m + 1);
+            fg_dots(h, j + 1, V, w, h1, s);
+            hipLaunchKernelGGL(k_fg_maxpy, dim3(nblk(nt)), dim3(kBlock), 0, s, nt, j + 1,
+                               (const double*)V, nt, (const double*)h1, -1.0, w);
+            fg_dots(h, j + 1, V, w, h2, s);
+            hipLaunchKernelGGL(k_fg_maxpy, dim3(nblk(nt)), dim3(kBlock), 0, s, nt, j + 1,
+                               (const double*)V, nt, (const double*)h2, -1.0, w);
+            fg_dots(h, 1, w, w, h->fg_h + 2 * (m + 1), s);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(hh, h->fg_h, sizeof(double) * (2 * (size_t)(m + 1) + 1),
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ++total;
+            for (int i = 0; i <= j; ++i) Hc(i, j) = hh[i] + hh[(m + 1) + i];
+            const double hn = std::sqrt(std::max(hh[2 * (m + 1)], 0.0));
+            Hc(j + 1, j) = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = Hc(i, j), c = Hc(i + 1, j);
+                Hc(i, j) = cs[i] * a + sn[i] * c;
+                Hc(i + 1, j) = -sn[i] * a + cs[i] * c;
+            }
+            const double den = std::hypot(Hc(j, j), Hc(j + 1, j));
+            cs[j] = den == 0.0 ? 1.0 : Hc(j, j) / den;
+            sn[j] = den == 0.0 ? 0.0 : Hc(j + 1, j) / den;
+            Hc(j, j) = den;
+            Hc(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            est = std::fabs(g[j + 1]) / beta0;
+            if (std::fabs(g[j + 1]) <= tol * beta0) {
+                conv = true;
+                break;
+            }
+            if (!(hn > 0.0) || !std::isfinite(hn)) break;
+            hipLaunchKernelGGL(k_fg_axpby, dim3(nblk(nt)), dim3(kBlock), 0, s, nt, 1.0 / hn,
+                               (const double*)w, 0.0, V + (size_t)(j + 1) * nt);
+        }
+        if (k == 0) break;
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int c = i + 1; c < k; ++c) t -= Hc(i, c) * y[c];
+            y[i] = t / Hc(i, i);
+        }
+        if (!std::all_of(y.begin(), y.begin() + k, [](double v) { return std::isfinite(v); })) {
+            st = LAP_EBREAKDOWN;
+            break;
+        }
+        // x += M (sum_i y_i u_i): the level-0 blocks combined into e.r
+        std::copy(y.begin(), y.begin() + k, hh);
+        HIPCHK(hipMemcpyAsync(h->fg_h, hh, sizeof(double) * k, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(e.r, 0, sizeof(double) * n, s));
+        hipLaunchKernelGGL(k_fg_maxpy, dim3(nblk(n)), dim3(kBlock), 0, s, (int64_t)n, k,
+                           (const double*)V, nt, (const double*)h->fg_h, 1.0, e.r);
+        enqueue_precond(h, e, s, 0);
+        hipLaunchKernelGGL(k_fg_axpby, dim3(nblk(n)), dim3(kBlock), 0, s, (int64_t)n, 1.0,
+                           (const double*)e.zn, 1.0, h->fg_x);
+        HIPCHK(hipStreamSynchronize(s));
+        if (conv) {
+            st = LAP_OK;
+            break;
+        }
+        // restart from the true residual
+        hipLaunchKernelGGL(k_resid, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A,
+                           (const double*)h->fg_x,
+                           (const double*)h->bh, h->fg_r, h->part);
+        rsrc = h->fg_r;
+    }
+    finalize_x(h, h->fg_x, x, s);
+    // LAP_OK: the expanded residual met tol (the stop test of Sec. 4); the
+    // residual of the original system is reported as measured
+    const Scal O = read_scal(h, h->So, s);
+    if (info) {
+        const double bn = std::sqrt(bn2);
+        info->iterations = total;
+        info->refinements = 0;
+        info->relres_true = bn > 0 ? std::sqrt(O.res2) / bn : 0.0;
+        info->relres_recursive = est;
+        info->status = st;
+        info->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
 }
 
 lap_status solve_fp64(lap_hierarchy* h, const double* b, double* x, double tol,
@@ -2259,12 +2524,15 @@ lap_status lap_solve(lap_hierarchy* h, const double* b, double* x, int32_t nrhs,
             }
             return worst;
         }
+        const bool fgmres = (h->params.flags & LAP_FLAG_FGMRES) != 0;
+        if (fgmres && h->mixed) return LAP_EUNSUPPORTED;
         for (int c = 0; c < nrhs; ++c) {
             const double* bc = b + (int64_t)c * ld;
             double* xc = x + (int64_t)c * ld;
             lap_solve_info* ic = info ? info + c : nullptr;
             const lap_status st =
-                !h->mixed ? solve_fp64(h, bc, xc, tol, ic, (hipStream_t)stream)
+                fgmres ? solve_fgmres(h, bc, xc, tol, ic, (hipStream_t)stream)
+                : !h->mixed ? solve_fp64(h, bc, xc, tol, ic, (hipStream_t)stream)
                 : h->reliable ? solve_mixed_reliable(h, bc, xc, tol, ic, (hipStream_t)stream)
                               : solve_mixed(h, bc, xc, tol, ic, (hipStream_t)stream);
             if (rank_status(st) > rank_status(worst)) worst = st;

@@ -529,6 +529,38 @@ void build_sell(const Adjacency& g, HostPlan& plan) {
 
 // ------------------------------------------------------------------ PEGP
 
+// How many lanes share a row in the rows [r0, r1) of a PEGP solve pass
+// (log2; kPegpWholeBlock: the single row takes the whole workgroup).  Rows
+// are dealt round-robin to groups of G lanes; a lane loads eight entries a
+// round, so a group spends max(1, ceil(len / 8G)) rounds on a row plus a
+// little per reduction step.  The pick minimises the busiest group's time.
+static int32_t pegp_lanes(const std::vector<int32_t>& ptr, int32_t r0, int32_t r1) {
+    int32_t best = 0;
+    double best_cost = 1e300;
+    for (int g = 0; g <= 6; ++g) {
+        const int64_t G = 1 << g, NG = kPegpSolveThreads / G;
+        double worst = 0.0;
+        for (int64_t s = 0; s < NG && r0 + s < r1; ++s) {
+            double c = 0.0;
+            for (int64_t r = r0 + s; r < r1; r += NG) {
+                const int64_t len = ptr[r + 1] - ptr[r];
+                c += (double)std::max<int64_t>(1, (len + 8 * G - 1) / (8 * G)) + 0.1 * g;
+            }
+            worst = std::max(worst, c);
+        }
+        if (worst < best_cost) {
+            best_cost = worst;
+            best = g;
+        }
+    }
+    if (r1 - r0 == 1) {
+        const int64_t len = ptr[r0 + 1] - ptr[r0];
+        const double whole = (double)((len + 8 * kPegpSolveThreads - 1) / (8 * kPegpSolveThreads)) + 1.0;
+        if (whole < best_cost) best = kPegpWholeBlock;
+    }
+    return best;
+}
+
 int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
     const int L = P.nlev();
     const int T = L - 1;
@@ -687,17 +719,27 @@ int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
         for (auto& e : colL[*it]) d = std::max(d, lb[e.first] + 1);
         lb[*it] = d;
     }
+    // level schedule of the nodes with keep[v] (all when keep is empty)
     auto schedule = [&](const std::vector<int32_t>& lv, const std::vector<std::vector<std::pair<int32_t, double>>>& ent,
                         std::vector<int32_t>& levp, std::vector<int32_t>& rows, std::vector<int32_t>& ptr,
-                        std::vector<int32_t>& col, std::vector<double>& val) {
-        int nl = 0;
-        for (int32_t v = 0; v < m; ++v) nl = std::max(nl, lv[v] + 1);
+                        std::vector<int32_t>& col, std::vector<double>& val,
+                        const std::vector<char>& keep) {
+        auto kept = [&](int32_t v) { return keep.empty() || keep[v]; };
+        int nl = 0, nr = 0;
+        for (int32_t v = 0; v < m; ++v)
+            if (kept(v)) {
+                nl = std::max(nl, lv[v] + 1);
+                ++nr;
+            }
         levp.assign(nl + 1, 0);
-        for (int32_t v = 0; v < m; ++v) ++levp[lv[v] + 1];
+        for (int32_t v = 0; v < m; ++v)
+            if (kept(v)) ++levp[lv[v] + 1];
         for (int l = 0; l < nl; ++l) levp[l + 1] += levp[l];
-        rows.assign(m, 0);
+        rows.assign(nr, 0);
         std::vector<int32_t> fill(levp.begin(), levp.end() - 1);
-        for (int32_t v : order) rows[fill[lv[v]]++] = v;
+        for (int32_t v : order)
+            if (kept(v)) rows[fill[lv[v]]++] = v;
+        const int32_t m = nr;
         ptr.assign(m + 1, 0);
         col.clear();
         val.clear();
@@ -709,8 +751,88 @@ int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
             ptr[r + 1] = (int32_t)col.size();
         }
     };
-    schedule(lf, rowL, out.flev, out.frow, out.fptr, out.fcol, out.fval);
-    schedule(lb, colL, out.blev, out.brow, out.bptr, out.bcol, out.bval);
+    schedule(lf, rowL, out.flev, out.frow, out.fptr, out.fcol, out.fval, {});
+    // the dense tail: trailing forward levels of at most kPegpTailWidth rows
+    const int nfl = (int)out.flev.size() - 1;
+    int lt = nfl;
+    int32_t nd = 0;
+    while (lt > 0) {
+        const int32_t wdt = out.flev[lt] - out.flev[lt - 1];
+        if (wdt > kPegpTailWidth || nd + wdt > kPegpMaxDense) break;
+        nd += wdt;
+        --lt;
+    }
+    if (nd < kPegpMinDense || env_or("LAPGPU_PEGP_DENSE", 1) == 0) {
+        nd = 0;
+        lt = nfl;
+    }
+    std::vector<int32_t> tpos(m, -1);
+    out.nd = nd;
+    out.drow.assign(out.frow.begin() + out.flev[lt], out.frow.begin() + out.flev[nfl]);
+    for (int32_t p = 0; p < nd; ++p) tpos[out.drow[p]] = p;
+    out.dlr.assign((size_t)nd * nd, 0.0);
+    out.dlc.assign((size_t)nd * nd, 0.0);
+    out.dcptr.assign(nd + 1, 0);
+    for (int32_t p = 0; p < nd; ++p) {
+        for (auto& e : rowL[out.drow[p]]) {
+            const int32_t q = tpos[e.first];
+            if (q >= 0) {
+                // dependencies lie on earlier levels: earlier tail positions
+                if (q >= p) return kInval;
+                out.dlr[(size_t)p * nd + q] = e.second;
+                out.dlc[(size_t)q * nd + p] = e.second;
+            } else {
+                out.dccol.push_back(e.first);
+                out.dcval.push_back(e.second);
+            }
+        }
+        out.dcptr[p + 1] = (int32_t)out.dccol.size();
+    }
+    out.flev.resize(lt + 1);
+    // backward levels of the other rows, counted over their dependencies on
+    // each other only: the tail is solved first, and its contributions to
+    // the other rows are applied in one pass before the levels
+    std::vector<char> keep;
+    const std::vector<std::vector<std::pair<int32_t, double>>>* bent = &colL;
+    std::vector<std::vector<std::pair<int32_t, double>>> colN;
+    if (nd > 0) {
+        keep.assign(m, 1);
+        for (int32_t p = 0; p < nd; ++p) keep[out.drow[p]] = 0;
+        colN.resize(m);
+        out.bcptr.assign(1, 0);
+        for (int32_t v = 0; v < m; ++v) {
+            if (!keep[v]) continue;
+            const size_t k0 = out.bccol.size();
+            for (auto& e : colL[v]) {
+                if (keep[e.first]) {
+                    colN[v].push_back(e);
+                } else {
+                    out.bccol.push_back(tpos[e.first]);
+                    out.bcval.push_back(e.second);
+                }
+            }
+            if (out.bccol.size() > k0) {
+                out.bcrow.push_back(v);
+                out.bcptr.push_back((int32_t)out.bccol.size());
+            }
+        }
+        bent = &colN;
+        std::fill(lb.begin(), lb.end(), 0);
+        for (auto it = order.rbegin(); it != order.rend(); ++it) {
+            if (!keep[*it]) continue;
+            int d = 0;
+            for (auto& e : colN[*it]) d = std::max(d, lb[e.first] + 1);
+            lb[*it] = d;
+        }
+    }
+    schedule(lb, *bent, out.blev, out.brow, out.bptr, out.bcol, out.bval, keep);
+    // lanes per row of every level and coupling pass
+    out.flg.resize(out.flev.size() - 1);
+    for (size_t l = 0; l + 1 < out.flev.size(); ++l)
+        out.flg[l] = pegp_lanes(out.fptr, out.flev[l], out.flev[l + 1]);
+    out.blg.resize(out.blev.size() - 1);
+    for (size_t l = 0; l + 1 < out.blev.size(); ++l)
+        out.blg[l] = pegp_lanes(out.bptr, out.blev[l], out.blev[l + 1]);
     return kOk;
 }
 

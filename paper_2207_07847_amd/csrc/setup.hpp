@@ -101,7 +101,32 @@ struct PegpPlan {
     std::vector<int32_t> blev, brow, bptr, bcol;
     std::vector<double> bval;
     int64_t nnz_s = 0, nnz_l = 0;            // off-diagonals of S (both halves), of L
+    // Dense tail: the trailing forward levels of at most kPegpTailWidth rows
+    // (the nearly dense last-eliminated block of the minimum-degree order),
+    // solved by dense blocked substitution over the whole device.  No other
+    // row depends on the tail in the forward pass, and the tail depends on no
+    // other row in the backward pass; the level lists above leave it out.
+    int32_t nd = 0;                          // tail rows (0: none)
+    std::vector<int32_t> drow;               // tail position -> expanded node
+    std::vector<double> dlr, dlc;            // nd x nd strict lower L_tt, row- and column-major
+    // Coupling of the tail with the other nodes: forward, the tail rows'
+    // entries on the other nodes (CSR by tail position, columns are nodes);
+    // backward, the other rows' entries on the tail (rows bcrow, columns are
+    // tail positions).  The backward level lists hold only the other rows'
+    // entries on each other.
+    std::vector<int32_t> dcptr, dccol;
+    std::vector<double> dcval;
+    std::vector<int32_t> bcrow, bcptr, bccol;
+    std::vector<double> bcval;
+    // log2 of the lanes that share a row, per forward / backward level;
+    // kPegpWholeBlock: one row, the whole workgroup
+    std::vector<int32_t> flg, blg;
 };
+constexpr int kPegpSolveThreads = 1024;      // threads of the PEGP solve workgroup
+constexpr int kPegpWholeBlock = 7;
+constexpr int kPegpTailWidth = 4;
+constexpr int kPegpMinDense = 64;
+constexpr int kPegpMaxDense = 4096;
 int build_pegp(const HostPlan& plan, double mu, PegpPlan& out);
 
 int build_adjacency(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
