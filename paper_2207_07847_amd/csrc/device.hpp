@@ -1461,73 +1461,119 @@ __device__ inline double sparse_dot(const double* __restrict__ val,
     return acc;
 }
 
-// Rows [r0, r1) of one pass of a triangular solve on the LDS vector f: for
-// each row r, f[rows[r]] -= sum_k val[k] f[col[k]] over the row's entries
-// (no row of the pass reads another's node).  Groups of G lanes share a
-// row, rows dealt round-robin to the groups.
-template <int G>
-__device__ inline void pegp_rows_g(double* f, const int32_t* __restrict__ rows,
-                                   const int32_t* __restrict__ ptr,
-                                   const int32_t* __restrict__ col,
-                                   const double* __restrict__ val, int r0, int r1) {
-    constexpr int NG = kPegpThreads / G;
-    const int tid = threadIdx.x, q = tid & (G - 1);
-    for (int r = r0 + tid / G; r < r1; r += NG) {
-        double acc = sparse_dot<G>(val, col, ptr[r], ptr[r + 1], q, f);
+// The levels of a level-scheduled triangular solve on the LDS vector f, as
+// packed by the host: level l's descriptor deals the rows [r0, r0 + nr) of
+// the level list to groups of 2^g lanes over P passes of NT threads; thread
+// t's u-th entry of pass p is at base + (p U + u) NT + t.  Each row r gets
+// f[rows[r]] -= sum of its entries' values times f at their nodes (no row of
+// a level reads another's node).  The first kPegpPre entries of pass 0 of
+// the next level are loaded into registers while the current level runs:
+// its loads depend on nothing the level computes.  The descriptors are read
+// from an LDS copy when there is room for one (an LDS read does not wait for
+// the vector loads in flight, as a global one would).
+constexpr int kPegpPre = 8;
+
+struct PegpLvl {
+    int base, nt, u, np, g, r0, nr;
+};
+
+template <class DT>
+__device__ __forceinline__ PegpLvl pegp_desc(DT* desc, int l) {
+    const int4 d = desc[l];
+    return PegpLvl{d.x, d.y & 0xfff, d.y >> 16, d.z & 0xffff, (d.y >> 12) & 0xf, d.w, d.z >> 16};
+}
+
+struct PegpPreRow {
+    int node;
+    double a[kPegpPre];
+    int c[kPegpPre];
+};
+
+// Pass 0's first entries of thread t (threads past NT load thread NT-1's,
+// rounds past U load round U-1's: no load is masked, so none is waited for
+// on its own; those values are not used).
+__device__ __forceinline__ void pegp_fetch(PegpPreRow& s, const PegpLvl& D,
+                                           const int32_t* __restrict__ rows,
+                                           const double* __restrict__ val,
+                                           const int32_t* __restrict__ col, int t) {
+    const int tt = min(t, D.nt - 1);
+    s.node = rows[D.r0 + (tt >> D.g)];
 #pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (q == 0) f[rows[r]] -= acc;
+    for (int u = 0; u < kPegpPre; ++u) {
+        const int i = D.base + min(u, D.u - 1) * D.nt + tt;
+        s.a[u] = val[i];
+        s.c[u] = col[i];
     }
 }
 
-// One pass with 2^g lanes per row (g == kPegpWholeBlock: the single row
-// r0 takes the whole workgroup), then a barrier.
-__device__ __forceinline__ void pegp_rows(double* f, const int32_t* __restrict__ rows,
-                                 const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                 const double* __restrict__ val, int r0, int r1, int g,
-                                 double* red) {
-    switch (g) {
-    case 0: pegp_rows_g<1>(f, rows, ptr, col, val, r0, r1); break;
-    case 1: pegp_rows_g<2>(f, rows, ptr, col, val, r0, r1); break;
-    case 2: pegp_rows_g<4>(f, rows, ptr, col, val, r0, r1); break;
-    case 3: pegp_rows_g<8>(f, rows, ptr, col, val, r0, r1); break;
-    case 4: pegp_rows_g<16>(f, rows, ptr, col, val, r0, r1); break;
-    case 5: pegp_rows_g<32>(f, rows, ptr, col, val, r0, r1); break;
-    case 6: pegp_rows_g<64>(f, rows, ptr, col, val, r0, r1); break;
-    default: {
-        constexpr int NW = kPegpThreads / 64;
-        const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-        double acc = sparse_dot<kPegpThreads>(val, col, ptr[r0], ptr[r0 + 1], tid, f);
-        acc = wave_sum1(acc);
-        if (lane == 0) red[wid] = acc;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < NW; ++w) t += red[w];
-            f[rows[r0]] -= t;
+__device__ __forceinline__ double pegp_group_sum(double v, int g) {
+    for (int o = (1 << g) >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void pegp_level(double* f, const PegpLvl& D, const PegpPreRow& s,
+                                           const int32_t* __restrict__ rows,
+                                           const double* __restrict__ val,
+                                           const int32_t* __restrict__ col, int t) {
+    if (t < D.nt) {
+        const int q = t & ((1 << D.g) - 1);
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < kPegpPre; ++u) acc += (u < D.u ? s.a[u] : 0.0) * f[s.c[u]];
+        for (int u = kPegpPre; u < D.u; ++u) {
+            const int i = D.base + u * D.nt + t;
+            acc += val[i] * f[col[i]];
         }
-    }
+        acc = pegp_group_sum(acc, D.g);
+        if (q == 0) f[s.node] -= acc;
+        // further passes (levels wider than the workgroup's groups)
+        for (int p = 1; p < D.np; ++p) {
+            const int rr = p * (kPegpThreads >> D.g) + (t >> D.g);
+            if (rr < D.nr) {
+                double a2 = 0.0;
+                for (int u = 0; u < D.u; ++u) {
+                    const int i = D.base + (p * D.u + u) * D.nt + t;
+                    a2 += val[i] * f[col[i]];
+                }
+                a2 = pegp_group_sum(a2, D.g);
+                if (q == 0) f[rows[D.r0 + rr]] -= a2;
+            }
+        }
     }
     __syncthreads();
 }
 
-// The levels of a level-scheduled triangular solve, one pass each; the next
-// level's bounds are loaded while the current one runs.
-__device__ __forceinline__ void pegp_levels(double* f, const int32_t* __restrict__ lev,
-                                   const int32_t* __restrict__ lg,
-                                   const int32_t* __restrict__ rows,
-                                   const int32_t* __restrict__ ptr,
-                                   const int32_t* __restrict__ col,
-                                   const double* __restrict__ val, int nl, double* red) {
+// The descriptor table copied to LDS at `lds` (16-byte aligned, after the
+// vector); the caller's first barrier orders the copy before its reads.
+__device__ __forceinline__ void pegp_desc_copy(const int32_t* __restrict__ g, int nl, int4* lds) {
+    const int4* src = reinterpret_cast<const int4*>(g);
+    for (int l = threadIdx.x; l < nl; l += kPegpThreads) lds[l] = src[l];
+}
+
+// (DT: const int4 in LDS, or in global memory when the table does not fit;
+// the pointer's address space is known, so that LDS reads stay LDS reads)
+template <class DT>
+__device__ __forceinline__ void pegp_levels(double* f, DT* desc,
+                                            const int32_t* __restrict__ rows,
+                                            const double* __restrict__ val,
+                                            const int32_t* __restrict__ col, int nl) {
     if (nl <= 0) return;
-    int r0 = lev[0], r1 = lev[1], g = lg[0];
-    for (int l = 0; l < nl; ++l) {
-        const int ln = min(l + 1, nl - 1);
-        const int r2 = lev[ln + 1], g2 = lg[ln];
-        pegp_rows(f, rows, ptr, col, val, r0, r1, g, red);
-        r0 = r1;
-        r1 = r2;
-        g = g2;
+    const int t = threadIdx.x;
+    // two buffers taken in turn (no copy from one to the other, which would
+    // wait for the loads in flight); the last level fetches itself again
+    // rather than branch
+    PegpLvl DA = pegp_desc(desc, 0), DB;
+    PegpPreRow A, B;
+    pegp_fetch(A, DA, rows, val, col, t);
+    for (int l = 0;;) {
+        DB = pegp_desc(desc, min(l + 1, nl - 1));
+        pegp_fetch(B, DB, rows, val, col, t);
+        pegp_level(f, DA, A, rows, val, col, t);
+        if (++l == nl) break;
+        DA = pegp_desc(desc, min(l + 1, nl - 1));
+        pegp_fetch(A, DA, rows, val, col, t);
+        pegp_level(f, DB, B, rows, val, col, t);
+        if (++l == nl) break;
     }
 }
 
@@ -1553,9 +1599,10 @@ __global__ __launch_bounds__(kPegpThreads) void k_pegp_fwd(PegpDev P,
     if (S->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double* f = reinterpret_cast<double*>(smem);
-    __shared__ double red[kPegpThreads / 64];
     const int tid = threadIdx.x, nth = kPegpThreads;
     const int n0 = P.off[1] - P.off[0], T = P.nlev - 1;
+    int4* dl = reinterpret_cast<int4*>(smem + ((size_t)P.nt * sizeof(double) + 15) / 16 * 16);
+    if (P.desc_lds) pegp_desc_copy(P.fdesc, P.nflev, dl);
     for (int t = tid; t < n0; t += nth) f[t] = r[t];
     __syncthreads();
     for (int k = 0; k < T; ++k) {
@@ -1575,7 +1622,10 @@ __global__ __launch_bounds__(kPegpThreads) void k_pegp_fwd(PegpDev P,
     __syncthreads();
     if (tid == 0) f[P.ground] = 0.0;
     __syncthreads();
-    pegp_levels(f, P.flev, P.flg, P.frow, P.fptr, P.fcol, P.fval, P.nflev, red);
+    if (P.desc_lds)
+        pegp_levels(f, (const int4*)dl, P.frow, P.fpval, P.fpcol, P.nflev);
+    else
+        pegp_levels(f, reinterpret_cast<const int4*>(P.fdesc), P.frow, P.fpval, P.fpcol, P.nflev);
     for (int e = tid; e < P.nt; e += nth) P.fg[e] = f[e];
 }
 
@@ -1735,13 +1785,18 @@ __global__ __launch_bounds__(kPegpThreads) void k_pegp_bwd(PegpDev P,
     __shared__ double red[3 * (kPegpThreads / 64)];
     const int tid = threadIdx.x, nth = kPegpThreads;
     const int n0 = P.off[1] - P.off[0], T = P.nlev - 1;
+    int4* dl = reinterpret_cast<int4*>(smem + ((size_t)P.nt * sizeof(double) + 15) / 16 * 16);
+    if (P.desc_lds) pegp_desc_copy(P.bdesc, P.nblev, dl);
     for (int e = tid; e < P.nt; e += nth) f[e] = e != P.ground ? P.fg[e] / P.diag[e] : 0.0;
     __syncthreads();
     // the tail's values, and its contributions to the other rows
     for (int p = tid; p < P.nd; p += nth) f[P.drow[p]] = P.ty[p];
     for (int i = tid; i < P.nbc; i += nth) f[P.bcrow[i]] -= P.cpl[i];
     __syncthreads();
-    pegp_levels(f, P.blev, P.blg, P.brow, P.bptr, P.bcol, P.bval, P.nblev, red);
+    if (P.desc_lds)
+        pegp_levels(f, (const int4*)dl, P.brow, P.bpval, P.bpcol, P.nblev);
+    else
+        pegp_levels(f, reinterpret_cast<const int4*>(P.bdesc), P.brow, P.bpval, P.bpcol, P.nblev);
     for (int k = 1; k <= T; k += 2)
         for (int e = P.off[k] + tid; e < P.off[k + 1]; e += nth) f[e] = -f[e];
     __syncthreads();

@@ -200,17 +200,20 @@ struct Sell {
 constexpr int kPegpThreads = 1024;
 constexpr int kPegpMaxLevels = 64;
 constexpr int kPegpMaxNodes = 19456;     // expanded nodes held in LDS (152 KB)
+// dynamic LDS of the PEGP solve kernels: 160 KB less room for their static arrays
+constexpr size_t kPegpLdsBytes = 160 * 1024 - 1024;
 struct PegpDev {
     int32_t nt, nlev, ground, nflev, nblev;
+    int32_t desc_lds;                    // level descriptors copied to LDS (after the vector)
     int32_t off[kPegpMaxLevels + 1];     // level -> first expanded index
     const int32_t* cptr[kPegpMaxLevels]; // children ranges of level k+1 nodes
     const double* diag;
-    // level lists: level -> first row, log2 of the lanes per row, row ->
-    // node, the row's entries (CSR)
-    const int32_t *flev, *flg, *frow, *fptr, *fcol;
-    const double* fval;
-    const int32_t *blev, *blg, *brow, *bptr, *bcol;
-    const double* bval;
+    // level lists packed for the solve: per level a descriptor, row -> node,
+    // the padded entries (columns and values)
+    const int32_t *fdesc, *frow, *fpcol;
+    const double* fpval;
+    const int32_t *bdesc, *brow, *bpcol;
+    const double* bpval;
     // dense tail (nd rows, 0: none): tail position -> node, the strict lower
     // factor of the tail row-major (forward) and column-major (backward), the
     // forward coupling (CSR by tail position, columns are nodes), the

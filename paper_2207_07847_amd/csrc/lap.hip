@@ -892,19 +892,15 @@ void upload_pegp(lap_hierarchy* h, hipStream_t s) {
     for (int k = 0; k + 1 < d.nlev; ++k) d.cptr[k] = h->cptr[k];
     d.diag = h->upload(G.diag, s);
     d.nflev = (int32_t)G.flev.size() - 1;
-    d.flev = h->upload(G.flev, s);
-    d.flg = h->upload(G.flg, s);
+    d.fdesc = h->upload(G.fdesc, s);
     d.frow = h->upload(G.frow, s);
-    d.fptr = h->upload(G.fptr, s);
-    d.fcol = h->upload(G.fcol, s);
-    d.fval = h->upload(G.fval, s);
+    d.fpcol = h->upload(G.fpcol, s);
+    d.fpval = h->upload(G.fpval, s);
     d.nblev = (int32_t)G.blev.size() - 1;
-    d.blev = h->upload(G.blev, s);
-    d.blg = h->upload(G.blg, s);
+    d.bdesc = h->upload(G.bdesc, s);
     d.brow = h->upload(G.brow, s);
-    d.bptr = h->upload(G.bptr, s);
-    d.bcol = h->upload(G.bcol, s);
-    d.bval = h->upload(G.bval, s);
+    d.bpcol = h->upload(G.bpcol, s);
+    d.bpval = h->upload(G.bpval, s);
     d.nd = G.nd;
     d.nbc = (int32_t)G.bcrow.size();
     d.drow = h->upload(G.drow, s);
@@ -920,7 +916,12 @@ void upload_pegp(lap_hierarchy* h, hipStream_t s) {
     d.fg = h->dalloc<double>(G.nt);
     d.ty = h->dalloc<double>(G.nd);
     d.cpl = h->dalloc<double>(G.bcrow.size());
-    h->pegp_lds = (size_t)G.nt * sizeof(double);
+    // the vector, then (16-byte aligned) the larger level descriptor table
+    // when it fits beside it
+    const size_t vec = ((size_t)G.nt * sizeof(double) + 15) / 16 * 16;
+    const size_t tab = (size_t)std::max(d.nflev, d.nblev) * kPegpDescInts * sizeof(int32_t);
+    d.desc_lds = vec + tab <= kPegpLdsBytes;
+    h->pegp_lds = d.desc_lds ? vec + tab : (size_t)G.nt * sizeof(double);
     HIPCHK(hipFuncSetAttribute((const void*)k_pegp_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)h->pegp_lds));
     HIPCHK(hipFuncSetAttribute((const void*)k_pegp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -529,11 +529,11 @@ void build_sell(const Adjacency& g, HostPlan& plan) {
 
 // ------------------------------------------------------------------ PEGP
 
-// How many lanes share a row in the rows [r0, r1) of a PEGP solve pass
-// (log2; kPegpWholeBlock: the single row takes the whole workgroup).  Rows
-// are dealt round-robin to groups of G lanes; a lane loads eight entries a
-// round, so a group spends max(1, ceil(len / 8G)) rounds on a row plus a
-// little per reduction step.  The pick minimises the busiest group's time.
+// How many lanes share a row in the rows [r0, r1) of a PEGP solve level
+// (log2).  Rows are dealt round-robin to groups of G lanes; a lane loads
+// eight entries a round, so a group spends max(1, ceil(len / 8G)) rounds on
+// a row plus a little per reduction step.  The pick minimises the busiest
+// group's time.
 static int32_t pegp_lanes(const std::vector<int32_t>& ptr, int32_t r0, int32_t r1) {
     int32_t best = 0;
     double best_cost = 1e300;
@@ -553,12 +553,44 @@ static int32_t pegp_lanes(const std::vector<int32_t>& ptr, int32_t r0, int32_t r
             best = g;
         }
     }
-    if (r1 - r0 == 1) {
-        const int64_t len = ptr[r0 + 1] - ptr[r0];
-        const double whole = (double)((len + 8 * kPegpSolveThreads - 1) / (8 * kPegpSolveThreads)) + 1.0;
-        if (whole < best_cost) best = kPegpWholeBlock;
-    }
     return best;
+}
+
+// The level lists (lev, ptr, col, val) with lanes per level lg packed as
+// the descriptors and padded entry arrays the solve reads.
+static bool pegp_pack(const std::vector<int32_t>& lev, const std::vector<int32_t>& lg,
+                      const std::vector<int32_t>& ptr, const std::vector<int32_t>& col,
+                      const std::vector<double>& val, std::vector<int32_t>& desc,
+                      std::vector<double>& pval, std::vector<int32_t>& pcol) {
+    desc.clear();
+    pval.clear();
+    pcol.clear();
+    for (size_t l = 0; l + 1 < lev.size(); ++l) {
+        const int32_t r0 = lev[l], r1 = lev[l + 1], nr = r1 - r0, g = lg[l];
+        const int32_t G = 1 << g, NG = kPegpSolveThreads / G;
+        const int32_t np = (nr + NG - 1) / NG, nt = np > 1 ? kPegpSolveThreads : nr * G;
+        int32_t maxlen = 0;
+        for (int32_t r = r0; r < r1; ++r) maxlen = std::max(maxlen, ptr[r + 1] - ptr[r]);
+        const int32_t U = std::max(1, (maxlen + G - 1) / G);
+        if (U >= 1 << 15 || np >= 1 << 16 || nr >= 1 << 15 ||
+            pval.size() + (size_t)np * U * nt > (size_t)INT32_MAX)
+            return false;
+        const int32_t base = (int32_t)pval.size();
+        pval.resize(base + (size_t)np * U * nt, 0.0);
+        pcol.resize(pval.size(), 0);
+        for (int32_t rr = 0; rr < nr; ++rr) {
+            const int32_t p = rr / NG, grp = rr % NG, r = r0 + rr;
+            for (int32_t e = 0; e < ptr[r + 1] - ptr[r]; ++e) {
+                const int32_t t = grp * G + e % G, u = e / G;
+                const size_t i = (size_t)base + ((size_t)p * U + u) * nt + t;
+                pval[i] = val[ptr[r] + e];
+                pcol[i] = col[ptr[r] + e];
+            }
+        }
+        const int32_t d[kPegpDescInts] = {base, nt | g << 12 | U << 16, np | nr << 16, r0};
+        desc.insert(desc.end(), d, d + kPegpDescInts);
+    }
+    return true;
 }
 
 int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
@@ -833,6 +865,11 @@ int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
     out.blg.resize(out.blev.size() - 1);
     for (size_t l = 0; l + 1 < out.blev.size(); ++l)
         out.blg[l] = pegp_lanes(out.bptr, out.blev[l], out.blev[l + 1]);
+    if (!pegp_pack(out.flev, out.flg, out.fptr, out.fcol, out.fval, out.fdesc, out.fpval,
+                   out.fpcol) ||
+        !pegp_pack(out.blev, out.blg, out.bptr, out.bcol, out.bval, out.bdesc, out.bpval,
+                   out.bpcol))
+        return kUnsupported;
     return kOk;
 }
 

@@ -118,12 +118,20 @@ struct PegpPlan {
     std::vector<double> dcval;
     std::vector<int32_t> bcrow, bcptr, bccol;
     std::vector<double> bcval;
-    // log2 of the lanes that share a row, per forward / backward level;
-    // kPegpWholeBlock: one row, the whole workgroup
+    // log2 of the lanes that share a row, per forward / backward level
     std::vector<int32_t> flg, blg;
+    // The levels packed for the solve: per level a descriptor of
+    // kPegpDescInts ints {base, NT | g << 12 | U << 16, P | nr << 16, r0}:
+    // 2^g lanes per row, the rows [r0, r0 + nr) of the level list dealt to P
+    // passes of NT threads, U entries per thread and pass; the entry of pass
+    // p, round u, thread t at base + (p U + u) NT + t (padding: value 0 on
+    // node 0).  A thread's entries are found from the descriptor alone, so a
+    // level's loads can be issued before the previous level is done.
+    std::vector<int32_t> fdesc, bdesc, fpcol, bpcol;
+    std::vector<double> fpval, bpval;
 };
 constexpr int kPegpSolveThreads = 1024;      // threads of the PEGP solve workgroup
-constexpr int kPegpWholeBlock = 7;
+constexpr int kPegpDescInts = 4;
 constexpr int kPegpTailWidth = 4;
 constexpr int kPegpMinDense = 64;
 constexpr int kPegpMaxDense = 4096;
