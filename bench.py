@@ -336,6 +336,67 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def select_mu(args):
+    """mu chosen by the smallest estimated kappa of M L (lap_select_mu), then
+    one full solve at every candidate: the choice against the fastest."""
+    import numpy as np
+    import torch
+
+    import paper_2207_07847_amd as lap
+    torch.cuda.set_device(0)
+    wl = workload(args.workload, args.scale)
+    n = wl["n"]
+    sh = torch.cuda.current_stream().cuda_stream
+    mus = [float(x) for x in args.mu_candidates.split(",")]
+    pc = lap.LAP_PREC_PEGP if wl["precond"] == "pegp" else lap.LAP_PREC_MSP
+    params = lap.lap_default_params(max_iter=args.max_iter, precond=pc)
+    bd = torch.tensor(np.ascontiguousarray(wl["b"]), dtype=torch.float64, device="cuda")
+    xd = torch.empty_like(bd)
+    t0 = time.time()
+    st, best, kap = lap.lap_select_mu(n, wl["u"], wl["v"], wl["w"], mus, bd.data_ptr(),
+                                      args.select_steps, params, sh)
+    torch.cuda.synchronize()
+    sel_s = time.time() - t0
+    if st != 0:
+        raise SystemExit(f"lap_select_mu: {lap.lap_status_str(st)}")
+    log(f"selection {sel_s:.2f}s: mu {mus[best]}; kappa estimates "
+        + ", ".join(f"{m}: {k:.1f}" for m, k in zip(mus, kap)))
+    runs = []
+    for m in mus:
+        h = lap.lap_setup(n, wl["u"], wl["v"], wl["w"],
+                          lap.lap_default_params(mu=m, max_iter=args.max_iter, precond=pc), sh)
+        lap.lap_solve(h, bd.data_ptr(), xd.data_ptr(), n, wl["tol"], stream=sh)  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, inf = lap.lap_solve(h, bd.data_ptr(), xd.data_ptr(), n, wl["tol"], stream=sh)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        lap.lap_free(h)
+        runs.append(dict(mu=m, status=lap.lap_status_str(st), iterations=inf[0]["iterations"],
+                         seconds=dt, relres_true=inf[0]["relres_true"]))
+        log(f"mu {m}: {inf[0]['iterations']} iterations, {dt:.3f}s, "
+            f"{lap.lap_status_str(st)}")
+    ok = [r for r in runs if r["status"] == lap.lap_status_str(0)]
+    fastest = min(ok, key=lambda r: r["seconds"]) if ok else None
+    chosen = runs[best]
+    ref = [r for r in runs if abs(r["mu"] - wl["mu"]) < 1e-12]
+    out = {
+        "metric": "solves/s at the mu chosen by estimated kappa (lap_select_mu)",
+        "value": 1.0 / chosen["seconds"] if chosen["status"] == lap.lap_status_str(0) else 0.0,
+        "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload].replace(f"mu={wl['mu']:g}", "mu chosen"),
+                   "candidates": mus, "estimate_steps": args.select_steps},
+        "chosen_mu": mus[best], "selection_s": sel_s,
+        "kappa_estimates": [float(k) for k in kap],
+        "fastest_mu": fastest["mu"] if fastest else None,
+        "per_mu": runs,
+        "vs_default_mu": (ref[0]["seconds"] / chosen["seconds"]) if ref and ref[0]["status"] ==
+        lap.lap_status_str(0) else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +430,12 @@ def main():
                     help="stop waiting after this long; unfinished requests are reported")
     ap.add_argument("--serve-compare", type=int, default=20,
                     help="requests whose columns are also timed as single FP64 solves")
+    ap.add_argument("--select-mu", action="store_true",
+                    help="choose mu by the smallest estimated kappa (lap_select_mu) and "
+                         "solve at every candidate to check the choice")
+    ap.add_argument("--mu-candidates", default="0.7,0.8,0.9,0.95,0.98")
+    ap.add_argument("--select-steps", type=int, default=40,
+                    help="PCG steps of each candidate's spectrum estimate")
     ap.add_argument("--max-iter", type=int, default=200000,
                     help="cap per solve (profiling runs); a capped solve is not a valid step")
     args = ap.parse_args()
@@ -379,6 +446,9 @@ def main():
 
     if args.serve:
         serve(args)
+        return
+    if args.select_mu:
+        select_mu(args)
         return
 
     import numpy as np
@@ -454,7 +524,7 @@ def main():
              (lap.LAP_KERNEL_DOWN0, "down0"), (lap.LAP_KERNEL_PRECOND, "update_precond"),
              (lap.LAP_KERNEL_ITER, "iteration")]
     if wl["precond"] == "pegp":
-        # the PEGP solve is one kernel: no level parts to time
+        # the PEGP application has no MSP level parts to time
         parts = [parts[0], parts[-1]]
     for kid, name in parts:
         ms, by = lap.lap_profile_kernel(h, kid, args.profile_reps, sh)

@@ -217,6 +217,39 @@ enum { LAP_KERNEL_SPMV = 0, LAP_KERNEL_UPDATE = 1, LAP_KERNEL_DOWN0 = 2,
 lap_status lap_profile_kernel(lap_hierarchy *h, int32_t kernel, int32_t reps,
                               void *stream, double *avg_ms, double *alg_bytes);
 
+/* Extreme eigenvalues of the preconditioned operator M L_G on range(L_G),
+ * whose ratio kappa governs PCG's convergence (the theorem of Sec. 3.2
+ * bounds it by 1/(1 - rho) when mu is small enough; how to choose mu is
+ * left open after it).  Estimated from PCG's own coefficients: up to `steps`
+ * FP64 PCG iterations on b with the hierarchy's preconditioner (MSP or
+ * PEGP), stopping early at ||r|| <= 1e-10 ||b^||; the step lengths alpha_j
+ * and direction updates beta_j give the Lanczos tridiagonal
+ *   T_jj = 1/alpha_j + beta_j/alpha_{j-1},  T_j,j+1 = sqrt(beta_{j+1})/alpha_j
+ * (Saad, Iterative Methods for Sparse Linear Systems, Sec. 6.7.3), whose
+ * extreme eigenvalues (bisection on Sturm counts) approach the operator's
+ * from inside.  b: device array of n values, original order (any b with a
+ * component on every eigenvector; a random one).  *lmin, *lmax, *taken
+ * (steps taken; may be NULL): host outputs.  Uses the solve workspace.
+ * Errors: LAP_EINVAL (NULL, steps < 1, non-finite b), LAP_EUNSUPPORTED
+ * (host-only, or no preconditioner), LAP_EBREAKDOWN (no step taken),
+ * LAP_EDEVICE. */
+lap_status lap_estimate_spectrum(lap_hierarchy *h, const double *b, int32_t steps,
+                                 double *lmin, double *lmax, int32_t *taken,
+                                 void *stream);
+
+/* The mu among mus[0..nmu) with the smallest estimated kappa: for each
+ * candidate, a hierarchy set up from g and p with p->mu replaced, the
+ * estimate of lap_estimate_spectrum with `steps` steps on b, and the
+ * hierarchy freed.  PCG's step count grows as sqrt(kappa), and an MSP
+ * application costs the same at every mu.  kappa: host array of nmu
+ * entries (may be NULL; HUGE_VAL for a candidate whose setup or estimate
+ * failed); *best: the chosen index.  Errors: LAP_EINVAL (NULL, nmu < 1,
+ * steps < 1), else the first failing candidate's status when none
+ * succeeded. */
+lap_status lap_select_mu(const lap_graph *g, const lap_params *p, const double *mus,
+                         int32_t nmu, const double *b, int32_t steps, double *kappa,
+                         int32_t *best, void *stream);
+
 /* Sizes and memory of a hierarchy.  Errors: LAP_EINVAL on NULL. */
 lap_status lap_hierarchy_info(const lap_hierarchy *h, lap_hierarchy_desc *d);
 

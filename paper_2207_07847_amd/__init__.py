@@ -87,6 +87,10 @@ def _load():
     L.lap_export_graph.argtypes = [vp, C.c_int32, vp, vp, vp]
     L.lap_profile_kernel.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
+    L.lap_estimate_spectrum.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
+    L.lap_select_mu.argtypes = [C.POINTER(lap_graph), C.POINTER(lap_params), vp, C.c_int32, vp,
+                                C.c_int32, vp, C.POINTER(C.c_int32), vp]
     L.lap_free.argtypes = [vp]
     L.lap_free.restype = None
     L.lap_server_create.argtypes = [C.c_int64, C.POINTER(vp)]
@@ -105,7 +109,7 @@ def _load():
     for f in ("lap_default_params", "lap_setup", "lap_solve", "lap_set_precision",
               "lap_apply_laplacian",
               "lap_apply_precond", "lap_hierarchy_info", "lap_export_level", "lap_export_graph",
-              "lap_profile_kernel"):
+              "lap_profile_kernel", "lap_estimate_spectrum", "lap_select_mu"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -136,14 +140,20 @@ def lap_default_params(**overrides) -> lap_params:
     return p
 
 
-def lap_setup(n, u, v, w, params: lap_params | None = None, stream=0):
-    """Host setup + upload.  u, v, w: host arrays (copied during the call).
-    Returns an opaque handle (int); raises LapError on a non-OK status."""
+def _graph(n, u, v, w):
+    """(lap_graph, the arrays it points into, which must outlive it)."""
     u = np.ascontiguousarray(u, dtype=np.int64)
     v = np.ascontiguousarray(v, dtype=np.int64)
     w = np.ascontiguousarray(w, dtype=np.float64)
     g = lap_graph(int(n), len(u), u.ctypes.data_as(C.POINTER(C.c_int64)),
                   v.ctypes.data_as(C.POINTER(C.c_int64)), w.ctypes.data_as(C.POINTER(C.c_double)))
+    return g, (u, v, w)
+
+
+def lap_setup(n, u, v, w, params: lap_params | None = None, stream=0):
+    """Host setup + upload.  u, v, w: host arrays (copied during the call).
+    Returns an opaque handle (int); raises LapError on a non-OK status."""
+    g, keep = _graph(n, u, v, w)
     p = params if params is not None else lap_default_params()
     h = C.c_void_p()
     st = _lib.lap_setup(C.byref(g), C.byref(p), C.c_void_p(stream or 0), C.byref(h))
@@ -220,6 +230,27 @@ def lap_profile_kernel(h, kernel: int, reps: int, stream=0):
     if st != LAP_OK:
         raise LapError(st, "lap_profile_kernel")
     return ms.value, by.value
+
+
+def lap_estimate_spectrum(h, b_ptr: int, steps: int, stream=0):
+    """(status, lambda_min, lambda_max, steps taken) of M L on range(L)."""
+    lo, hi, k = C.c_double(), C.c_double(), C.c_int32()
+    st = _lib.lap_estimate_spectrum(C.c_void_p(h), C.c_void_p(b_ptr), int(steps), C.byref(lo),
+                                    C.byref(hi), C.byref(k), C.c_void_p(stream or 0))
+    return st, lo.value, hi.value, k.value
+
+
+def lap_select_mu(n, u, v, w, mus, b_ptr: int, steps: int, params: lap_params | None = None,
+                  stream=0):
+    """(status, best index, estimated kappa per candidate)."""
+    g, keep = _graph(n, u, v, w)
+    p = params if params is not None else lap_default_params()
+    m = np.ascontiguousarray(mus, dtype=np.float64)
+    kap = np.zeros(len(m))
+    best = C.c_int32(-1)
+    st = _lib.lap_select_mu(C.byref(g), C.byref(p), m.ctypes.data, len(m), C.c_void_p(b_ptr),
+                            int(steps), kap.ctypes.data, C.byref(best), C.c_void_p(stream or 0))
+    return st, best.value, kap
 
 
 def lap_free(h) -> None:

@@ -1363,6 +1363,87 @@ void begin_solve(lap_hierarchy* h, const double* b, bool outer, hipStream_t s) {
     HIPCHK(hipGetLastError());
 }
 
+// ------------------------------------------------------------ spectrum
+//
+// The extreme eigenvalues of M L_G on range(L_G), from PCG's own
+// coefficients: k PCG steps with step lengths alpha_j and direction updates
+// beta_j (p_j = z_j + beta_j p_{j-1}) are k steps of Lanczos on M L_G, with
+// the tridiagonal T_k: T_jj = 1/alpha_j + beta_j/alpha_{j-1} (beta_0 = 0),
+// T_j,j+1 = sqrt(beta_{j+1})/alpha_j (Saad, Iterative Methods for Sparse
+// Linear Systems, Sec. 6.7.3).  The iterations run one at a time on the
+// FP64 engine, the scalars read back after each.
+
+constexpr double kSpectrumStop = 1e-10;  // relative residual that ends the run
+
+// Number of eigenvalues of the symmetric tridiagonal (d, e) below x: the
+// negative pivots of the LDL^T factorisation of T - x I (Sturm count).
+static int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+    int c = 0;
+    double q = 1.0;
+    for (size_t i = 0; i < d.size(); ++i) {
+        q = d[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++c;
+    }
+    return c;
+}
+
+// The idx-th smallest eigenvalue of (d, e) by bisection inside the
+// Gershgorin interval, to a relative width of 1e-15.
+static double tridiag_eig(const std::vector<double>& d, const std::vector<double>& e, int idx) {
+    const size_t k = d.size();
+    double lo = HUGE_VAL, hi = -HUGE_VAL;
+    for (size_t i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi))) || mid == lo || mid == hi)
+            break;
+        if (sturm_count(d, e, mid) > idx) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// PCG from x = 0 on b (device, original order) to `steps` steps or the
+// relative residual kSpectrumStop; alpha_0.. and beta_1.. of the steps
+// taken (a breakdown step is not taken).  Returns the final scalars.
+static Scal pcg_coefficients(lap_hierarchy* h, const double* b, int steps,
+                             std::vector<double>& alpha, std::vector<double>& beta,
+                             hipStream_t s) {
+    Engine<double>& e = h->e64;
+    const int n = (int)h->n;
+    begin_solve(h, b, false, s);
+    std::memset(h->stage, 0, sizeof(Scal));
+    h->stage->tol2 = kSpectrumStop * kSpectrumStop;
+    h->stage->maxit = steps;
+    HIPCHK(hipMemcpyAsync(h->S, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sum, dim3(nblk(n)), dim3(kBlock), 0, s, n, (const double*)h->bh,
+                       h->part);
+    finish<kFinBsum>(h, s, h->S, nblk(n));
+    hipLaunchKernelGGL(k_init<double>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->t2s,
+                       (const double*)h->bh, e.r, e.x, e.p[0], e.p[1], (const Scal*)h->S,
+                       h->part);
+    finish<kFinBn2>(h, s, h->S, nblk(n));
+    enqueue_precond(h, e, s, 0);
+    HIPCHK(hipGetLastError());
+    Scal R = read_scal(h, h->S, s);
+    for (int i = 0; i < steps && R.done == 0; ++i) {
+        enqueue_iteration(h, e, s, i & 1);
+        HIPCHK(hipGetLastError());
+        R = read_scal(h, h->S, s);
+        if (R.alpha > 0.0 && std::isfinite(R.alpha)) alpha.push_back(R.alpha);
+        else break;
+        // a run that stops (converged, or at `steps`) forms no new direction
+        if (R.done != 0) break;
+        beta.push_back(R.beta);
+    }
+    return R;
+}
+
 // ------------------------------------------------------------ FGMRES
 //
 // FGMRES on the expanded system L_G~ x~ = P(mu)^T b^ (Sec. 2.2; the solver
@@ -2771,6 +2852,59 @@ void lap_server_destroy(lap_server* S) {
     }
     for (SrvRequest* r : S->outbox) delete r;
     delete S;
+}
+
+lap_status lap_estimate_spectrum(lap_hierarchy* h, const double* b, int32_t steps, double* lmin,
+                                 double* lmax, int32_t* taken, void* stream) {
+    if (!h || !b || !lmin || !lmax || steps < 1) return LAP_EINVAL;
+    if (h->host_only || (!h->with_msp && !h->pegp)) return LAP_EUNSUPPORTED;
+    try {
+        std::vector<double> alpha, beta;
+        const Scal R = pcg_coefficients(h, b, steps, alpha, beta, (hipStream_t)stream);
+        if (R.done == 4) return LAP_EINVAL;
+        if (taken) *taken = (int32_t)alpha.size();
+        if (alpha.empty()) return LAP_EBREAKDOWN;
+        const size_t k = alpha.size();
+        std::vector<double> d(k), e(k > 0 ? k - 1 : 0);
+        for (size_t j = 0; j < k; ++j) {
+            d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+            if (j + 1 < k) e[j] = std::sqrt(beta[j]) / alpha[j];
+        }
+        *lmin = tridiag_eig(d, e, 0);
+        *lmax = tridiag_eig(d, e, (int)k - 1);
+    } catch (const HipErr&) {
+        return LAP_EDEVICE;
+    }
+    return LAP_OK;
+}
+
+lap_status lap_select_mu(const lap_graph* g, const lap_params* p, const double* mus, int32_t nmu,
+                         const double* b, int32_t steps, double* kappa, int32_t* best,
+                         void* stream) {
+    if (!g || !p || !mus || !b || !best || nmu < 1 || steps < 1) return LAP_EINVAL;
+    lap_status first_err = LAP_OK;
+    double best_k = HUGE_VAL;
+    *best = -1;
+    for (int32_t i = 0; i < nmu; ++i) {
+        lap_params q = *p;
+        q.mu = mus[i];
+        lap_hierarchy* h = nullptr;
+        double k = HUGE_VAL;
+        lap_status st = lap_setup(g, &q, stream, &h);
+        if (st == LAP_OK) {
+            double lo = 0.0, hi = 0.0;
+            st = lap_estimate_spectrum(h, b, steps, &lo, &hi, nullptr, stream);
+            if (st == LAP_OK && lo > 0.0) k = hi / lo;
+            lap_free(h);
+        }
+        if (st != LAP_OK && first_err == LAP_OK) first_err = st;
+        if (kappa) kappa[i] = k;
+        if (k < best_k) {
+            best_k = k;
+            *best = i;
+        }
+    }
+    return *best >= 0 ? LAP_OK : first_err;
 }
 
 void lap_free(lap_hierarchy* h) { delete h; }

@@ -74,6 +74,12 @@ class GpuLap:
         assert st == 0
         return zd.cpu().numpy()
 
+    def estimate_spectrum(self, b, steps):
+        bd = self.dev(b)
+        out = self.lap.lap_estimate_spectrum(self.h, bd.data_ptr(), steps, self.stream())
+        self.torch.cuda.synchronize()
+        return out
+
     def close(self):
         if self.h:
             self.lap.lap_free(self.h)
