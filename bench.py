@@ -336,6 +336,39 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def auto_mu(lap, wl, args, bd, xd, sh):
+    """The same workload with mu chosen by lap_select_mu: the choice, its
+    cost, and one solve at the chosen mu (after an untimed one)."""
+    import torch
+    n = wl["n"]
+    mus = [float(x) for x in args.auto_mu_candidates.split(",")]
+    t0 = time.time()
+    st, best, kap = lap.lap_select_mu(n, wl["u"], wl["v"], wl["w"], mus, bd.data_ptr(),
+                                      args.select_steps,
+                                      lap.lap_default_params(max_iter=args.max_iter), sh)
+    torch.cuda.synchronize()
+    sel_s = time.time() - t0
+    if st != 0:
+        return {"status": lap.lap_status_str(st)}
+    mu = mus[best]
+    h = lap.lap_setup(n, wl["u"], wl["v"], wl["w"],
+                      lap.lap_default_params(mu=mu, max_iter=args.max_iter), sh)
+    lap.lap_solve(h, bd.data_ptr(), xd.data_ptr(), n, wl["tol"], stream=sh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, inf = lap.lap_solve(h, bd.data_ptr(), xd.data_ptr(), n, wl["tol"], stream=sh)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    lap.lap_free(h)
+    log(f"auto mu: {mu} chosen in {sel_s:.2f}s; {inf[0]['iterations']} iterations, {dt:.3f}s")
+    return {"mu": mu, "candidates": mus, "kappa_estimates": [float(k) for k in kap],
+            "selection_s": sel_s, "solves_per_s": 1.0 / dt if st == 0 else 0.0,
+            "iterations": inf[0]["iterations"], "relres_true": inf[0]["relres_true"],
+            "status": lap.lap_status_str(st),
+            "what": "the same solve with mu chosen by the smallest estimated kappa of M L "
+                    "(lap_select_mu, Lanczos from PCG coefficients); value above keeps mu = 0.8"}
+
+
 def select_mu(args):
     """mu chosen by the smallest estimated kappa of M L (lap_select_mu), then
     one full solve at every candidate: the choice against the fastest."""
@@ -434,6 +467,10 @@ def main():
                     help="choose mu by the smallest estimated kappa (lap_select_mu) and "
                          "solve at every candidate to check the choice")
     ap.add_argument("--mu-candidates", default="0.7,0.8,0.9,0.95,0.98")
+    ap.add_argument("--no-auto-mu", action="store_true",
+                    help="skip the auto_mu field (the same solve at the mu lap_select_mu "
+                         "chooses)")
+    ap.add_argument("--auto-mu-candidates", default="0.8,0.9,0.95,0.98,0.99,0.995")
     ap.add_argument("--select-steps", type=int, default=40,
                     help="PCG steps of each candidate's spectrum estimate")
     ap.add_argument("--max-iter", type=int, default=200000,
@@ -601,6 +638,9 @@ def main():
         }
         line["speedup_vs_fp64"] = (base["elapsed"] / res["elapsed"]) if args.nrhs == 1 else \
             (base["elapsed"] / (res["elapsed"] / args.steps))
+    if (not args.no_auto_mu and wl["precond"] == "msp" and args.nrhs == 1 and
+            args.precision == "fp64" and args.solver == "pcg" and not capped):
+        line["auto_mu"] = auto_mu(lap, wl, args, bd, xd, sh)
     if not args.no_cpu:
         if args.workload == "grid3d_128" and args.scale == 1.0 and args.solver == "pcg":
             log("cpu baseline (oracle) ...")
