@@ -467,6 +467,8 @@ def main():
                     help="choose mu by the smallest estimated kappa (lap_select_mu) and "
                          "solve at every candidate to check the choice")
     ap.add_argument("--mu-candidates", default="0.7,0.8,0.9,0.95,0.98")
+    ap.add_argument("--device-setup", action="store_true",
+                    help="build the hierarchy's graphs on the device (LAP_FLAG_DEVICE_SETUP)")
     ap.add_argument("--no-auto-mu", action="store_true",
                     help="skip the auto_mu field (the same solve at the mu lap_select_mu "
                          "chooses)")
@@ -503,6 +505,8 @@ def main():
     prec = lap.LAP_FP64 if args.precision == "fp64" else lap.LAP_MIXED_FP32_FP64
     t0 = time.time()
     flags = lap.LAP_FLAG_MULTI_RHS if args.nrhs > 1 else 0
+    if args.device_setup:
+        flags |= lap.LAP_FLAG_DEVICE_SETUP
     if args.solver == "fgmres":
         flags |= lap.LAP_FLAG_FGMRES
     pc = lap.LAP_PREC_PEGP if wl["precond"] == "pegp" else lap.LAP_PREC_MSP
@@ -638,6 +642,26 @@ def main():
         }
         line["speedup_vs_fp64"] = (base["elapsed"] / res["elapsed"]) if args.nrhs == 1 else \
             (base["elapsed"] / (res["elapsed"] / args.steps))
+    if not capped:
+        # the same set-up with the graphs built on the device (bit-identical
+        # hierarchy), timed beside the host build above
+        t0 = time.time()
+        h2 = lap.lap_setup(n, wl["u"], wl["v"], wl["w"],
+                           lap.lap_default_params(mu=wl["mu"], max_iter=args.max_iter,
+                                                  precision=prec,
+                                                  flags=flags ^ lap.LAP_FLAG_DEVICE_SETUP,
+                                                  precond=pc), sh)
+        torch.cuda.synchronize()
+        other_s = time.time() - t0
+        lap.lap_free(h2)
+        line["setup_graphs"] = {
+            "host_s": other_s if args.device_setup else setup_s,
+            "device_s": setup_s if args.device_setup else other_s,
+            "what": "lap_setup with the adjacency and coarse graphs built on the host, and on "
+                    "the device (LAP_FLAG_DEVICE_SETUP); the rest of the set-up on the host "
+                    "in both"}
+        log(f"setup: host graphs {line['setup_graphs']['host_s']:.2f}s, device graphs "
+            f"{line['setup_graphs']['device_s']:.2f}s")
     if (not args.no_auto_mu and wl["precond"] == "msp" and args.nrhs == 1 and
             args.precision == "fp64" and args.solver == "pcg" and not capped):
         line["auto_mu"] = auto_mu(lap, wl, args, bd, xd, sh)

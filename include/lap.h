@@ -62,6 +62,16 @@ typedef enum {
 #define LAP_FLAG_MULTI_RHS 2u  /* lap_setup also builds the block solve: calls
                                   with nrhs > 1 advance up to 64 columns
                                   together (see lap_solve) */
+#define LAP_FLAG_DEVICE_SETUP 8u /* lap_setup builds the graphs of the
+                                  hierarchy on the device: the symmetric
+                                  adjacency of the edge list and each coarse
+                                  graph P^T L P (Sec. 2.2), by stable radix
+                                  sorts of (row, column) keys with each run's
+                                  weights summed in the host's order, so the
+                                  hierarchy is bit-identical to the host
+                                  build.  The matching and the rest of the
+                                  setup stay on the host.  Ignored with
+                                  LAP_FLAG_HOST_ONLY. */
 #define LAP_FLAG_FGMRES 4u     /* lap_solve runs FGMRES on the expanded system
                                   L_G~ x~ = P(mu)^T b^ (Sec. 2.2, the solver of
                                   Sec. 4) instead of PCG: right-preconditioned

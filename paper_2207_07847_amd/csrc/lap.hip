@@ -4,6 +4,7 @@
 // The kernels are in device.hpp.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <atomic>
@@ -52,6 +53,8 @@ void record_error(const char* what, hipError_t e, int line) {
             throw HipErr();                               \
         }                                                 \
     } while (0)
+
+#include "devsetup.hpp"
 
 int env_int(const char* name, int dflt) {
     const char* v = std::getenv(name);
@@ -2537,8 +2540,18 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
     try {
         // only the MSP solves the top level on chip (a dense pseudo-inverse)
         const bool any_top = h->host_only || p->precond != LAP_PREC_MSP;
+        const bool dev_setup = (p->flags & LAP_FLAG_DEVICE_SETUP) && !h->host_only;
+        if (dev_setup) {
+            int ndev = 0;
+            if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+                std::snprintf(g_last_error, sizeof(g_last_error), "no HIP device visible");
+                delete h;
+                return LAP_EDEVICE;
+            }
+        }
+        DeviceGraphBuilder dgb((hipStream_t)stream);
         const int rc = build_plan(g->n, g->m, g->u, g->v, g->w, p->mu, p->max_levels, p->n_top,
-                                  p->mwm_seed, any_top, h->plan);
+                                  p->mwm_seed, any_top, h->plan, dev_setup ? &dgb : nullptr);
         if (rc != kOk) {
             delete h;
             return (lap_status)rc;

@@ -16,13 +16,18 @@ namespace lapgpu {
 // counting pass, then each row is ordered by (neighbour, edge position) and
 // parallel edges merged in edge-position order (same order in both rows, so
 // the merged weights are exactly symmetric).
-int build_adjacency(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
-                    const double* w, Adjacency& out) {
+int validate_edges(int64_t n, int64_t m, const int64_t* u, const int64_t* v, const double* w) {
     if (n < 2 || m < 1 || n > INT32_MAX - 1) return kInval;
     for (int64_t e = 0; e < m; ++e) {
         if (u[e] < 0 || u[e] >= n || v[e] < 0 || v[e] >= n || u[e] == v[e]) return kInval;
         if (!(w[e] > 0.0) || !std::isfinite(w[e])) return kInval;
     }
+    return kOk;
+}
+
+int build_adjacency(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+                    const double* w, Adjacency& out) {
+    if (validate_edges(n, m, u, v, w) != kOk) return kInval;
     std::vector<int64_t> start(n + 1, 0);
     for (int64_t e = 0; e < m; ++e) { ++start[u[e] + 1]; ++start[v[e] + 1]; }
     for (int64_t i = 0; i < n; ++i) start[i + 1] += start[i];
@@ -260,12 +265,13 @@ static double level_theta(double mu, int k) {
 
 int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                const double* w, double mu, int max_levels, int64_t n_top,
-               uint64_t seed, bool any_top, HostPlan& plan) {
+               uint64_t seed, bool any_top, HostPlan& plan, GraphBuilder* gb) {
     if (!(mu > 0.0 && mu < 1.0) || n_top < 2 || max_levels < 0) return kInval;
     plan = HostPlan();
     plan.mu = mu;
     plan.lv.emplace_back();
-    int rc = build_adjacency(n, m, u, v, w, plan.lv[0].g);
+    int rc = gb ? gb->adjacency(n, m, u, v, w, plan.lv[0].g)
+                : build_adjacency(n, m, u, v, w, plan.lv[0].g);
     if (rc != kOk) return rc;
     if (!is_connected(plan.lv[0].g)) return kDisconnected;
 
@@ -284,7 +290,8 @@ int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
         }
         if (nc < 2 || nc >= f.g.n) break;
         Level c;
-        coarse_graph(f.g, agg, nc, c.g);
+        if (gb) gb->coarse(f.g, agg, nc, c.g);
+        else coarse_graph(f.g, agg, nc, c.g);
         f.agg.swap(agg);
         f.matched.swap(mt);
         plan.lv.push_back(std::move(c));

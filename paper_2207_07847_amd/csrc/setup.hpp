@@ -147,9 +147,21 @@ void coarse_graph(const Adjacency& f, const std::vector<int64_t>& agg, int64_t n
 // Full host setup; returns a Status.  any_top allows top levels larger
 // than kTopMax (no on-chip dense top solve: host-only setups, PEGP, plain
 // CG); their top pseudo-inverse is then not formed.
+// Graph construction done elsewhere (on the device): the same outputs as
+// build_adjacency (after validate_edges) and coarse_graph, bit for bit.
+struct GraphBuilder {
+    virtual int adjacency(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
+                          const double* w, Adjacency& out) = 0;
+    virtual void coarse(const Adjacency& f, const std::vector<int64_t>& agg, int64_t nc,
+                        Adjacency& c) = 0;
+    virtual ~GraphBuilder() = default;
+};
 int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                const double* w, double mu, int max_levels, int64_t n_top,
-               uint64_t seed, bool any_top, HostPlan& plan);
+               uint64_t seed, bool any_top, HostPlan& plan, GraphBuilder* gb = nullptr);
+// kOk when the edge list is a valid input: n >= 2, 0 <= u, v < n, u != v,
+// w > 0 finite; kInval otherwise.
+int validate_edges(int64_t n, int64_t m, const int64_t* u, const int64_t* v, const double* w);
 // The SpMV layout of the fine Laplacian g (part of build_plan).
 void build_sell(const Adjacency& g, HostPlan& plan);
 // Whether g is mesh-like for the SpMV: no row above kHeavyDeg and slices of
