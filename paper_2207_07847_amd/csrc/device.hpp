@@ -1464,7 +1464,8 @@ __device__ inline double sparse_dot(const double* __restrict__ val,
 // The levels of a level-scheduled triangular solve on the LDS vector f, as
 // packed by the host: level l's descriptor deals the rows [r0, r0 + nr) of
 // the level list to groups of 2^g lanes over P passes of NT threads; thread
-// t's u-th entry of pass p is at base + (p U + u) NT + t.  Each row r gets
+// t's u-th entry of pass p is at base + (p U + u) NT + t (columns as LDS
+// byte offsets, node * 8).  Each row r gets
 // f[rows[r]] -= sum of its entries' values times f at their nodes (no row of
 // a level reads another's node).  The first kPegpPre entries of pass 0 of
 // the next level are loaded into registers while the current level runs:
@@ -1492,6 +1493,8 @@ struct PegpPreRow {
 // Pass 0's first entries of thread t (threads past NT load thread NT-1's,
 // rounds past U load round U-1's: no load is masked, so none is waited for
 // on its own; those values are not used).
+// (the round's offset is uniform: it goes into the scalar base of each
+// load, which then takes the same per-thread offset)
 __device__ __forceinline__ void pegp_fetch(PegpPreRow& s, const PegpLvl& D,
                                            const int32_t* __restrict__ rows,
                                            const double* __restrict__ val,
@@ -1500,14 +1503,40 @@ __device__ __forceinline__ void pegp_fetch(PegpPreRow& s, const PegpLvl& D,
     s.node = rows[D.r0 + (tt >> D.g)];
 #pragma unroll
     for (int u = 0; u < kPegpPre; ++u) {
-        const int i = D.base + min(u, D.u - 1) * D.nt + tt;
-        s.a[u] = val[i];
-        s.c[u] = col[i];
+        const size_t off = (size_t)D.base + (size_t)min(u, D.u - 1) * D.nt;
+        s.a[u] = (val + off)[tt];
+        s.c[u] = (col + off)[tt];
     }
 }
 
-__device__ __forceinline__ double pegp_group_sum(double v, int g) {
-    for (int o = (1 << g) >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// f at an LDS byte offset (the packed columns hold node * 8)
+__device__ __forceinline__ double pegp_at(const double* f, int byte_off) {
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(f) + byte_off);
+}
+
+// v moved by the DPP control CTRL (rows in ROWMASK written, lanes with no
+// source read 0; the other rows get 0)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, ROWMASK, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+
+// Sum of each aligned group of 2^g lanes (g <= 6), valid in the group's last
+// lane (q = lane within the group): an inclusive scan inside each 16-lane
+// row by row shifts (masked at the group's start), then the row totals
+// carried up by row broadcasts.  Register moves only, no LDS permutes.
+__device__ __forceinline__ double pegp_group_sum(double v, int g, int q) {
+    constexpr int kShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
+    if (g >= 1) { const double t = dpp_f64<kShr + 1, 0xf>(v); v += q >= 1 ? t : 0.0; }
+    if (g >= 2) { const double t = dpp_f64<kShr + 2, 0xf>(v); v += q >= 2 ? t : 0.0; }
+    if (g >= 3) { const double t = dpp_f64<kShr + 4, 0xf>(v); v += q >= 4 ? t : 0.0; }
+    if (g >= 4) { const double t = dpp_f64<kShr + 8, 0xf>(v); v += q >= 8 ? t : 0.0; }
+    if (g >= 5) v += dpp_f64<kBcast15, 0xa>(v);
+    if (g >= 6) v += dpp_f64<kBcast31, 0xc>(v);
     return v;
 }
 
@@ -1519,13 +1548,13 @@ __device__ __forceinline__ void pegp_level(double* f, const PegpLvl& D, const Pe
         const int q = t & ((1 << D.g) - 1);
         double acc = 0.0;
 #pragma unroll
-        for (int u = 0; u < kPegpPre; ++u) acc += (u < D.u ? s.a[u] : 0.0) * f[s.c[u]];
+        for (int u = 0; u < kPegpPre; ++u) acc += (u < D.u ? s.a[u] : 0.0) * pegp_at(f, s.c[u]);
         for (int u = kPegpPre; u < D.u; ++u) {
             const int i = D.base + u * D.nt + t;
-            acc += val[i] * f[col[i]];
+            acc += val[i] * pegp_at(f, col[i]);
         }
-        acc = pegp_group_sum(acc, D.g);
-        if (q == 0) f[s.node] -= acc;
+        acc = pegp_group_sum(acc, D.g, q);
+        if (q == (1 << D.g) - 1) f[s.node] -= acc;
         // further passes (levels wider than the workgroup's groups)
         for (int p = 1; p < D.np; ++p) {
             const int rr = p * (kPegpThreads >> D.g) + (t >> D.g);
@@ -1533,10 +1562,10 @@ __device__ __forceinline__ void pegp_level(double* f, const PegpLvl& D, const Pe
                 double a2 = 0.0;
                 for (int u = 0; u < D.u; ++u) {
                     const int i = D.base + (p * D.u + u) * D.nt + t;
-                    a2 += val[i] * f[col[i]];
+                    a2 += val[i] * pegp_at(f, col[i]);
                 }
-                a2 = pegp_group_sum(a2, D.g);
-                if (q == 0) f[rows[D.r0 + rr]] -= a2;
+                a2 = pegp_group_sum(a2, D.g, q);
+                if (q == (1 << D.g) - 1) f[rows[D.r0 + rr]] -= a2;
             }
         }
     }

@@ -591,7 +591,7 @@ static bool pegp_pack(const std::vector<int32_t>& lev, const std::vector<int32_t
                 const int32_t t = grp * G + e % G, u = e / G;
                 const size_t i = (size_t)base + ((size_t)p * U + u) * nt + t;
                 pval[i] = val[ptr[r] + e];
-                pcol[i] = col[ptr[r] + e];
+                pcol[i] = col[ptr[r] + e] * (int32_t)sizeof(double);
             }
         }
         const int32_t d[kPegpDescInts] = {base, nt | g << 12 | U << 16, np | nr << 16, r0};

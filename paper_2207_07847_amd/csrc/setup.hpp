@@ -124,8 +124,9 @@ struct PegpPlan {
     // kPegpDescInts ints {base, NT | g << 12 | U << 16, P | nr << 16, r0}:
     // 2^g lanes per row, the rows [r0, r0 + nr) of the level list dealt to P
     // passes of NT threads, U entries per thread and pass; the entry of pass
-    // p, round u, thread t at base + (p U + u) NT + t (padding: value 0 on
-    // node 0).  A thread's entries are found from the descriptor alone, so a
+    // p, round u, thread t at base + (p U + u) NT + t, its column as the
+    // node's byte offset in a vector of doubles, node * 8 (padding: value 0
+    // on node 0).  A thread's entries are found from the descriptor alone, so a
     // level's loads can be issued before the previous level is done.
     std::vector<int32_t> fdesc, bdesc, fpcol, bpcol;
     std::vector<double> fpval, bpval;
