@@ -442,6 +442,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "both"],
                     help="both: mixed precision timed, plain FP64 timed beside it")
     ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--mu", type=float, default=0.0,
+                    help="mu in (0, 1) instead of the workload's (0: the workload's)")
     ap.add_argument("--nrhs", type=int, default=1,
                     help="right-hand sides per solve (> 1: the 64-column block solve)")
     ap.add_argument("--compare-cols", type=int, default=8,
@@ -498,6 +500,8 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.time()
     wl = workload(args.workload, args.scale, args.nrhs)
+    if args.mu > 0.0:
+        wl["mu"] = args.mu
     log(f"workload {args.workload}: n={wl['n']} edges={len(wl['u'])} ({time.time() - t0:.1f}s)")
     n = wl["n"]
     stream = torch.cuda.current_stream()
@@ -597,8 +601,10 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {
-            "workload": WORKLOADS[args.workload].replace("^3", f"^3 (scale {args.scale})")
-            if args.scale != 1.0 else WORKLOADS[args.workload],
+            "workload": (WORKLOADS[args.workload].replace("^3", f"^3 (scale {args.scale})")
+                         if args.scale != 1.0 else WORKLOADS[args.workload]).replace(
+                "mu=0.8", f"mu={wl['mu']:g}").replace("mu=1/64", f"mu={wl['mu']:g}"
+                                                     if args.mu > 0.0 else "mu=1/64"),
             "precision": "FP64" if args.precision == "fp64" else
                          "FP32 SpMV/preconditioner inside FP64 iterative refinement",
             "solver": "FGMRES on the expanded system" if args.solver == "fgmres" else

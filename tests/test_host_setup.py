@@ -215,3 +215,37 @@ def test_default_params_and_status_strings():
     assert p.mu == 0.8 and p.n_top == 2 and p.max_levels == 0 and p.max_iter == 1000
     assert lap.lap_status_str(lap.LAP_ENOCONV) == "LAP_ENOCONV"
     assert lap.lap_status_str(99) == "LAP_UNKNOWN"
+
+
+def test_spectrum_and_mu_choice_errors_without_device():
+    """The spectrum estimate and the choice of mu reject bad arguments and
+    host-only hierarchies before touching a device."""
+    import ctypes as C
+    lap = _lap()
+    n, u, v = W.grid2d(8)
+    w = W.unit_weights(len(u))
+    h = lap.lap_setup(n, u, v, w, lap.lap_default_params(flags=lap.LAP_FLAG_HOST_ONLY))
+    try:
+        b = np.ones(n)
+        st, *_ = lap.lap_estimate_spectrum(h, b.ctypes.data, 10)
+        assert st == lap.LAP_EUNSUPPORTED
+        st, *_ = lap.lap_estimate_spectrum(h, b.ctypes.data, 0)
+        assert st == lap.LAP_EINVAL
+        st, *_ = lap.lap_estimate_spectrum(h, 0, 10)
+        assert st == lap.LAP_EINVAL
+    finally:
+        lap.lap_free(h)
+    st, best, _ = lap.lap_select_mu(n, u, v, w, [], 1, 10)
+    assert st == lap.LAP_EINVAL and best == -1
+    st, best, _ = lap.lap_select_mu(n, u, v, w, [0.8], 1, 0)
+    assert st == lap.LAP_EINVAL
+    # a mu outside (0, 1) fails in set-up for every candidate: its status
+    kap = np.zeros(2)
+    g, keep = lap._graph(n, u, v, w)
+    p = lap.lap_default_params(flags=lap.LAP_FLAG_HOST_ONLY)
+    mus = np.array([1.5, -0.2])
+    bi = C.c_int32(-1)
+    st = lap._lib.lap_select_mu(C.byref(g), C.byref(p), mus.ctypes.data, 2, C.c_void_p(1), 10,
+                                kap.ctypes.data, C.byref(bi), None)
+    assert st == lap.LAP_EINVAL and bi.value == -1
+    assert np.all(np.isinf(kap))
