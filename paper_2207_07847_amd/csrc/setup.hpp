@@ -133,7 +133,7 @@ struct PegpPlan {
 };
 constexpr int kPegpSolveThreads = 1024;      // threads of the PEGP solve workgroup
 constexpr int kPegpDescInts = 4;
-constexpr int kPegpTailWidth = 4;
+constexpr int kPegpTailWidth = 8;
 constexpr int kPegpMinDense = 64;
 constexpr int kPegpMaxDense = 4096;
 int build_pegp(const HostPlan& plan, double mu, PegpPlan& out);
