@@ -1677,7 +1677,9 @@ __global__ __launch_bounds__(kBlock) void k_pegp_tail_rhs(PegpDev P, const Scal*
 // unit triangle, a lane per row holding its row of the block in registers
 // (coalesced loads of the factor's other orientation) and taking the solved
 // values from the lanes before it; the other workgroups apply block b's
-// values to all rows past the next block, a wavefront per row.
+// values to all rows past the next block, a wavefront per row.  The tail is
+// padded to whole blocks (zero factor, unit diagonal, zero values), so every
+// block has kTailB rows and no load needs a bound.
 constexpr int kTailB = 64;
 
 // v broadcast from lane j (j uniform)
@@ -1688,11 +1690,10 @@ __device__ inline double lane_bcast(double v, int j) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// sum over j < n (n <= kTailB) of a[j * stride] * x[j], the loads issued in
-// two batches of half a block each (the terms past n load entry n - 1 and
-// count 0: no load is masked, so none is waited for on its own)
+// sum over j < kTailB of a[j * stride] * x[j], the loads issued in two
+// batches of half a block each
 __device__ inline double tail_dot(const double* __restrict__ a, int stride,
-                                  const double* __restrict__ x, int n) {
+                                  const double* __restrict__ x) {
     constexpr int H = kTailB / 2;
     double acc = 0.0;
 #pragma unroll
@@ -1700,42 +1701,38 @@ __device__ inline double tail_dot(const double* __restrict__ a, int stride,
         double v[H], w[H];
 #pragma unroll
         for (int j = 0; j < H; ++j) {
-            const int jj = min(h * H + j, n - 1);
-            v[j] = a[(size_t)jj * stride];
-            w[j] = x[jj];
+            v[j] = a[(size_t)(h * H + j) * stride];
+            w[j] = x[h * H + j];
         }
 #pragma unroll
-        for (int j = 0; j < H; ++j) acc += (h * H + j < n ? v[j] : 0.0) * w[j];
+        for (int j = 0; j < H; ++j) acc += v[j] * w[j];
     }
     return acc;
 }
 
-// forward, block b solved (b = -1: none yet); solves block b + 1
+// forward, block b solved (b = -1: none yet); solves block b + 1.  The
+// tail is padded to whole blocks (ndp rows, zero factor, unit diagonal).
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pegp_tail_fwd(PegpDev P, int b, const Scal* S) {
     if (S->done) return;
-    const int nd = P.nd, b0 = b * kTailB, b1 = (b + 1) * kTailB, nb1 = min(kTailB, nd - b1);
+    const int nd = P.ndp, b0 = b * kTailB, b1 = (b + 1) * kTailB;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     constexpr int NW = kBlock / 64;
     double* y = P.ty;
     if (blockIdx.x == 0) {
         if (wid != 0) return;
-        // Lanes past the block's end repeat its last row: they are never
-        // broadcast or stored, so no load needs a mask (a masked load would
-        // be waited for on its own).
-        const int row = b1 + min(lane, nb1 - 1);
+        const int row = b1 + lane;
         // L[j] = L_tt[row][b1 + j], used for j < lane
         double L[kTailB];
 #pragma unroll
-        for (int j = 0; j < kTailB; ++j) L[j] = P.dlc[(size_t)(b1 + min(j, nb1 - 1)) * nd + row];
+        for (int j = 0; j < kTailB; ++j) L[j] = P.dlc[(size_t)(b1 + j) * nd + row];
         double yi = y[row];
-        if (b >= 0) yi -= tail_dot(P.dlc + (size_t)b0 * nd + row, nd, y + b0, kTailB);
+        if (b >= 0) yi -= tail_dot(P.dlc + (size_t)b0 * nd + row, nd, y + b0);
 #pragma unroll
         for (int j = 0; j + 1 < kTailB; ++j) {
-            if (j + 1 >= nb1) continue;
             const double xj = lane_bcast(yi, j);
             if (lane > j) yi -= L[j] * xj;
         }
-        if (lane < nb1) y[row] = yi;
+        y[row] = yi;
         return;
     }
     const int r = b1 + kTailB + (blockIdx.x - 1) * NW + wid;
@@ -1750,42 +1747,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pegp_tail_bwd(PegpDev P, int b, int nblk,
                                                           const Scal* S) {
     if (S->done) return;
-    const int nd = P.nd, c0 = (b - 1) * kTailB, nc = min(kTailB, nd - c0);
-    const int b0 = b * kTailB, nb = b < nblk ? min(kTailB, nd - b0) : 0;
+    const int nd = P.ndp, c0 = (b - 1) * kTailB, b0 = b * kTailB;
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     constexpr int NW = kBlock / 64;
     double* y = P.ty;
     if (blockIdx.x == 0) {
         if (wid != 0) return;
-        // (lanes past the block's end as in the forward kernel)
-        const int row = c0 + min(lane, nc - 1);
-        // L[j] = L_tt[c0 + j][row], used for lane < j < nc
+        const int row = c0 + lane;
+        // L[j] = L_tt[c0 + j][row], used for j > lane
         double L[kTailB];
 #pragma unroll
-        for (int j = 0; j < kTailB; ++j) L[j] = P.dlr[(size_t)(c0 + min(j, nc - 1)) * nd + row];
+        for (int j = 0; j < kTailB; ++j) L[j] = P.dlr[(size_t)(c0 + j) * nd + row];
         double yi = y[row];
-        if (b == nblk) {
-            yi /= P.diag[P.drow[row]];
-        } else {
-            yi -= tail_dot(P.dlr + (size_t)b0 * nd + row, nd, y + b0, nb);
-        }
+        if (b == nblk) yi /= P.dd[row];
+        else yi -= tail_dot(P.dlr + (size_t)b0 * nd + row, nd, y + b0);
 #pragma unroll
         for (int j = kTailB - 1; j > 0; --j) {
-            if (j >= nc) continue;
             const double xj = lane_bcast(yi, j);
             if (lane < j) yi -= L[j] * xj;
         }
-        if (lane < nc) y[row] = yi;
+        y[row] = yi;
         return;
     }
     if (b == nblk) {
         const int r = (blockIdx.x - 1) * kBlock + tid;
-        if (r < c0) y[r] /= P.diag[P.drow[r]];
+        if (r < c0) y[r] /= P.dd[r];
         return;
     }
     const int r = (blockIdx.x - 1) * NW + wid;
     if (r >= c0) return;
-    double a = lane < nb ? P.dlc[(size_t)r * nd + b0 + lane] * y[b0 + lane] : 0.0;
+    double a = P.dlc[(size_t)r * nd + b0 + lane] * y[b0 + lane];
     a = wave_sum1(a);
     if (lane == 0) y[r] -= a;
 }

@@ -218,9 +218,10 @@ struct PegpDev {
     // factor of the tail row-major (forward) and column-major (backward), the
     // forward coupling (CSR by tail position, columns are nodes), the
     // backward coupling (nbc rows bcrow, columns are tail positions)
-    int32_t nd, nbc;
+    int32_t nd, ndp, nbc;                 // tail rows, padded to whole blocks (the
+                                         // dense arrays' dimension), coupling rows
     const int32_t *drow, *dcptr, *dccol, *bcrow, *bcptr, *bccol;
-    const double *dlr, *dlc, *dcval, *bcval;
+    const double *dlr, *dlc, *dd, *dcval, *bcval;
     // device scratch of one apply: the expanded vector between the
     // single-workgroup kernels, the tail's values, the backward coupling sums
     double *fg, *ty, *cpl;

@@ -574,10 +574,10 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
                 const int per = kBlock / 64;   // a wavefront per row
                 hipLaunchKernelGGL(k_pegp_tail_rhs, dim3((P.nd + per - 1) / per), dim3(kBlock), 0,
                                    s, P, (const Scal*)S);
-                const int nblk = (P.nd + kTailB - 1) / kTailB;
+                const int nblk = P.ndp / kTailB;
                 for (int b = -1; b + 1 < nblk; ++b) {
                     // workgroup 0, and a wavefront per row past the next block
-                    const int rest = std::max(0, P.nd - (b + 2) * kTailB);
+                    const int rest = std::max(0, P.ndp - (b + 2) * kTailB);
                     const int grid = 1 + (b >= 0 ? (rest + per - 1) / per : 0);
                     hipLaunchKernelGGL(k_pegp_tail_fwd, dim3(grid), dim3(kBlock), 0, s, P, b,
                                        (const Scal*)S);
@@ -905,10 +905,12 @@ void upload_pegp(lap_hierarchy* h, hipStream_t s) {
     d.bpcol = h->upload(G.bpcol, s);
     d.bpval = h->upload(G.bpval, s);
     d.nd = G.nd;
+    d.ndp = G.ndp;
     d.nbc = (int32_t)G.bcrow.size();
     d.drow = h->upload(G.drow, s);
     d.dlr = h->upload(G.dlr, s);
     d.dlc = h->upload(G.dlc, s);
+    d.dd = h->upload(G.dd, s);
     d.dcptr = h->upload(G.dcptr, s);
     d.dccol = h->upload(G.dccol, s);
     d.dcval = h->upload(G.dcval, s);
@@ -917,7 +919,10 @@ void upload_pegp(lap_hierarchy* h, hipStream_t s) {
     d.bccol = h->upload(G.bccol, s);
     d.bcval = h->upload(G.bcval, s);
     d.fg = h->dalloc<double>(G.nt);
-    d.ty = h->dalloc<double>(G.nd);
+    // (the padding rows of the tail vector stay 0: nothing writes them
+    // but the dense solve, which keeps them 0)
+    d.ty = h->dalloc<double>(std::max(G.ndp, 1));
+    HIPCHK(hipMemsetAsync(d.ty, 0, (size_t)std::max(G.ndp, 1) * sizeof(double), s));
     d.cpl = h->dalloc<double>(G.bcrow.size());
     // the vector, then (16-byte aligned) the larger level descriptor table
     // when it fits beside it
@@ -1172,6 +1177,7 @@ constexpr int kTuneReps = 3;
 constexpr size_t kTuneMaxScratch = size_t(512) << 20;  // split-row scratch of a candidate
 static_assert(2048 <= 3 * kMmMaxGrid, "the SpMM's partials fit the partial buffer");
 static_assert(kPegpThreads == kPegpSolveThreads, "the PEGP plan is made for the solve's workgroup");
+static_assert(kTailB == kPegpTailBlock, "the PEGP tail is padded to the solve's blocks");
 
 // Average time per call of `launch` over kTuneReps calls after one warm-up.
 template <class F>

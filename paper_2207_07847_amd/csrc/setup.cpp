@@ -807,10 +807,14 @@ int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
     }
     std::vector<int32_t> tpos(m, -1);
     out.nd = nd;
+    const int32_t ndp = (nd + kPegpTailBlock - 1) / kPegpTailBlock * kPegpTailBlock;
+    out.ndp = ndp;
     out.drow.assign(out.frow.begin() + out.flev[lt], out.frow.begin() + out.flev[nfl]);
     for (int32_t p = 0; p < nd; ++p) tpos[out.drow[p]] = p;
-    out.dlr.assign((size_t)nd * nd, 0.0);
-    out.dlc.assign((size_t)nd * nd, 0.0);
+    out.dlr.assign((size_t)ndp * ndp, 0.0);
+    out.dlc.assign((size_t)ndp * ndp, 0.0);
+    out.dd.assign(ndp, 1.0);
+    for (int32_t p = 0; p < nd; ++p) out.dd[p] = out.diag[out.drow[p]];
     out.dcptr.assign(nd + 1, 0);
     for (int32_t p = 0; p < nd; ++p) {
         for (auto& e : rowL[out.drow[p]]) {
@@ -818,8 +822,8 @@ int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
             if (q >= 0) {
                 // dependencies lie on earlier levels: earlier tail positions
                 if (q >= p) return kInval;
-                out.dlr[(size_t)p * nd + q] = e.second;
-                out.dlc[(size_t)q * nd + p] = e.second;
+                out.dlr[(size_t)p * ndp + q] = e.second;
+                out.dlc[(size_t)q * ndp + p] = e.second;
             } else {
                 out.dccol.push_back(e.first);
                 out.dcval.push_back(e.second);

@@ -107,8 +107,12 @@ struct PegpPlan {
     // row depends on the tail in the forward pass, and the tail depends on no
     // other row in the backward pass; the level lists above leave it out.
     int32_t nd = 0;                          // tail rows (0: none)
+    int32_t ndp = 0;                         // nd rounded up to a multiple of kPegpTailBlock
     std::vector<int32_t> drow;               // tail position -> expanded node
-    std::vector<double> dlr, dlc;            // nd x nd strict lower L_tt, row- and column-major
+    // ndp x ndp strict lower L_tt, row- and column-major, and the diagonal
+    // of the tail by position; the padding rows and columns are 0 (diagonal
+    // 1), so every block of the dense solve is whole and solves to 0 there
+    std::vector<double> dlr, dlc, dd;
     // Coupling of the tail with the other nodes: forward, the tail rows'
     // entries on the other nodes (CSR by tail position, columns are nodes);
     // backward, the other rows' entries on the tail (rows bcrow, columns are
@@ -134,6 +138,7 @@ struct PegpPlan {
 constexpr int kPegpSolveThreads = 1024;      // threads of the PEGP solve workgroup
 constexpr int kPegpDescInts = 4;
 constexpr int kPegpTailWidth = 8;
+constexpr int kPegpTailBlock = 64;            // rows per block of the dense tail solve
 constexpr int kPegpMinDense = 64;
 constexpr int kPegpMaxDense = 4096;
 int build_pegp(const HostPlan& plan, double mu, PegpPlan& out);
