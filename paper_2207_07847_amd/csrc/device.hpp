@@ -1670,17 +1670,23 @@ __global__ __launch_bounds__(kBlock) void k_pegp_tail_rhs(PegpDev P, const Scal*
 }
 
 // The dense tail solves, y = L_tt^-1 y, y = D_t^-1 y and y = L_tt^-T y in
-// place on the tail vector, by blocks of kTailB rows with a kernel per block
-// (the kernels' order on the stream carries the dependencies).  In the
-// kernel for block b, the first wavefront of workgroup 0 brings the rows of
-// the next block up to date with block b's values and solves that block's
-// unit triangle, a lane per row holding its row of the block in registers
-// (coalesced loads of the factor's other orientation) and taking the solved
-// values from the lanes before it; the other workgroups apply block b's
-// values to all rows past the next block, a wavefront per row.  The tail is
-// padded to whole blocks (zero factor, unit diagonal, zero values), so every
-// block has kTailB rows and no load needs a bound.
+// place on the tail vector, by superblocks of kTailS rows with a kernel per
+// superblock (the kernels' order on the stream carries the dependencies).
+// A superblock is kTailW blocks of kTailB rows.  In the kernel for
+// superblock b, the first kTailW wavefronts of workgroup 0 each take one
+// block of the next superblock, a lane per row holding its row of that
+// block's diagonal block in registers (coalesced loads of the factor's
+// other orientation), and bring it up to date with superblock b's values;
+// then, block after block, one wavefront solves its unit triangle with a
+// broadcast chain, passes the values on through LDS, and the wavefronts of
+// the blocks after it apply them (their loads issued before the wait).  The
+// other workgroups apply superblock b's values to all rows past the next
+// superblock, a wavefront per row.  The tail is padded to whole superblocks
+// (zero factor, unit diagonal, zero values), so no load needs a bound.
 constexpr int kTailB = 64;
+constexpr int kTailW = 4;
+constexpr int kTailS = kTailB * kTailW;
+static_assert(kTailW * 64 <= kBlock, "a wavefront of workgroup 0 per block");
 
 // v broadcast from lane j (j uniform)
 __device__ inline double lane_bcast(double v, int j) {
@@ -1690,83 +1696,154 @@ __device__ inline double lane_bcast(double v, int j) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// sum over j < kTailB of a[j * stride] * x[j], the loads issued in two
-// batches of half a block each
-__device__ inline double tail_dot(const double* __restrict__ a, int stride,
-                                  const double* __restrict__ x) {
+// sum over j < kTailB of a[j * stride] * x_j, where lane j holds x_j in xv;
+// the loads issued in two batches of half a block each
+__device__ inline double tail_dot(const double* __restrict__ a, int stride, double xv) {
     constexpr int H = kTailB / 2;
     double acc = 0.0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        double v[H], w[H];
+        double v[H];
 #pragma unroll
-        for (int j = 0; j < H; ++j) {
-            v[j] = a[(size_t)(h * H + j) * stride];
-            w[j] = x[h * H + j];
-        }
+        for (int j = 0; j < H; ++j) v[j] = a[(size_t)(h * H + j) * stride];
 #pragma unroll
-        for (int j = 0; j < H; ++j) acc += v[j] * w[j];
+        for (int j = 0; j < H; ++j) acc += v[j] * lane_bcast(xv, h * H + j);
     }
     return acc;
 }
 
-// forward, block b solved (b = -1: none yet); solves block b + 1.  The
-// tail is padded to whole blocks (ndp rows, zero factor, unit diagonal).
+// forward, superblock b solved (b = -1: none yet); solves superblock b + 1
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pegp_tail_fwd(PegpDev P, int b, const Scal* S) {
     if (S->done) return;
-    const int nd = P.ndp, b0 = b * kTailB, b1 = (b + 1) * kTailB;
-    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int nd = P.ndp, b0 = b * kTailS, b1 = (b + 1) * kTailS;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     constexpr int NW = kBlock / 64;
     double* y = P.ty;
     if (blockIdx.x == 0) {
-        if (wid != 0) return;
-        const int row = b1 + lane;
-        // L[j] = L_tt[row][b1 + j], used for j < lane
-        double L[kTailB];
+        __shared__ double xs[kTailS];
+        const bool act = wid < kTailW;
+        const int r0 = b1 + (act ? wid : 0) * kTailB, row = r0 + lane;
+        // L[j] = L_tt[row][r0 + j], used for j < lane
+        double L[kTailB], yi = 0.0;
+        if (act) {
 #pragma unroll
-        for (int j = 0; j < kTailB; ++j) L[j] = P.dlc[(size_t)(b1 + j) * nd + row];
-        double yi = y[row];
-        if (b >= 0) yi -= tail_dot(P.dlc + (size_t)b0 * nd + row, nd, y + b0);
+            for (int j = 0; j < kTailB; ++j) L[j] = P.dlc[(size_t)(r0 + j) * nd + row];
+            yi = y[row];
+            if (b >= 0) {
 #pragma unroll
-        for (int j = 0; j + 1 < kTailB; ++j) {
-            const double xj = lane_bcast(yi, j);
-            if (lane > j) yi -= L[j] * xj;
+                for (int q = 0; q < kTailW; ++q) {
+                    const int c = b0 + q * kTailB;
+                    yi -= tail_dot(P.dlc + (size_t)c * nd + row, nd, y[c + lane]);
+                }
+            }
         }
-        y[row] = yi;
+#pragma unroll
+        for (int m = 0; m < kTailW; ++m) {
+            // stage m: wavefront m solves its block, the later ones apply it
+            const bool cross = act && wid > m;
+            double C[kTailB];
+            if (cross) {
+#pragma unroll
+                for (int j = 0; j < kTailB; ++j)
+                    C[j] = P.dlc[(size_t)(b1 + m * kTailB + j) * nd + row];
+            }
+            if (wid == m) {
+#pragma unroll
+                for (int j = 0; j + 1 < kTailB; ++j) {
+                    const double xj = lane_bcast(yi, j);
+                    if (lane > j) yi -= L[j] * xj;
+                }
+                y[row] = yi;
+                xs[m * kTailB + lane] = yi;
+            }
+            if (m + 1 < kTailW) __syncthreads();
+            if (cross) {
+                const double xv = xs[m * kTailB + lane];
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < kTailB; ++j) acc += C[j] * lane_bcast(xv, j);
+                yi -= acc;
+            }
+        }
         return;
     }
-    const int r = b1 + kTailB + (blockIdx.x - 1) * NW + wid;
+    const int r = b1 + kTailS + (blockIdx.x - 1) * NW + wid;
     if (b < 0 || r >= nd) return;
-    double a = P.dlr[(size_t)r * nd + b0 + lane] * y[b0 + lane];
-    a = wave_sum1(a);
-    if (lane == 0) y[r] -= a;
+    double a[kTailW];
+#pragma unroll
+    for (int q = 0; q < kTailW; ++q) {
+        const int c = b0 + q * kTailB + lane;
+        a[q] = wave_sum1(P.dlr[(size_t)r * nd + c] * y[c]);
+    }
+    if (lane == 0) {
+        double v = y[r];
+#pragma unroll
+        for (int q = 0; q < kTailW; ++q) v -= a[q];
+        y[r] = v;
+    }
 }
 
-// backward, block b solved (b = nblk: none yet; then the diagonal D_t^-1 is
-// applied to every tail row first); solves block b - 1
+// backward, superblock b solved (b = nblk: none yet; then the diagonal
+// D_t^-1 is applied to every tail row first); solves superblock b - 1, its
+// last block first
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_pegp_tail_bwd(PegpDev P, int b, int nblk,
                                                           const Scal* S) {
     if (S->done) return;
-    const int nd = P.ndp, c0 = (b - 1) * kTailB, b0 = b * kTailB;
-    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int nd = P.ndp, c0 = (b - 1) * kTailS, b0 = b * kTailS;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     constexpr int NW = kBlock / 64;
     double* y = P.ty;
     if (blockIdx.x == 0) {
-        if (wid != 0) return;
-        const int row = c0 + lane;
-        // L[j] = L_tt[c0 + j][row], used for j > lane
-        double L[kTailB];
+        __shared__ double xs[kTailS];
+        const bool act = wid < kTailW;
+        const int r0 = c0 + (act ? wid : 0) * kTailB, row = r0 + lane;
+        // L[j] = L_tt[r0 + j][row], used for j > lane
+        double L[kTailB], yi = 0.0;
+        if (act) {
 #pragma unroll
-        for (int j = 0; j < kTailB; ++j) L[j] = P.dlr[(size_t)(c0 + j) * nd + row];
-        double yi = y[row];
-        if (b == nblk) yi /= P.dd[row];
-        else yi -= tail_dot(P.dlr + (size_t)b0 * nd + row, nd, y + b0);
+            for (int j = 0; j < kTailB; ++j) L[j] = P.dlr[(size_t)(r0 + j) * nd + row];
+            yi = y[row];
+            if (b == nblk) {
+                yi /= P.dd[row];
+            } else {
 #pragma unroll
-        for (int j = kTailB - 1; j > 0; --j) {
-            const double xj = lane_bcast(yi, j);
-            if (lane < j) yi -= L[j] * xj;
+                for (int q = 0; q < kTailW; ++q) {
+                    const int c = b0 + q * kTailB;
+                    yi -= tail_dot(P.dlr + (size_t)c * nd + row, nd, y[c + lane]);
+                }
+            }
         }
-        y[row] = yi;
+#pragma unroll
+        for (int m = 0; m < kTailW; ++m) {
+            // stage m: wavefront ws solves its block, the earlier ones apply it
+            const int ws = kTailW - 1 - m;
+            const bool cross = act && wid < ws;
+            double C[kTailB];
+            if (cross) {
+#pragma unroll
+                for (int j = 0; j < kTailB; ++j)
+                    C[j] = P.dlr[(size_t)(c0 + ws * kTailB + j) * nd + row];
+            }
+            if (wid == ws) {
+#pragma unroll
+                for (int j = kTailB - 1; j > 0; --j) {
+                    const double xj = lane_bcast(yi, j);
+                    if (lane < j) yi -= L[j] * xj;
+                }
+                y[row] = yi;
+                xs[ws * kTailB + lane] = yi;
+            }
+            if (m + 1 < kTailW) __syncthreads();
+            if (cross) {
+                const double xv = xs[ws * kTailB + lane];
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < kTailB; ++j) acc += C[j] * lane_bcast(xv, j);
+                yi -= acc;
+            }
+        }
         return;
     }
     if (b == nblk) {
@@ -1776,9 +1853,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     }
     const int r = (blockIdx.x - 1) * NW + wid;
     if (r >= c0) return;
-    double a = P.dlc[(size_t)r * nd + b0 + lane] * y[b0 + lane];
-    a = wave_sum1(a);
-    if (lane == 0) y[r] -= a;
+    double a[kTailW];
+#pragma unroll
+    for (int q = 0; q < kTailW; ++q) {
+        const int c = b0 + q * kTailB + lane;
+        a[q] = wave_sum1(P.dlc[(size_t)r * nd + c] * y[c]);
+    }
+    if (lane == 0) {
+        double v = y[r];
+#pragma unroll
+        for (int q = 0; q < kTailW; ++q) v -= a[q];
+        y[r] = v;
+    }
 }
 
 // cpl[i] = sum over row bcrow[i]'s entries on the tail of l * y_tail, a

@@ -574,18 +574,18 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
                 const int per = kBlock / 64;   // a wavefront per row
                 hipLaunchKernelGGL(k_pegp_tail_rhs, dim3((P.nd + per - 1) / per), dim3(kBlock), 0,
                                    s, P, (const Scal*)S);
-                const int nblk = P.ndp / kTailB;
+                const int nblk = P.ndp / kTailS;
                 for (int b = -1; b + 1 < nblk; ++b) {
-                    // workgroup 0, and a wavefront per row past the next block
-                    const int rest = std::max(0, P.ndp - (b + 2) * kTailB);
+                    // workgroup 0, and a wavefront per row past the next superblock
+                    const int rest = std::max(0, P.ndp - (b + 2) * kTailS);
                     const int grid = 1 + (b >= 0 ? (rest + per - 1) / per : 0);
                     hipLaunchKernelGGL(k_pegp_tail_fwd, dim3(grid), dim3(kBlock), 0, s, P, b,
                                        (const Scal*)S);
                 }
                 for (int b = nblk; b > 0; --b) {
-                    // workgroup 0, and the rows before the block being solved:
-                    // a thread each for the diagonal, then a wavefront each
-                    const int before = (b - 1) * kTailB;
+                    // workgroup 0, and the rows before the superblock being
+                    // solved: a thread each for the diagonal, then a wavefront each
+                    const int before = (b - 1) * kTailS;
                     const int grid = 1 + (b == nblk ? (before + kBlock - 1) / kBlock
                                                     : (before + per - 1) / per);
                     hipLaunchKernelGGL(k_pegp_tail_bwd, dim3(grid), dim3(kBlock), 0, s, P, b,
@@ -1177,7 +1177,7 @@ constexpr int kTuneReps = 3;
 constexpr size_t kTuneMaxScratch = size_t(512) << 20;  // split-row scratch of a candidate
 static_assert(2048 <= 3 * kMmMaxGrid, "the SpMM's partials fit the partial buffer");
 static_assert(kPegpThreads == kPegpSolveThreads, "the PEGP plan is made for the solve's workgroup");
-static_assert(kTailB == kPegpTailBlock, "the PEGP tail is padded to the solve's blocks");
+static_assert(kTailS == kPegpTailBlock, "the PEGP tail is padded to the solve's superblocks");
 
 // Average time per call of `launch` over kTuneReps calls after one warm-up.
 template <class F>

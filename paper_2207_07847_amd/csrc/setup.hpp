@@ -138,7 +138,7 @@ struct PegpPlan {
 constexpr int kPegpSolveThreads = 1024;      // threads of the PEGP solve workgroup
 constexpr int kPegpDescInts = 4;
 constexpr int kPegpTailWidth = 8;
-constexpr int kPegpTailBlock = 64;            // rows per block of the dense tail solve
+constexpr int kPegpTailBlock = 256;           // rows per kernel (superblock) of the dense tail solve
 constexpr int kPegpMinDense = 64;
 constexpr int kPegpMaxDense = 4096;
 int build_pegp(const HostPlan& plan, double mu, PegpPlan& out);
