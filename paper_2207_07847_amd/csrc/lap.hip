@@ -966,7 +966,12 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(h->So, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    h->chunk = std::max(2, env_int("LAPGPU_CHUNK", 8) & ~1);
+    // Iterations per captured chunk.  The driver keeps one chunk in flight
+    // beyond the one it checks, so up to two chunks run past convergence as
+    // iterations that return at once; each still costs its dispatches.  A
+    // PEGP iteration is about 30 dispatches and a few hundred microseconds,
+    // so two iterations already cover the host's check.
+    h->chunk = std::max(2, env_int("LAPGPU_CHUNK", h->pegp ? 2 : 8) & ~1);
     h->inner_tol = env_double("LAPGPU_INNER_TOL", 1e-4);
     h->reliable_drop = env_double("LAPGPU_RELIABLE_DROP", kReliableDrop);
     h->reliable = env_int("LAPGPU_MIXED_RESTART", 0) == 0;
