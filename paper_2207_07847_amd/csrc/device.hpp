@@ -1684,7 +1684,7 @@ __global__ __launch_bounds__(kBlock) void k_pegp_tail_rhs(PegpDev P, const Scal*
 // superblock, a wavefront per row.  The tail is padded to whole superblocks
 // (zero factor, unit diagonal, zero values), so no load needs a bound.
 constexpr int kTailB = 64;
-constexpr int kTailW = 4;
+constexpr int kTailW = 3;
 constexpr int kTailS = kTailB * kTailW;
 static_assert(kTailW * 64 <= kBlock, "a wavefront of workgroup 0 per block");
 

@@ -137,8 +137,8 @@ struct PegpPlan {
 };
 constexpr int kPegpSolveThreads = 1024;      // threads of the PEGP solve workgroup
 constexpr int kPegpDescInts = 4;
-constexpr int kPegpTailWidth = 8;
-constexpr int kPegpTailBlock = 256;           // rows per kernel (superblock) of the dense tail solve
+constexpr int kPegpTailWidth = 24;
+constexpr int kPegpTailBlock = 192;           // rows per kernel (superblock) of the dense tail solve
 constexpr int kPegpMinDense = 64;
 constexpr int kPegpMaxDense = 4096;
 int build_pegp(const HostPlan& plan, double mu, PegpPlan& out);
