@@ -1616,7 +1616,7 @@ __device__ __forceinline__ void pegp_levels(double* f, DT* desc,
 // them by kernels over the whole device:
 //   k_pegp_fwd        restriction, signs, forward levels -> fg
 //   k_pegp_tail_rhs   y = f_tail - (tail rows' entries on the others) f
-//   k_pegp_tail_fwd   y = L_tt^-1 y, a kernel per block of the tail
+//   k_pegp_tail_fwd   y = L_tt^-1 y, a kernel per superblock of the tail
 //   k_pegp_tail_bwd   y = L_tt^-T D_t^-1 y, the same
 //   k_pegp_tail_back  the other rows' entries on the tail times y
 //   k_pegp_bwd        diagonal, backward levels, signs, prolongation, z

@@ -218,7 +218,7 @@ struct PegpDev {
     // factor of the tail row-major (forward) and column-major (backward), the
     // forward coupling (CSR by tail position, columns are nodes), the
     // backward coupling (nbc rows bcrow, columns are tail positions)
-    int32_t nd, ndp, nbc;                 // tail rows, padded to whole blocks (the
+    int32_t nd, ndp, nbc;                 // tail rows, padded to whole superblocks (the
                                          // dense arrays' dimension), coupling rows
     const int32_t *drow, *dcptr, *dccol, *bcrow, *bcptr, *bccol;
     const double *dlr, *dlc, *dd, *dcval, *bcval;

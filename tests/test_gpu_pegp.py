@@ -1,6 +1,8 @@
 """GPU checks of the PEGP preconditioner (Sec. 3.1-3.2): z = P(mu) L_H~^+
 P(mu)^T r through the grounded, scaled system S = D L_H~ D factored on the
-host and solved on the device by one workgroup.
+host and solved on the device: the sparse levels of the factor by one
+workgroup, its dense tail (the last-eliminated rows) by blocked
+substitution over the whole device.
 
 The applied preconditioner is compared with the oracle's (scipy sparse
 products and a sparse LU of the same grounded, scaled matrix) in the
@@ -60,6 +62,42 @@ def test_pegp_apply_parity(oracle_lib, name):
     z0 = M.apply(r)
     spread = np.linalg.norm(M2.apply(r) - z0) / np.linalg.norm(z0)
     G = GpuLap(n, u, v, w, mu=mu, precond=lap.LAP_PREC_PEGP)
+    try:
+        z = G.apply_precond(r)
+    finally:
+        G.close()
+    err = np.linalg.norm(z - z0) / np.linalg.norm(z0)
+    say(name, "nt", M.nt, "rel err", err, "oracle ordering spread", spread)
+    assert err <= max(100 * spread, 1e-14)
+
+
+# Shapes of the dense tail on small grids (grid side, level setting):
+# the whole factor in the tail with no sparse level, no tail at all, one
+# superblock that is mostly padding, and one that is full but for two rows.
+TAIL_SHAPES = {
+    "grid2d_6_level_max_all_tail": (6, 0),
+    "grid2d_6_level2_no_tail": (6, 2),
+    "grid2d_8_level2_one_superblock": (8, 2),
+    "grid2d_12_level_max_one_full_superblock": (12, 0),
+}
+
+
+@pytest.mark.parametrize("name", list(TAIL_SHAPES))
+def test_pegp_apply_tail_shapes(oracle_lib, name):
+    """The same bar as above, on tails that the larger cases do not have."""
+    import paper_2207_07847_amd as lap
+    from oracle.pegp import PEGP
+    a, ml = TAIL_SHAPES[name]
+    n, u, v = W.grid2d(a)
+    w = W.unit_weights(len(u))
+    mu = n ** -0.25 if ml else 1.0 / a
+    g, h, M = _oracle_pegp(n, u, v, w, mu, ml)
+    M2 = PEGP(n, u, v, w, h.aggs(), mu, permc_spec="MMD_AT_PLUS_A")
+    r = np.random.default_rng(22).standard_normal(n)
+    r -= r.mean()
+    z0 = M.apply(r)
+    spread = np.linalg.norm(M2.apply(r) - z0) / np.linalg.norm(z0)
+    G = GpuLap(n, u, v, w, mu=mu, precond=lap.LAP_PREC_PEGP, max_levels=ml)
     try:
         z = G.apply_precond(r)
     finally:
