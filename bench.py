@@ -629,6 +629,12 @@ def main():
             "traffic": pmc_traffic(args.workload, args.scale) if args.precision == "fp64" else None,
         },
     }
+    if wl["precond"] == "pegp":
+        line["roofline"]["note"] = (
+            "the SpMV is a small part of a PEGP iteration: its time is in the "
+            "preconditioner's level and dense-tail solves, chains of dependent "
+            "steps bound by latency (per-kernel times in "
+            "profiles/k_pegp_grid2d_64_kernel_trace.txt)")
     if args.nrhs > 1:
         k = 1 if args.precision != "fp64" else 0
         line["autotuned"] = {"spmm_entries_per_item": info["mm_chunk"][k],
