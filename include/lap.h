@@ -38,7 +38,7 @@ typedef enum {
     LAP_EDEVICE = 4,        /* HIP runtime error, or no device */
     LAP_ENOCONV = 5,        /* max_iter reached; x and info still written */
     LAP_EBREAKDOWN = 6,     /* p^T L p <= 0 or a non-finite value */
-    LAP_EUNSUPPORTED = 7    /* valid but not supported by this build */
+    LAP_EUNSUPPORTED = 7    /* valid, but a combination the library does not support */
 } lap_status;
 
 typedef enum {
