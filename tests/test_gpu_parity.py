@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Bars (the benchmark spec): PCG iteration counts within +-1; the GPU iterate within
+Bars: PCG iteration counts within +-1; the GPU iterate within
 1e-7 (relative 2-norm) of the oracle's iterate after the same number of
 iterations; true relative residual <= tol.  Kernel-level checks compare
 L x and the preconditioner M r element by element.
