@@ -966,7 +966,7 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(h->So, h->stage, sizeof(Scal), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    // Iterations per captured chunk.  The driver keeps one chunk in flight
+    // Iterations per captured chunk.  The PCG loop keeps one chunk in flight
     // beyond the one it checks, so up to two chunks run past convergence as
     // iterations that return at once; each still costs its dispatches.  A
     // PEGP iteration is about 30 dispatches and a few hundred microseconds,
