@@ -35,7 +35,8 @@ PRECOND_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_
 
 class _PcgInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("status", C.c_int32),
-                ("relres_recursive", C.c_double), ("relres_true", C.c_double)]
+                ("relres_recursive", C.c_double), ("relres_true", C.c_double),
+                ("restarts", C.c_int32), ("pad", C.c_int32)]
 
 
 def build(force: bool = True) -> str:
@@ -101,6 +102,9 @@ def lib():
     L.lr_pcg_noisy.argtypes = [vp, vp, vp, _f64p, C.c_double, C.c_int32, _f64p,
                                C.POINTER(_PcgInfo), vp, C.c_double, C.c_uint64]
     L.lr_pcg_noisy.restype = C.c_int
+    L.lr_pcg_ex.argtypes = [vp, vp, vp, _f64p, C.c_double, C.c_int32, _f64p,
+                            C.POINTER(_PcgInfo), vp, C.c_double, C.c_uint64, C.c_int32]
+    L.lr_pcg_ex.restype = C.c_int
     _lib = L
     return L
 
@@ -279,13 +283,20 @@ class PcgResult:
         self.status = int(info.status)
         self.relres_recursive = float(info.relres_recursive)
         self.relres_true = float(info.relres_true)
+        self.restarts = int(info.restarts)
         self.hist = hist[: self.iterations + 1]
 
 
-def pcg(g: Graph, b, tol=1e-8, maxit=1000, precond=None, noise=0.0, seed=0):
+MAX_RESTARTS = 3   # residual replacements after a converged recurrence (Sec. 4 stop rule)
+
+
+def pcg(g: Graph, b, tol=1e-8, maxit=1000, precond=None, noise=0.0, seed=0,
+        restarts=MAX_RESTARTS):
     """PCG on L_G x = b.  precond: None (plain CG), an MSP, or a callable
     r -> z on numpy arrays (e.g. the PEGP of oracle.pegp).  noise > 0 runs
-    the rounding model of lr_pcg_noisy."""
+    the rounding model of lr_pcg_noisy.  restarts: residual replacements
+    allowed when the recurrence converges with a true residual above tol
+    (lr_pcg_ex)."""
     L = lib()
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.empty(g.n)
@@ -306,7 +317,7 @@ def pcg(g: Graph, b, tol=1e-8, maxit=1000, precond=None, noise=0.0, seed=0):
 
         keep = PRECOND_FN(_cb)
         fn, ctx = C.cast(keep, C.c_void_p), None
-    L.lr_pcg_noisy(g.handle, fn, ctx, b, float(tol), int(maxit), x, C.byref(info),
-                   hist.ctypes.data, float(noise), int(seed))
+    L.lr_pcg_ex(g.handle, fn, ctx, b, float(tol), int(maxit), x, C.byref(info),
+                hist.ctypes.data, float(noise), int(seed), int(restarts))
     del keep
     return PcgResult(x, info, hist)

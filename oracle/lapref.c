@@ -723,6 +723,13 @@ static void remove_mean(int64_t n, double *a)
  *           alpha = rho/pq; x += alpha p; r -= alpha q;
  *           stop if ||r|| <= tol ||b^|| (iterations = products with L);
  *           z = M r - mean; rho' = r.z; beta = rho'/rho; p = z + beta p.
+ * Sec. 4 stops on the residual of the original system, which the
+ * recurrence only tracks: once the recursive residual meets tol, x is made
+ * mean-free and the true residual t = b^ - L x is formed.  If ||t|| is
+ * still above tol ||b^||, the iteration restarts from x with r = t - mean(t),
+ * z = M r - mean, p = z (a residual replacement) and continues under the
+ * same stop rule and the same cap on products with L.  After max_restarts
+ * replacements a true residual above tol ends the run with LR_ENOCONV.
  *   x -= mean(x); report ||b^ - L x|| / ||b^||.
  * relres_hist (optional, maxit+1 entries) receives ||r_k||/||b^||. */
 /* Rounding model for parity bands: with noise > 0 every product L p and
@@ -743,12 +750,43 @@ int lr_pcg(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
            double tol, int32_t maxit, double *x, lr_pcg_info *info,
            double *relres_hist)
 {
-    return lr_pcg_noisy(g, M, ctx, b, tol, maxit, x, info, relres_hist, 0.0, 0);
+    return lr_pcg_ex(g, M, ctx, b, tol, maxit, x, info, relres_hist, 0.0, 0,
+                     LR_MAX_RESTARTS);
 }
 
 int lr_pcg_noisy(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
                  double tol, int32_t maxit, double *x, lr_pcg_info *info,
                  double *relres_hist, double noise, uint64_t seed)
+{
+    return lr_pcg_ex(g, M, ctx, b, tol, maxit, x, info, relres_hist, noise, seed,
+                     LR_MAX_RESTARTS);
+}
+
+/* z = M r - mean (or r - mean without a preconditioner), perturbed by the
+ * rounding model when noise > 0; returns r.z. */
+static double precondition(int64_t n, lr_precond_fn M, void *ctx, const double *r,
+                           double *z, double noise, uint64_t *st)
+{
+    if (M) M(ctx, r, z);
+    else memcpy(z, r, sizeof(double) * (size_t)n);
+    if (noise > 0.0) perturb(n, z, noise, st);
+    remove_mean(n, z);
+    return dot(n, r, z);
+}
+
+/* t = b^ - L x after x -= mean(x); returns ||t||. */
+static double true_residual(const lr_csr *g, const double *bh, double *x, double *t)
+{
+    int64_t n = g->n;
+    remove_mean(n, x);
+    lr_lap_apply(g, x, t);
+    for (int64_t i = 0; i < n; ++i) t[i] = bh[i] - t[i];
+    return sqrt(dot(n, t, t));
+}
+
+int lr_pcg_ex(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
+              double tol, int32_t maxit, double *x, lr_pcg_info *info,
+              double *relres_hist, double noise, uint64_t seed, int32_t max_restarts)
 {
     uint64_t st = seed;
     int64_t n = g->n;
@@ -764,19 +802,15 @@ int lr_pcg_noisy(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
         x[i] = 0.0;
         r[i] = bh[i];
     }
-    int32_t it = 0;
+    int32_t it = 0, restarts = 0;
     int status = LR_ENOCONV;
     double rn = nb;
     if (relres_hist) relres_hist[0] = nb > 0.0 ? 1.0 : 0.0;
     if (nb == 0.0) {
         status = LR_OK;
     } else {
-        if (M) M(ctx, r, z);
-        else memcpy(z, r, sizeof(double) * (size_t)n);
-        if (noise > 0.0) perturb(n, z, noise, &st);
-        remove_mean(n, z);
+        double rho = precondition(n, M, ctx, r, z, noise, &st);
         memcpy(p, z, sizeof(double) * (size_t)n);
-        double rho = dot(n, r, z);
         while (it < maxit) {
             lr_lap_apply(g, p, q);
             if (noise > 0.0) perturb(n, q, noise, &st);
@@ -794,27 +828,37 @@ int lr_pcg_noisy(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
             rn = sqrt(dot(n, r, r));
             if (relres_hist) relres_hist[it] = rn / nb;
             if (rn <= tol * nb) {
-                status = LR_OK;
-                break;
+                /* the recurrence has converged: check the true residual */
+                double tn = true_residual(g, bh, x, q);
+                if (tn <= tol * nb) {
+                    status = LR_OK;
+                    break;
+                }
+                if (restarts == max_restarts) {
+                    status = LR_ENOCONV;
+                    break;
+                }
+                ++restarts;
+                memcpy(r, q, sizeof(double) * (size_t)n);
+                remove_mean(n, r);
+                rn = sqrt(dot(n, r, r));
+                rho = precondition(n, M, ctx, r, z, noise, &st);
+                memcpy(p, z, sizeof(double) * (size_t)n);
+                continue;
             }
-            if (M) M(ctx, r, z);
-            else memcpy(z, r, sizeof(double) * (size_t)n);
-            if (noise > 0.0) perturb(n, z, noise, &st);
-            remove_mean(n, z);
-            double rho2 = dot(n, r, z);
+            double rho2 = precondition(n, M, ctx, r, z, noise, &st);
             double beta = rho2 / rho;
             rho = rho2;
             for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         }
     }
-    remove_mean(n, x);
-    lr_lap_apply(g, x, q);
-    for (int64_t i = 0; i < n; ++i) q[i] = bh[i] - q[i];
+    double tn = true_residual(g, bh, x, q);
     if (info) {
         info->iterations = it;
         info->status = status;
+        info->restarts = restarts;
         info->relres_recursive = nb > 0.0 ? rn / nb : 0.0;
-        info->relres_true = nb > 0.0 ? sqrt(dot(n, q, q)) / nb : 0.0;
+        info->relres_true = nb > 0.0 ? tn / nb : 0.0;
     }
     free(bh);
     free(r);

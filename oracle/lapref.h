@@ -99,11 +99,16 @@ void lr_msp_solve_expanded(const lr_msp *f, const double *bt, double *y);
 /* Preconditioned CG on L_G x = b (see lr_pcg for the exact steps). */
 typedef void (*lr_precond_fn)(void *ctx, const double *r, double *z);
 typedef struct {
-    int32_t iterations;        /* number of products with L_G */
+    int32_t iterations;        /* number of products with L_G (all restarts) */
     int32_t status;            /* LR_OK, LR_ENOCONV, LR_EBREAKDOWN */
     double relres_recursive;   /* ||r_k|| / ||b - mean(b)|| */
     double relres_true;        /* ||b^ - L x|| / ||b^|| after projection */
+    int32_t restarts;          /* residual replacements after a converged
+                                  recurrence whose true residual was above tol */
+    int32_t pad;
 } lr_pcg_info;
+/* Residual replacements lr_pcg and lr_pcg_noisy allow (Sec. 4 stop rule). */
+#define LR_MAX_RESTARTS 3
 int lr_pcg(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
            double tol, int32_t maxit, double *x, lr_pcg_info *info,
            double *relres_hist);
@@ -113,6 +118,11 @@ int lr_pcg(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
 int lr_pcg_noisy(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
                  double tol, int32_t maxit, double *x, lr_pcg_info *info,
                  double *relres_hist, double noise, uint64_t seed);
+/* Same, with the number of residual replacements given (0: none; the
+ * status is then LR_ENOCONV whenever the true residual misses tol). */
+int lr_pcg_ex(const lr_csr *g, lr_precond_fn M, void *ctx, const double *b,
+              double tol, int32_t maxit, double *x, lr_pcg_info *info,
+              double *relres_hist, double noise, uint64_t seed, int32_t max_restarts);
 
 #ifdef __cplusplus
 }

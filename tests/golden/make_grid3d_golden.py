@@ -1,0 +1,115 @@
+"""Write the oracle's reference solves of the 3D grid workload family.
+
+The workload: a 7-point a x a x a grid with edge weights 10^U(-3,3) and a
+mean-zero Gaussian right-hand side (the seeds of ``workloads``), solved by
+MSP-preconditioned CG at mu = 0.8, tol 1e-8, level max (Sec. 3.3, Sec. 4).
+For each size this records, from the oracle only:
+
+  * the converged solve: iterations, residual replacements, status, the
+    recursive and true relative residuals, ||x||_2 and x at a fixed seeded
+    sample of vertices;
+  * checkpoints: the iterate after k iterations (tol 0, so no stop and no
+    replacement) at the same sample, and its recursive residual, so that a
+    GPU run capped at k iterations can be compared at the same count;
+  * for the smaller sizes, the iteration band of the oracle's rounding model
+    (``oracle.iteration_band``: the unperturbed run and eight runs with
+    relative noise 4e-16 on L p and M r).
+
+Run from the repository root:  python tests/golden/make_grid3d_golden.py [a ...]
+(default 40 48 128; 128 takes about 70 minutes of one core for the
+converged solve).  Output: tests/golden/grid3d_<a>_mu08.json.
+"""
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+MU, TOL, MAXIT = 0.8, 1e-8, 60000
+SAMPLE = 4096
+CHECKPOINTS = {40: [100, 1000], 48: [100, 1000], 128: [100, 1000, 5000]}
+BAND = {40, 48}
+SEEDS = 8
+NOISE = 4e-16
+
+
+def sample_index(n):
+    rng = np.random.default_rng(W.MASTER_SEED + 77)
+    if n <= SAMPLE:
+        return np.arange(n)
+    return np.sort(rng.choice(n, size=SAMPLE, replace=False))
+
+
+def _problem(a):
+    from oracle import MSP, Graph, Hierarchy
+    n, u, v, w = W.config_graph("grid3d_128", a / 128)
+    b = W.gaussian_rhs(n, W.MASTER_SEED + 3)
+    g = Graph(n, u, v, w)
+    h = Hierarchy(g)
+    return n, b, g, h, MSP(h, MU)
+
+
+def task(job):
+    from oracle import pcg
+    a, kind, arg = job
+    t0 = time.time()
+    n, b, g, h, M = _problem(a)
+    idx = sample_index(n)
+    if kind == "final":
+        r = pcg(g, b, TOL, MAXIT, M)
+        out = dict(iterations=r.iterations, restarts=r.restarts, status=r.status,
+                   relres_recursive=r.relres_recursive, relres_true=r.relres_true,
+                   xnorm=float(np.linalg.norm(r.x)), x=[float(t) for t in r.x[idx]],
+                   nlev=h.nlev, n=n)
+    elif kind == "ck":
+        r = pcg(g, b, 0.0, arg, M)
+        out = dict(k=arg, relres_recursive=r.relres_recursive, relres_true=r.relres_true,
+                   xnorm=float(np.linalg.norm(r.x)), x=[float(t) for t in r.x[idx]])
+    else:
+        r = pcg(g, b, TOL, MAXIT, M, noise=NOISE, seed=arg)
+        out = dict(seed=arg, iterations=r.iterations)
+    print(f"grid3d {a}: {kind} {arg} done in {time.time() - t0:.0f} s", flush=True)
+    return a, kind, arg, out
+
+
+def main(sizes):
+    jobs = []
+    for a in sizes:
+        jobs.append((a, "final", 0))
+        jobs += [(a, "ck", k) for k in CHECKPOINTS.get(a, [100])]
+        if a in BAND:
+            jobs += [(a, "band", s) for s in range(1, SEEDS + 1)]
+    res = {a: dict(checkpoints=[], band_runs=[]) for a in sizes}
+    with mp.get_context("fork").Pool(min(7, len(jobs))) as pool:
+        for a, kind, arg, out in pool.imap_unordered(task, jobs):
+            if kind == "final":
+                res[a].update(out)
+            elif kind == "ck":
+                res[a]["checkpoints"].append(out)
+            else:
+                res[a]["band_runs"].append(out["iterations"])
+    for a in sizes:
+        d = res[a]
+        d["checkpoints"].sort(key=lambda c: c["k"])
+        d.update(workload=f"grid3d {a}^3, weights 10^U(-3,3) seed MASTER_SEED+2, "
+                 "Gaussian rhs seed MASTER_SEED+3",
+                 mu=MU, tol=TOL, maxit=MAXIT, sample_seed=W.MASTER_SEED + 77,
+                 sample_size=len(sample_index(d["n"])))
+        if d["band_runs"]:
+            its = [d["iterations"]] + d["band_runs"]
+            d["band"] = [min(its), max(its)]
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"grid3d_{a}_mu08.json")
+        with open(path, "w") as f:
+            json.dump(d, f, indent=0)
+        print("wrote", path, flush=True)
+
+
+if __name__ == "__main__":
+    main([int(t) for t in sys.argv[1:]] or [40, 48, 128])
