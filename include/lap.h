@@ -1,9 +1,12 @@
 /*
  * lap.h - C ABI of the MI355X (gfx950) Laplacian solver: preconditioned
  * conjugate gradients on a weighted graph Laplacian L_G, preconditioned by
- * the multilevel sparsifier preconditioner (MSP) of Hu & Lin, "Solving Graph
- * Laplacians via Multilevel Sparsifiers" (arXiv 2207.07847), Sec. 3.3, or
- * left unpreconditioned.
+ * the multilevel sparsifier preconditioner (MSP, Sec. 3.3) or the
+ * positively-weighted expanded graph preconditioner (PEGP, Sec. 3.2) of
+ * Hu & Lin, "Solving Graph Laplacians via Multilevel Sparsifiers"
+ * (arXiv 2207.07847), or left unpreconditioned.  Both preconditioners are
+ * applied through the lifting of Sec. 3.1: M = P(mu) S^+ P(mu)^T, S the
+ * sparsifier of the expanded graph (the tree T~ for MSP, H~ for PEGP).
  *
  * Problem (Sec. 1, Sec. 2.1): G = (E, V, w) simply connected with positive
  * weights, L_G = B^T W B symmetric positive semidefinite with null space
@@ -43,7 +46,10 @@ typedef enum {
 
 typedef enum {
     LAP_PREC_MSP = 0,       /* multilevel sparsifier preconditioner, Sec. 3.3 */
-    LAP_PREC_PEGP = 1,      /* positive expanded graph, Sec. 3.2 (reserved) */
+    LAP_PREC_PEGP = 1,      /* positively-weighted expanded graph, Sec. 3.2:
+                               FP64 single right-hand-side solves only, and
+                               expanded graphs of at most 19,456 nodes (the
+                               sum of all level sizes) in at most 64 levels */
     LAP_PREC_NONE = 2       /* plain conjugate gradients */
 } lap_precond;
 
@@ -83,7 +89,11 @@ typedef enum {
                                   LAP_PREC_NONE or mixed precision.
                                   info.iterations counts products with L_G~,
                                   info.relres_recursive is the expanded
-                                  residual estimate. */
+                                  residual estimate.  LAP_OK means the
+                                  expanded residual met tol (the stop test
+                                  of Sec. 4); info.relres_true reports the
+                                  residual of the original system as
+                                  measured, which may lie above tol. */
 
 /* Undirected weighted graph, host memory, edges (u[e], v[e], w[e]).
  * Requirements: n >= 2; 0 <= u, v < n; u != v; w finite and > 0.
@@ -109,7 +119,8 @@ typedef struct {
 
 typedef struct {
     int32_t iterations;        /* products with L_G performed */
-    int32_t refinements;       /* outer refinement steps (0 for FP64) */
+    int32_t refinements;       /* mixed precision: refinement steps; FP64
+                                  PCG: residual replacements taken (0..3) */
     double relres_true;        /* ||b^ - L_G x|| / ||b^|| in FP64, b^ = b - mean(b) */
     double relres_recursive;   /* ||r_k|| / ||b^|| of the PCG recurrence */
     double seconds;            /* host wall time of the call */
@@ -158,7 +169,10 @@ lap_status lap_default_params(lap_params *p);
  * On success *out owns the hierarchy.  Errors: LAP_EINVAL (bad graph or
  * params: mu outside (0,1), n_top < 2, unknown precond/precision),
  * LAP_EDISCONNECTED, LAP_ENOMEM, LAP_EDEVICE, LAP_EUNSUPPORTED (top level
- * larger than the on-chip coarse solve allows, or PEGP requested). */
+ * larger than the on-chip coarse solve allows; PEGP with mixed precision,
+ * with LAP_FLAG_MULTI_RHS, or with an expanded graph above 19,456 nodes or
+ * 64 levels).  PEGP (Sec. 3.2) factors the grounded, level-scaled
+ * L_H~ once on the host (sparse LDL^T) and applies it on the device. */
 lap_status lap_setup(const lap_graph *g, const lap_params *p, void *stream,
                      lap_hierarchy **out);
 
@@ -166,10 +180,20 @@ lap_status lap_setup(const lap_graph *g, const lap_params *p, void *stream,
  * system; the Theorem of Sec. 3.1 maps it back).  b, x: device arrays of
  * nrhs columns with leading dimension ld >= n (column c at b + c*ld),
  * original vertex order.  x is overwritten with the mean-free solution.
- * Stops when ||r_k|| <= tol ||b^||.  info: host array of nrhs entries (may
- * be NULL).  Returns the worst per-column status: LAP_ENOCONV when
- * max_iter is reached, LAP_EBREAKDOWN, LAP_EINVAL (tol <= 0, nrhs < 1,
- * ld < n, non-finite b), LAP_EDEVICE.
+ * info: host array of nrhs entries (may be NULL).
+ *
+ * FP64 PCG stops when the recursive residual meets ||r_k|| <= tol ||b^||;
+ * then the true residual t = b^ - L x of the mean-free x is formed in FP64
+ * (Sec. 4 stops on the residual of the original system).  If ||t|| is
+ * still above tol ||b^||, PCG restarts from x with r = t - mean(t) (a
+ * residual replacement; at most 3, all within max_iter products with L).
+ * LAP_OK therefore means info->relres_true <= tol.  info->iterations counts
+ * products with L over all restarts, info->refinements the replacements.
+ *
+ * Returns the worst per-column status: LAP_ENOCONV when max_iter is
+ * reached or the true residual misses tol after the last replacement (x
+ * and info are still written), LAP_EBREAKDOWN, LAP_EINVAL (tol <= 0,
+ * nrhs < 1, ld < n, non-finite b), LAP_EDEVICE.
  *
  * Mixed precision (LAP_MIXED_FP32_FP64): x and r = b^ - L x are kept in
  * FP64; one PCG run with FP32 vectors, FP32 SpMV and FP32 preconditioner
@@ -196,9 +220,14 @@ lap_status lap_set_precision(lap_hierarchy *h, int32_t precision);
 lap_status lap_apply_laplacian(lap_hierarchy *h, const double *x, double *y,
                                void *stream);
 
-/* z = M r - mean, the MSP preconditioner of Sec. 3.3 applied through the
- * lifting of Sec. 3.1: M = P(mu) L_T~^+ P(mu)^T.  r must be mean-free (a
- * residual).  Device arrays, original order. */
+/* z = M r - mean, the hierarchy's preconditioner applied through the
+ * lifting of Sec. 3.1: M = P(mu) L_T~^+ P(mu)^T for MSP (Sec. 3.3, in the
+ * closed form of its tree elimination), M = P(mu) L_H~^+ P(mu)^T for PEGP
+ * (Sec. 3.2, by the grounded factor).  r must be mean-free (a residual).
+ * Device arrays of n values, original order; r is read, z written.  Uses
+ * the hierarchy's solve workspace.  A mixed-precision hierarchy applies
+ * its FP32 form.  Errors: LAP_EINVAL (NULL), LAP_EUNSUPPORTED (host-only),
+ * LAP_EDEVICE. */
 lap_status lap_apply_precond(lap_hierarchy *h, const double *r, double *z,
                              void *stream);
 
@@ -209,7 +238,10 @@ lap_status lap_apply_precond(lap_hierarchy *h, const double *r, double *z,
  * the part is timed in the cache state of a real solve.  Returns the
  * average milliseconds of the part and the algorithmic HBM bytes it must
  * move (FP64 values, int32 indices, each datum counted once):
- *   LAP_KERNEL_SPMV     p update + q = L p + p^T q   (32 n + 12 nnz bytes)
+ *   LAP_KERNEL_SPMV     p update + q = L p + p^T q, with the previous
+ *                       iteration's x step riding along (48 n + 12 nnz
+ *                       bytes: z, p_old, x read, p, q, x written, and col,
+ *                       w of the matrix)
  *   LAP_KERNEL_UPDATE   x, r update + level-0 restriction and pair solves
  *   LAP_KERNEL_DOWN0    level-0 prolongation + z, r^T z reductions
  *   LAP_KERNEL_PRECOND  update through down0: the x, r update and the

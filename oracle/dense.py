@@ -165,3 +165,55 @@ def stretch(T, H):
                 e[i], e[j] = 1.0, -1.0
                 total += -H[i, j] * (e @ Tp @ e)
     return total
+
+
+def msp_apply_highprec(n, u, v, w, aggs, mu, r, dps=50):
+    """z = P(mu) pinv(L_T~) P(mu)^T r - mean(.), every step of the
+    definition carried out densely in mpmath at `dps` digits: P(mu)
+    (Sec. 2.2), L_G~ = P(mu)^T L_G P(mu), H~ its positively weighted edges
+    (Sec. 3.2), T~ the MSP edges of H~ (Sec. 3.3, same reading as
+    msp_from_h), pinv(L) = (L + J/t)^(-1) - J/t for the connected T~ with t
+    nodes (J the all-ones matrix).  For tiny graphs only (the expanded
+    graph's size cubed mpmath operations): a reference whose rounding is far
+    below FP64, for checking FP64 evaluations at any mu."""
+    import mpmath as mpm
+    ctx = mpm.mp.clone()
+    ctx.dps = dps
+    mu_ = ctx.mpf(mu)
+    sizes = level_sizes(aggs, n)
+    nt = sum(sizes)
+    # sign pattern of H~ and the MSP edge mask come from the FP64 objects
+    # (which entries are kept is structural, App.: ancestor links positive
+    # iff the level gap is odd); the values are recomputed in mpmath
+    Pm64 = p_mu(aggs, n, float(mu))
+    Gt64 = expanded(laplacian(n, u, v, w), Pm64)
+    T64 = msp_from_h(positive_subgraph(Gt64), aggs, sizes)
+    keep = (T64 != 0.0) & ~np.eye(nt, dtype=bool)
+    Ps = composite(aggs, n)
+    Pm = ctx.zeros(n, nt)
+    col = 0
+    for k, P in enumerate(Ps):
+        f = (-mu_) ** k
+        for i, j in zip(*np.nonzero(P)):
+            Pm[int(i), col + int(j)] = f
+        col += P.shape[1]
+    Lg = ctx.zeros(n, n)
+    for a, b, c in zip(u, v, w):
+        c = ctx.mpf(float(c))
+        a, b = int(a), int(b)
+        Lg[a, a] += c
+        Lg[b, b] += c
+        Lg[a, b] -= c
+        Lg[b, a] -= c
+    Gt = Pm.T * Lg * Pm
+    T = ctx.zeros(nt, nt)
+    for i, j in zip(*np.nonzero(keep)):
+        T[int(i), int(j)] = Gt[int(i), int(j)]
+    for i in range(nt):
+        T[i, i] = -ctx.fsum(T[i, j] for j in range(nt) if j != i)
+    J = ctx.ones(nt, nt) / nt
+    Tp = ctx.inverse(T + J) - J
+    rm = ctx.matrix([ctx.mpf(float(t)) for t in r])
+    z = Pm * (Tp * (Pm.T * rm))
+    mean = ctx.fsum(z[i] for i in range(n)) / n
+    return np.array([float(z[i] - mean) for i in range(n)])

@@ -3,9 +3,11 @@ advanced together, each with its own PCG scalars and stop test.
 
 Every column must meet what a single solve promises: FP64 true residual
 <= tol, recomputed on the host with the oracle's L, and a mean-free x.  On
-a graph small enough for a dense spectrum, each column is also within the
-bound kappa(L) * tol of the oracle's solution at 1e-13.  Columns that are
-zero converge at once; a non-finite column is rejected.
+a small weighted graph every column is also within 1e-7 (relative 2-norm)
+of the oracle's solution at tol 1e-13, the solution bar of the single
+solves (any iterate with relative residual tol lies within kappa(L) tol of
+it; the GPU's are far closer).  Columns that are zero converge at once; a
+non-finite column is rejected.
 """
 import numpy as np
 import pytest
@@ -69,9 +71,10 @@ def test_block_residuals(oracle_lib, name, precision):
     assert np.all(np.abs(X.mean(axis=1)) <= 1e-12 * np.abs(X).max(axis=1))
 
 
-def test_block_matches_single_solves(oracle_lib):
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_block_matches_single_solves(oracle_lib, precision):
     """Each column of a block solve against the oracle solution at 1e-13,
-    within kappa * tol (dense spectrum, small graph)."""
+    within 1e-7 (and the kappa * tol bound, reported)."""
     import paper_2207_07847_amd as lap
     from oracle import MSP, Graph, Hierarchy, pcg
     from oracle.dense import laplacian
@@ -82,7 +85,8 @@ def test_block_matches_single_solves(oracle_lib):
     M = MSP(Hierarchy(g), 0.8)
     ev = np.linalg.eigvalsh(laplacian(n, u, v, w))
     kappa = ev[-1] / ev[1]
-    G = GpuLap(n, u, v, w, mu=0.8, precision=lap.LAP_MIXED_FP32_FP64, max_iter=20000,
+    prec = lap.LAP_MIXED_FP32_FP64 if precision == "mixed" else lap.LAP_FP64
+    G = GpuLap(n, u, v, w, mu=0.8, precision=prec, max_iter=20000,
                flags=lap.LAP_FLAG_MULTI_RHS)
     try:
         st, X, info = G.solve_many(B, 1e-8)
@@ -94,8 +98,9 @@ def test_block_matches_single_solves(oracle_lib):
         ref = pcg(g, B[c], 1e-13, 20000, M)
         d = np.linalg.norm(X[c] - ref.x) / np.linalg.norm(ref.x)
         worst = max(worst, d)
-    say("block vs oracle: worst diff", worst, "kappa*tol", kappa * 1e-8)
-    assert worst <= kappa * 1.01e-8
+    msg = f"block {precision} vs oracle: worst diff {worst:.3e}, kappa*tol {kappa * 1e-8:.3e}"
+    say(msg)
+    assert worst <= 1e-7, msg
 
 
 def test_block_ragged_columns_and_ld(oracle_lib):

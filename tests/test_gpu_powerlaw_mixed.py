@@ -7,15 +7,17 @@ stages in LDS, and hubs inside the one-block coarse tail.
 
 Mixed precision (iterative refinement with an FP32 inner PCG) is checked
 by what it promises: the FP64 true residual <= tol, recomputed on the host
-with the oracle's L; and, on graphs small enough for a dense spectrum, the
-distance to the oracle's solution at 1e-12 within the bound that any
-iterate with that residual satisfies, kappa(L) * tol (on range(L):
-||x - x*|| <= ||L^+|| ||r|| and ||x*|| >= ||b^|| / ||L||).
+with the oracle's L; and the distance to the oracle's solution at tol 1e-13
+within 1e-7 relative, the solution bar of the FP64 solves (any iterate with
+relative residual tol lies within kappa(L) tol of it, which is reported
+beside it).  The FP32 preconditioner is compared with the oracle's FP64
+closed form at ten times its measured error.
 """
 import numpy as np
 import pytest
 
 import workloads as W
+from cases import hub_case
 from gpu_util import GpuLap, say
 
 pytestmark = pytest.mark.gpu
@@ -70,29 +72,48 @@ def test_precond_big_aggregates(oracle_lib, make):
         z = G.apply_precond(r)
     finally:
         G.close()
+    from oracle.msp_closed import closed_form
     z0 = MSP(h, 0.8).apply(r)
+    zc = closed_form(h, 0.8)(r)
     err = np.linalg.norm(z - z0) / np.linalg.norm(z0)
+    err_c = np.linalg.norm(z - zc) / np.linalg.norm(zc)
     tol = 1e-10 + 1e3 * np.finfo(float).eps * 0.8 ** (-2.0 * (h.nlev - 1))
-    say("precond", n, "levels", h.nlev, "rel err", err, "tol", tol)
-    assert err <= tol
+    msg = (f"precond {n}: levels {h.nlev} rel err vs closed form {err_c:.3e}, "
+           f"vs elimination {err:.3e} (bar {tol:.1e})")
+    say(msg)
+    assert err_c <= 1e-12 and err <= tol, msg
 
 
 def test_solve_hub_fp64(oracle_lib):
-    from oracle import MSP, pcg
-    n, u, v, w = _hub()
+    """Whole FP64 solve on the hub graph: iterations inside the stored
+    rounding band (widened by 1), iterate at the same count and solution
+    within 1e-7 of the oracle's (closed-form MSP), true residual <= tol."""
+    from oracle import pcg
+    from oracle.msp_closed import closed_form
+    from test_gpu_parity import iteration_band
+    n, u, v, w, mu, b = hub_case()
     g, h = _oracle(n, u, v, w)
-    b = W.gaussian_rhs(n, 72)
-    ref = pcg(g, b, 1e-8, 5000, MSP(h, 0.8))
-    G = GpuLap(n, u, v, w, mu=0.8, max_iter=5000)
+    M = closed_form(h, mu)
+    ref = pcg(g, b, 1e-8, 5000, M)
+    tight = pcg(g, b, 1e-13, 20000, M)
+    lo, hi = iteration_band("hub_21267")
+    G = GpuLap(n, u, v, w, mu=mu, max_iter=5000)
     try:
         st, x, info = G.solve(b, 1e-8)
     finally:
         G.close()
-    it, k = info["iterations"], ref.iterations
-    say("hub fp64: gpu", it, "oracle", k, info)
-    assert st == 0 and int(np.floor(0.70 * k)) - 1 <= it <= k + 1 + int(np.ceil(0.06 * k))
+    k = info["iterations"]
+    same = pcg(g, b, 0.0, k, M)
+    d_same = np.linalg.norm(x - same.x) / np.linalg.norm(same.x)
+    d_tight = np.linalg.norm(x - tight.x) / np.linalg.norm(tight.x)
     bh = b - b.mean()
-    assert np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh) <= 1.01e-8
+    host = np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh)
+    msg = (f"hub fp64: gpu {k} oracle {ref.iterations} band [{lo}, {hi}] relres "
+           f"{info['relres_true']:.3e} host {host:.3e}; diff same count {d_same:.2e}, "
+           f"tight {d_tight:.2e}")
+    say(msg)
+    assert st == 0 and lo <= k <= hi, msg
+    assert host <= 1.01e-8 and d_same <= 1e-7 and d_tight <= 1e-7, msg
 
 
 MIXED_CASES = {
@@ -147,15 +168,17 @@ def test_mixed_solution_within_kappa_bound(oracle_lib, seed):
     finally:
         G.close()
     diff = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
-    say("mixed vs oracle 1e-13:", info, "diff", diff, "kappa*tol", kappa * 1e-8)
-    assert st == 0 and diff <= kappa * 1.01e-8
+    msg = f"mixed vs oracle 1e-13: {info} diff {diff:.3e} kappa*tol {kappa * 1e-8:.3e}"
+    say(msg)
+    assert st == 0 and diff <= 1e-7, msg
 
 
 def test_mixed_precond_fp32(oracle_lib):
     """The FP32 preconditioner against the FP64 oracle: rounding of FP32
-    coefficients and arithmetic only (relative 2-norm)."""
+    coefficients and arithmetic only (relative 2-norm).  Measured 5.7e-8 on
+    this graph (14 levels); the bar is ten times that."""
     import paper_2207_07847_amd as lap
-    from oracle import MSP
+    from oracle.msp_closed import closed_form
     n, u, v, w, _ = MIXED_CASES["chunglu_40000"]()
     g, h = _oracle(n, u, v, w)
     G = GpuLap(n, u, v, w, mu=0.8, precision=lap.LAP_MIXED_FP32_FP64)
@@ -165,8 +188,9 @@ def test_mixed_precond_fp32(oracle_lib):
         z = G.apply_precond(r)
     finally:
         G.close()
-    z0 = MSP(h, 0.8).apply(r)
+    z0 = closed_form(h, 0.8)(r)
     err = np.linalg.norm(z - z0) / np.linalg.norm(z0)
-    tol = 1e3 * np.finfo(np.float32).eps * 0.8 ** (-2.0 * (h.nlev - 1))
-    say("fp32 precond: levels", h.nlev, "rel err", err, "tol", tol)
-    assert err <= tol
+    tol = 5.7e-7
+    msg = f"fp32 precond: levels {h.nlev} rel err {err:.3e} bar {tol:.1e}"
+    say(msg)
+    assert err <= tol, msg

@@ -1,0 +1,68 @@
+"""GPU checks of the FP64 stop rule on the original system (Sec. 4): when
+the recurrence meets tol, the true residual of the mean-free x is formed;
+above tol, PCG restarts from x on it (residual replacement), at most three
+times, and a true residual still above tol gives LAP_ENOCONV.
+
+The workload is the oracle's own pin of that rule (tests/test_oracle_restart.py):
+a weighted 32 x 32 grid at tol 1e-12, where the oracle's recurrence meets
+tol with a true residual about 5x above it.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import GpuLap, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _grid():
+    n, u, v = W.grid2d(32)
+    return n, u, v, W.loguniform_weights(len(u), 5), W.gaussian_rhs(n, 6)
+
+
+def test_tight_tolerance_meets_the_true_residual(oracle_lib):
+    from oracle import MSP, Graph, Hierarchy, pcg
+    n, u, v, w, b = _grid()
+    g = Graph(n, u, v, w)
+    ref = pcg(g, b, 1e-12, 20000, MSP(Hierarchy(g), 0.8))
+    G = GpuLap(n, u, v, w, mu=0.8, max_iter=20000)
+    try:
+        st, x, info = G.solve(b, 1e-12)
+    finally:
+        G.close()
+    bh = b - b.mean()
+    host = np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh)
+    d = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    msg = (f"tol 1e-12: gpu status {st} iterations {info['iterations']} replacements "
+           f"{info['refinements']} relres true {info['relres_true']:.3e} host {host:.3e}; "
+           f"oracle {ref.iterations} iterations, {ref.restarts} replacements; diff {d:.2e}")
+    say(msg)
+    assert st == 0 and ref.status == 0, msg
+    assert info["relres_true"] <= 1e-12 and host <= 1.05e-12, msg
+    assert 0 <= info["refinements"] <= 3, msg
+    assert d <= 1e-7, msg
+
+
+def test_unreachable_tolerance_is_not_reported_converged(oracle_lib):
+    """tol 1e-17 is below what FP64 can reach: the solve must end in
+    LAP_ENOCONV (replacements exhausted or max_iter), x still written."""
+    import paper_2207_07847_amd as lap
+    from oracle import MSP, Graph, Hierarchy, pcg
+    n, u, v, w, b = _grid()
+    g = Graph(n, u, v, w)
+    ref = pcg(g, b, 1e-17, 3000, MSP(Hierarchy(g), 0.8))
+    G = GpuLap(n, u, v, w, mu=0.8, max_iter=3000)
+    try:
+        st, x, info = G.solve(b, 1e-17)
+    finally:
+        G.close()
+    msg = (f"tol 1e-17: gpu status {st} iterations {info['iterations']} replacements "
+           f"{info['refinements']} relres true {info['relres_true']:.3e}; oracle status "
+           f"{ref.status} {ref.iterations} iterations, {ref.restarts} replacements")
+    say(msg)
+    assert st == lap.LAP_ENOCONV and ref.status != 0, msg
+    assert info["refinements"] == 3 or info["iterations"] >= 3000, msg
+    assert info["relres_true"] > 1e-17 and np.all(np.isfinite(x)), msg
+    bh = b - b.mean()
+    assert np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh) <= 1e-12, msg
