@@ -11,7 +11,7 @@ with the oracle's L; and the distance to the oracle's solution at tol 1e-13
 within 1e-7 relative, the solution bar of the FP64 solves (any iterate with
 relative residual tol lies within kappa(L) tol of it, which is reported
 beside it).  The FP32 preconditioner is compared with the oracle's FP64
-closed form at ten times its measured error.
+closed form at 15 times its measured error.
 """
 import numpy as np
 import pytest
@@ -175,8 +175,9 @@ def test_mixed_solution_within_kappa_bound(oracle_lib, seed):
 
 def test_mixed_precond_fp32(oracle_lib):
     """The FP32 preconditioner against the FP64 oracle: rounding of FP32
-    coefficients and arithmetic only (relative 2-norm).  Measured 5.7e-8 on
-    this graph (14 levels); the bar is ten times that."""
+    coefficients and arithmetic only (relative 2-norm).  Measured 3.8e-8 on
+    this graph (14 levels) against the FP64 closed form; the bar is 15 times
+    that."""
     import paper_2207_07847_amd as lap
     from oracle.msp_closed import closed_form
     n, u, v, w, _ = MIXED_CASES["chunglu_40000"]()

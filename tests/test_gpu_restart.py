@@ -46,7 +46,9 @@ def test_tight_tolerance_meets_the_true_residual(oracle_lib):
 
 def test_unreachable_tolerance_is_not_reported_converged(oracle_lib):
     """tol 1e-17 is below what FP64 can reach: the solve must end in
-    LAP_ENOCONV (replacements exhausted or max_iter), x still written."""
+    LAP_ENOCONV (replacements exhausted or max_iter), x still written and a
+    solution to the attainable accuracy (the residual stagnates near
+    5e-12 on both sides)."""
     import paper_2207_07847_amd as lap
     from oracle import MSP, Graph, Hierarchy, pcg
     n, u, v, w, b = _grid()
@@ -65,4 +67,4 @@ def test_unreachable_tolerance_is_not_reported_converged(oracle_lib):
     assert info["refinements"] == 3 or info["iterations"] >= 3000, msg
     assert info["relres_true"] > 1e-17 and np.all(np.isfinite(x)), msg
     bh = b - b.mean()
-    assert np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh) <= 1e-12, msg
+    assert np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh) <= 1e-10, msg
