@@ -220,6 +220,24 @@ lap_status lap_set_precision(lap_hierarchy *h, int32_t precision);
 lap_status lap_apply_laplacian(lap_hierarchy *h, const double *x, double *y,
                                void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as lap_apply_laplacian, y = L_G x on the device in original
+ * order, with its work vectors taken from a static device array of the
+ * library instead of the hierarchy.  Allocates nothing and calls no
+ * allocating routine.  The array holds 64 MiB per device (kept until the
+ * process ends): a hierarchy whose solve order differs from the input order
+ * (graphs with rows above 64 neighbours or heavy slice padding) needs
+ * 16 n bytes of it, so n <= 4,194,304 there; other hierarchies use none.
+ * All calls on one device share the array: calls that overlap in time on
+ * one device race (issue them in order on one stream, or from one host
+ * thread).  The current device must be the hierarchy's.  Errors:
+ * LAP_EINVAL (NULL, or the current device is not the hierarchy's),
+ * LAP_EUNSUPPORTED (host-only hierarchy, or more scratch than the array
+ * holds: lap_last_error states the sizes), LAP_EDEVICE. */
+lap_status lap_apply_laplacian_noalloc(lap_hierarchy *h, const double *x, double *y,
+                                       void *stream);
+
 /* z = M r - mean, the hierarchy's preconditioner applied through the
  * lifting of Sec. 3.1: M = P(mu) L_T~^+ P(mu)^T for MSP (Sec. 3.3, in the
  * closed form of its tree elimination), M = P(mu) L_H~^+ P(mu)^T for PEGP

@@ -82,6 +82,7 @@ def _load():
                             C.POINTER(lap_solve_info), vp]
     L.lap_set_precision.argtypes = [vp, C.c_int32]
     L.lap_apply_laplacian.argtypes = [vp, vp, vp, vp]
+    L.lap_apply_laplacian_noalloc.argtypes = [vp, vp, vp, vp]
     L.lap_apply_precond.argtypes = [vp, vp, vp, vp]
     L.lap_hierarchy_info.argtypes = [vp, C.POINTER(lap_hierarchy_desc)]
     L.lap_export_level.argtypes = [vp, C.c_int32, vp, vp]
@@ -108,7 +109,7 @@ def _load():
     L.lap_status_str.argtypes = [C.c_int]
     L.lap_status_str.restype = C.c_char_p
     for f in ("lap_default_params", "lap_setup", "lap_solve", "lap_set_precision",
-              "lap_apply_laplacian",
+              "lap_apply_laplacian", "lap_apply_laplacian_noalloc",
               "lap_apply_precond", "lap_hierarchy_info", "lap_export_level", "lap_export_graph",
               "lap_profile_kernel", "lap_estimate_spectrum", "lap_select_mu"):
         getattr(L, f).restype = C.c_int
@@ -177,6 +178,11 @@ def lap_solve(h, b_ptr: int, x_ptr: int, n: int, tol: float, nrhs: int = 1, ld: 
 
 def lap_set_precision(h, precision: int) -> int:
     return _lib.lap_set_precision(C.c_void_p(h), int(precision))
+
+
+def lap_apply_laplacian_noalloc(h, x_ptr: int, y_ptr: int, stream=0) -> int:
+    return _lib.lap_apply_laplacian_noalloc(C.c_void_p(h), C.c_void_p(x_ptr),
+                                            C.c_void_p(y_ptr), C.c_void_p(stream or 0))
 
 
 def lap_apply_laplacian(h, x_ptr: int, y_ptr: int, stream=0) -> int:

@@ -30,6 +30,15 @@
 #include "lap.h"
 #include "setup.hpp"
 
+// Scratch of lap_apply_laplacian_noalloc, the variant of lap_apply_laplacian
+// for callers that cannot allocate: the two permuted n-vectors that the
+// other entry point keeps in the hierarchy.  Each device that runs the
+// library holds one copy until the process ends; every call on a device
+// shares it (calls that overlap in time on one device race).
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;  // 64 MiB: n <= 4,194,304
+constexpr int kNoallocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
 using namespace lapgpu;
 
 namespace {
@@ -2535,6 +2544,58 @@ void srv_loop(lap_server* S) {
     }
 }
 
+// y = L x in the caller's order.  When the solve order differs from the
+// input order (sperm), x is gathered into w0 in solve order, the product
+// goes to w1 and is scattered back: w0 and w1 are n-vector work buffers.
+lap_status apply_laplacian(lap_hierarchy* h, const double* x, double* y, double* w0, double* w1,
+                           hipStream_t s) {
+    const Engine<double>& e = h->e64;
+    const int n = (int)h->n;
+    if (h->sperm) {
+        hipLaunchKernelGGL(k_gather<double>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm, x,
+                           w0);
+        hipLaunchKernelGGL(k_spmv_plain, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A,
+                           (const double*)w0, w1);
+        hipLaunchKernelGGL(k_shift_out<double>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm,
+                           (const double*)w1, y, (const Scal*)nullptr);
+    } else {
+        hipLaunchKernelGGL(k_spmv_plain, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A, x,
+                           y);
+    }
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        record_error("k_spmv_plain launch", err, __LINE__);
+        return LAP_EDEVICE;
+    }
+    return LAP_OK;
+}
+
+// Device address of this device's copy of `scratch`, taken once per device
+// with that device current (the array's name is only a host-side stand-in)
+// and kept for the life of the process.
+lap_status noalloc_scratch(int dev, double** out) {
+    static std::mutex mu;
+    static void* ptr[kNoallocMaxDevices] = {};
+    if (dev < 0 || dev >= kNoallocMaxDevices) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "lap_apply_laplacian_noalloc: device %d beyond the %d supported", dev,
+                      kNoallocMaxDevices);
+        return LAP_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            record_error("hipGetSymbolAddress(scratch)", e, __LINE__);
+            return LAP_EDEVICE;
+        }
+        ptr[dev] = p;
+    }
+    *out = static_cast<double*>(ptr[dev]);
+    return LAP_OK;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -2698,28 +2759,36 @@ lap_status lap_set_precision(lap_hierarchy* h, int32_t precision) {
 lap_status lap_apply_laplacian(lap_hierarchy* h, const double* x, double* y, void* stream) {
     if (!h || !x || !y) return LAP_EINVAL;
     if (h->host_only) return LAP_EUNSUPPORTED;
-    const Engine<double>& e = h->e64;
-    hipStream_t s = (hipStream_t)stream;
-    const int n = (int)h->n;
-    if (h->sperm) {
-        // solve order differs from the input order: permute in and out
-        // through two FP64 work vectors of the hierarchy
-        hipLaunchKernelGGL(k_gather<double>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm, x,
-                           h->xc);
-        hipLaunchKernelGGL(k_spmv_plain, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A,
-                           (const double*)h->xc, h->bh);
-        hipLaunchKernelGGL(k_shift_out<double>, dim3(nblk(n)), dim3(kBlock), 0, s, n, h->sperm,
-                           (const double*)h->bh, y, (const Scal*)nullptr);
-    } else {
-        hipLaunchKernelGGL(k_spmv_plain, dim3(e.spmv_grid()), dim3(kBlock), 0, s, e.nlb, e.A, x,
-                           y);
+    // the permuted copies go through two FP64 work vectors of the hierarchy
+    return apply_laplacian(h, x, y, h->xc, h->bh, (hipStream_t)stream);
+}
+
+lap_status lap_apply_laplacian_noalloc(lap_hierarchy* h, const double* x, double* y,
+                                       void* stream) {
+    if (!h || !x || !y) return LAP_EINVAL;
+    if (h->host_only) return LAP_EUNSUPPORTED;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LAP_EDEVICE;
+    if (dev != h->device) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "lap_apply_laplacian_noalloc: current device %d, hierarchy on device %d",
+                      dev, h->device);
+        return LAP_EINVAL;
     }
-    const hipError_t err = hipGetLastError();
-    if (err != hipSuccess) {
-        record_error("k_spmv_plain launch", err, __LINE__);
-        return LAP_EDEVICE;
+    if (!h->sperm) return apply_laplacian(h, x, y, nullptr, nullptr, (hipStream_t)stream);
+    const size_t need = 2 * sizeof(double) * (size_t)h->n;
+    if (need > kNoallocScratchBytes) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "lap_apply_laplacian_noalloc: n = %lld needs %zu bytes of scratch, the "
+                      "maximum is %zu (n <= %zu for this graph)",
+                      (long long)h->n, need, kNoallocScratchBytes,
+                      kNoallocScratchBytes / (2 * sizeof(double)));
+        return LAP_EUNSUPPORTED;
     }
-    return LAP_OK;
+    double* scr = nullptr;
+    const lap_status st = noalloc_scratch(dev, &scr);
+    if (st != LAP_OK) return st;
+    return apply_laplacian(h, x, y, scr, scr + h->n, (hipStream_t)stream);
 }
 
 lap_status lap_apply_precond(lap_hierarchy* h, const double* r, double* z, void* stream) {
