@@ -225,6 +225,10 @@ struct PegpDev {
     // device scratch of one apply: the expanded vector between the
     // single-workgroup kernels, the tail's values, the backward coupling sums
     double *fg, *ty, *cpl;
+    // the explicit operator (PegpPlan::op; opn = 0: not formed)
+    int32_t opn, opld;
+    const double* op;
 };
+constexpr int kPegpOpRows = 8;           // rows of the operator per workgroup (2 per wavefront)
 
 }  // namespace lapgpu

@@ -577,6 +577,15 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
                 finish<kFinRr>(h, s, S, nblk(n), 0, h->part2);
             }
             const PegpDev& P = h->pegp_dev;
+            if (P.opn > 0) {
+                // the explicit operator: one matrix-vector product
+                const int grid = (P.opn + kPegpOpRows - 1) / kPegpOpRows;
+                hipLaunchKernelGGL(k_pegp_op, dim3(grid), dim3(kBlock),
+                                   (uint32_t)(P.opld * sizeof(double)), s, P, h->t2s,
+                                   (const double*)e.r, e.zn, (const Scal*)S, h->part);
+                finish<kFinRho>(h, s, S, grid);
+                return;
+            }
             hipLaunchKernelGGL(k_pegp_fwd, dim3(1), dim3(kPegpThreads), h->pegp_lds, s, P,
                                (const double*)e.r, (const Scal*)S);
             if (P.nd > 0) {
@@ -943,6 +952,18 @@ void upload_pegp(lap_hierarchy* h, hipStream_t s) {
                                (int)h->pegp_lds));
     HIPCHK(hipFuncSetAttribute((const void*)k_pegp_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)h->pegp_lds));
+    // the explicit operator, when formed (its host copy is not kept)
+    d.opn = G.opn;
+    d.opld = G.opld;
+    d.op = nullptr;
+    if (G.opn > 0) {
+        d.op = h->upload(G.op, s);
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<double>().swap(h->pegp_plan.op);
+        HIPCHK(hipFuncSetAttribute((const void*)k_pegp_op,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(G.opld * sizeof(double))));
+    }
 }
 
 void upload_plan(lap_hierarchy* h, hipStream_t s) {
@@ -967,6 +988,7 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     int gmax = std::max(nblk(n), h->e64.spmv_grid());
     for (int b : h->nb) gmax = std::max(gmax, b);
     gmax = std::max(gmax, std::max(h->e64.nb01, h->e32.nb01));
+    if (h->pegp) gmax = std::max(gmax, (h->pegp_dev.opn + kPegpOpRows - 1) / kPegpOpRows);
     h->part = h->dalloc<double>((size_t)kMaxGridPart * gmax + 64);
     h->part2 = h->dalloc<double>((size_t)gmax + 64);
     HIPCHK(hipHostMalloc((void**)&h->stage, sizeof(Scal), hipHostMallocDefault));

@@ -6,6 +6,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <atomic>
+#include <thread>
 #include <unordered_map>
 
 namespace lapgpu {
@@ -600,6 +602,92 @@ static bool pegp_pack(const std::vector<int32_t>& lev, const std::vector<int32_t
     return true;
 }
 
+// Columns of the explicit PEGP operator (see PegpPlan::op): for r = e_j -
+// 1/n, the scaled right-hand side D P(mu)^T r has, on a level-k node A,
+// (-1)^k times the sum of r over A's fine descendants; the grounded solve
+// S y' = D P(mu)^T r runs through the factor S = L diag(d) L^T in
+// elimination order, and z = P(mu) D y' = sum_k (-1)^k y'(ancestor on level
+// k), made mean-free.  Columns are spread over host threads.
+static void pegp_operator(const HostPlan& P, const std::vector<int32_t>& off,
+                          const std::vector<std::vector<int32_t>>& par,
+                          const std::vector<int32_t>& order,
+                          const std::vector<std::vector<std::pair<int32_t, double>>>& rowL,
+                          const std::vector<std::vector<std::pair<int32_t, double>>>& colL,
+                          const std::vector<double>& diag, PegpPlan& out) {
+    const int L = P.nlev(), T = L - 1;
+    const int32_t n = (int32_t)P.lv[0].g.n, nt = off[L], m = nt - 1;
+    const int32_t ld = (n + kPegpOpAlign - 1) / kPegpOpAlign * kPegpOpAlign;
+    // the factor as CSR in elimination order
+    std::vector<int32_t> fp(m + 1, 0), bp(m + 1, 0), fi, bi;
+    std::vector<double> fv, bv;
+    for (int32_t q = 0; q < m; ++q) {
+        const int32_t v = order[q];
+        for (auto& e : rowL[v]) {
+            fi.push_back(e.first);
+            fv.push_back(e.second);
+        }
+        fp[q + 1] = (int32_t)fi.size();
+        for (auto& e : colL[v]) {
+            bi.push_back(e.first);
+            bv.push_back(e.second);
+        }
+        bp[q + 1] = (int32_t)bi.size();
+    }
+    // fine descendants of every expanded node, and the level of each
+    std::vector<double> cnt(nt, 0.0);
+    std::vector<int> lev(nt, 0);
+    for (int k = 0; k < L; ++k)
+        for (int32_t e = off[k]; e < off[k + 1]; ++e) lev[e] = k;
+    for (int32_t t = 0; t < n; ++t) cnt[t] = 1.0;
+    for (int k = 0; k < T; ++k)
+        for (int32_t t = 0; t < off[k + 1] - off[k]; ++t) cnt[off[k + 1] + par[k][t]] += cnt[off[k] + t];
+    out.opn = n;
+    out.opld = ld;
+    out.op.assign((size_t)n * ld, 0.0);
+    auto column = [&](int32_t j, std::vector<double>& w, std::vector<double>& acc) {
+        for (int32_t e = 0; e < nt; ++e) w[e] = -cnt[e] / (double)n * ((lev[e] & 1) ? -1.0 : 1.0);
+        for (int32_t a = j, k = 0;; ++k) {
+            w[off[k] + a] += (k & 1) ? -1.0 : 1.0;
+            if (k == T) break;
+            a = par[k][a];
+        }
+        for (int32_t q = 0; q < m; ++q) {
+            const int32_t v = order[q];
+            double x = w[v];
+            for (int32_t i = fp[q]; i < fp[q + 1]; ++i) x -= fv[i] * w[fi[i]];
+            w[v] = x;
+        }
+        for (int32_t q = 0; q < m; ++q) w[order[q]] /= diag[order[q]];
+        for (int32_t q = m - 1; q >= 0; --q) {
+            const int32_t v = order[q];
+            double x = w[v];
+            for (int32_t i = bp[q]; i < bp[q + 1]; ++i) x -= bv[i] * w[bi[i]];
+            w[v] = x;
+        }
+        w[nt - 1] = 0.0;  // the grounded node
+        // z = sum over levels of (-1)^k y'(ancestor), top down
+        for (int32_t e = off[T]; e < nt; ++e) acc[e] = (T & 1) ? -w[e] : w[e];
+        for (int k = T - 1; k >= 0; --k)
+            for (int32_t t = 0; t < off[k + 1] - off[k]; ++t)
+                acc[off[k] + t] = ((k & 1) ? -w[off[k] + t] : w[off[k] + t]) +
+                                  acc[off[k + 1] + par[k][t]];
+        double mean = 0.0;
+        for (int32_t t = 0; t < n; ++t) mean += acc[t];
+        mean /= (double)n;
+        for (int32_t t = 0; t < n; ++t) out.op[(size_t)t * ld + j] = acc[t] - mean;
+    };
+    const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    std::atomic<int32_t> next{0};
+    auto work = [&]() {
+        std::vector<double> w(nt), acc(nt);
+        for (int32_t j; (j = next.fetch_add(1)) < n;) column(j, w, acc);
+    };
+    std::vector<std::thread> pool;
+    for (int i = 1; i < nth; ++i) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+}
+
 int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
     const int L = P.nlev();
     const int T = L - 1;
@@ -881,6 +969,8 @@ int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
         !pegp_pack(out.blev, out.blg, out.bptr, out.bcol, out.bval, out.bdesc, out.bpval,
                    out.bpcol))
         return kUnsupported;
+    if (P.lv[0].g.n <= kPegpOpMax && env_or("LAPGPU_PEGP_OPERATOR", 1) != 0)
+        pegp_operator(P, out.off, par, order, rowL, colL, out.diag, out);
     return kOk;
 }
 

@@ -134,10 +134,19 @@ struct PegpPlan {
     // level's loads can be issued before the previous level is done.
     std::vector<int32_t> fdesc, bdesc, fpcol, bpcol;
     std::vector<double> fpval, bpval;
+    // The explicit operator M = P(mu) L_H~^+ P(mu)^T on mean-free vectors
+    // of the fine level (tree order), formed column by column through the
+    // factor: op[i * opld + j] = (M (e_j - 1/n))_i - mean, opld = n rounded
+    // up to a multiple of kPegpOpAlign (padding 0).  Empty when n exceeds
+    // kPegpOpMax or the operator is switched off.
+    int32_t opn = 0, opld = 0;
+    std::vector<double> op;
 };
 constexpr int kPegpSolveThreads = 1024;      // threads of the PEGP solve workgroup
 constexpr int kPegpDescInts = 4;
 constexpr int kPegpTailWidth = 24;
+constexpr int kPegpOpMax = 8192;             // largest fine level applied as an explicit operator
+constexpr int kPegpOpAlign = 512;            // row length of the operator: whole rounds of its kernel
 constexpr int kPegpTailBlock = 192;           // rows per kernel (superblock) of the dense tail solve
 constexpr int kPegpMinDense = 64;
 constexpr int kPegpMaxDense = 4096;

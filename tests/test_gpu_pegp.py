@@ -1,8 +1,10 @@
 """GPU checks of the PEGP preconditioner (Sec. 3.1-3.2): z = P(mu) L_H~^+
 P(mu)^T r through the grounded, scaled system S = D L_H~ D factored on the
-host and solved on the device: the sparse levels of the factor by one
-workgroup, its dense tail (the last-eliminated rows) by blocked
-substitution over the whole device.
+host.  Two device paths, each tested: the explicit operator M (formed at
+set-up through the factor, applied as one matrix-vector product; the
+default up to 8192 fine nodes), and the factor itself (the sparse levels by
+one workgroup, the dense tail, the last-eliminated rows, by blocked
+substitution over the whole device).
 
 The applied preconditioner is compared with the oracle's (scipy sparse
 products and a sparse LU of the same grounded, scaled matrix) in the
@@ -11,6 +13,9 @@ kappa(S) (kappa from a dense spectrum where the system is small enough).
 Whole solves reproduce the PCG step counts the paper prints in Table 3
 (grids, level = max with mu = 1/sqrt(n), level = 2 with mu = n^(-1/4)).
 """
+import contextlib
+import os
+
 import numpy as np
 import pytest
 
@@ -18,6 +23,23 @@ import workloads as W
 from gpu_util import GpuLap, say
 
 pytestmark = pytest.mark.gpu
+
+
+MODES = ["operator", "factor"]
+
+
+@contextlib.contextmanager
+def _mode(mode):
+    """The device path of PEGP hierarchies set up inside the block."""
+    old = os.environ.get("LAPGPU_PEGP_OPERATOR")
+    os.environ["LAPGPU_PEGP_OPERATOR"] = "1" if mode == "operator" else "0"
+    try:
+        yield
+    finally:
+        if old is None:
+            del os.environ["LAPGPU_PEGP_OPERATOR"]
+        else:
+            os.environ["LAPGPU_PEGP_OPERATOR"] = old
 
 
 def _oracle_pegp(n, u, v, w, mu, max_levels=0):
@@ -45,8 +67,9 @@ def _weights(kind, m, seed):
     return W.uniform01_weights(m, seed)
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name", list(CASES))
-def test_pegp_apply_parity(oracle_lib, name):
+def test_pegp_apply_parity(oracle_lib, name, mode):
     """The bar is the rounding spread of the direct solve itself: the oracle
     solved with two fill orderings (the same grounded system, different
     elimination orders) differs by `spread`; the GPU's elimination order is a
@@ -61,14 +84,16 @@ def test_pegp_apply_parity(oracle_lib, name):
     r -= r.mean()
     z0 = M.apply(r)
     spread = np.linalg.norm(M2.apply(r) - z0) / np.linalg.norm(z0)
-    G = GpuLap(n, u, v, w, mu=mu, precond=lap.LAP_PREC_PEGP)
+    with _mode(mode):
+        G = GpuLap(n, u, v, w, mu=mu, precond=lap.LAP_PREC_PEGP)
     try:
         z = G.apply_precond(r)
     finally:
         G.close()
     err = np.linalg.norm(z - z0) / np.linalg.norm(z0)
-    say(name, "nt", M.nt, "rel err", err, "oracle ordering spread", spread)
-    assert err <= max(100 * spread, 1e-14)
+    msg = f"{name} ({mode}): nt {M.nt} rel err {err:.3e}, oracle ordering spread {spread:.3e}"
+    say(msg)
+    assert err <= max(100 * spread, 1e-14), msg
 
 
 # Shapes of the dense tail on small grids (grid side, level setting):
@@ -82,8 +107,9 @@ TAIL_SHAPES = {
 }
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name", list(TAIL_SHAPES))
-def test_pegp_apply_tail_shapes(oracle_lib, name):
+def test_pegp_apply_tail_shapes(oracle_lib, name, mode):
     """The same bar as above, on tails that the larger cases do not have."""
     import paper_2207_07847_amd as lap
     from oracle.pegp import PEGP
@@ -97,18 +123,21 @@ def test_pegp_apply_tail_shapes(oracle_lib, name):
     r -= r.mean()
     z0 = M.apply(r)
     spread = np.linalg.norm(M2.apply(r) - z0) / np.linalg.norm(z0)
-    G = GpuLap(n, u, v, w, mu=mu, precond=lap.LAP_PREC_PEGP, max_levels=ml)
+    with _mode(mode):
+        G = GpuLap(n, u, v, w, mu=mu, precond=lap.LAP_PREC_PEGP, max_levels=ml)
     try:
         z = G.apply_precond(r)
     finally:
         G.close()
     err = np.linalg.norm(z - z0) / np.linalg.norm(z0)
-    say(name, "nt", M.nt, "rel err", err, "oracle ordering spread", spread)
-    assert err <= max(100 * spread, 1e-14)
+    msg = f"{name} ({mode}): nt {M.nt} rel err {err:.3e}, oracle ordering spread {spread:.3e}"
+    say(msg)
+    assert err <= max(100 * spread, 1e-14), msg
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("a", [16, 32, 64])
-def test_pegp_table3_steps(oracle_lib, a):
+def test_pegp_table3_steps(oracle_lib, a, mode):
     """Table 3: PEGP, tol 1e-8, b = [1,...,1,1-n]: the paper's step counts."""
     import paper_2207_07847_amd as lap
     from oracle import Graph
@@ -118,7 +147,9 @@ def test_pegp_table3_steps(oracle_lib, a):
     b = W.lowfreq_rhs(n)
     g = Graph(n, u, v, w)
     for ml, mu in [(0, 1 / np.sqrt(n)), (2, n ** -0.25)]:
-        G = GpuLap(n, u, v, w, mu=mu, max_levels=ml, precond=lap.LAP_PREC_PEGP, max_iter=1000)
+        with _mode(mode):
+            G = GpuLap(n, u, v, w, mu=mu, max_levels=ml, precond=lap.LAP_PREC_PEGP,
+                       max_iter=1000)
         try:
             st, x, info = G.solve(b, 1e-8)
         finally:
@@ -131,7 +162,8 @@ def test_pegp_table3_steps(oracle_lib, a):
         assert host <= 1.01e-8
 
 
-def test_pegp_c1_solve(oracle_lib):
+@pytest.mark.parametrize("mode", MODES)
+def test_pegp_c1_solve(oracle_lib, mode):
     """64x64 grid, unit weights, mu = 1/64, Gaussian right-hand side: the
     oracle's PEGP-PCG iteration count, FP64 residual <= tol."""
     import paper_2207_07847_amd as lap
@@ -141,7 +173,8 @@ def test_pegp_c1_solve(oracle_lib):
     b = W.gaussian_rhs(n, W.MASTER_SEED + 1)
     g, h, M = _oracle_pegp(n, u, v, w, 1 / 64.0)
     ref = pcg(g, b, 1e-8, 1000, M)
-    G = GpuLap(n, u, v, w, mu=1 / 64.0, precond=lap.LAP_PREC_PEGP, max_iter=1000)
+    with _mode(mode):
+        G = GpuLap(n, u, v, w, mu=1 / 64.0, precond=lap.LAP_PREC_PEGP, max_iter=1000)
     try:
         st, x, info = G.solve(b, 1e-8)
     finally:
@@ -149,6 +182,8 @@ def test_pegp_c1_solve(oracle_lib):
     bh = b - b.mean()
     host = np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh)
     diff = np.linalg.norm(x - pcg(g, b, 0.0, info["iterations"], M).x) / np.linalg.norm(x)
-    say("C1 pegp: gpu", info, "oracle it", ref.iterations, "host relres", host, "iterate diff", diff)
-    assert st == 0 and info["iterations"] == ref.iterations
-    assert host <= 1.01e-8 and diff <= 1e-7
+    msg = (f"C1 pegp ({mode}): gpu {info} oracle it {ref.iterations} host relres {host:.3e} "
+           f"iterate diff {diff:.2e}")
+    say(msg)
+    assert st == 0 and info["iterations"] == ref.iterations, msg
+    assert host <= 1.01e-8 and diff <= 1e-7, msg
