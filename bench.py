@@ -242,18 +242,26 @@ def serve(args):
         gi = int(rng.integers(len(pool)))
         m = int(rng.integers(1, 17))
         tol = 1e-8 if rng.random() < 0.5 else 1e-6
-        b = rng.standard_normal((m, pool[gi]["n"]))
-        reqs.append(dict(g=gi, b=b, x=np.empty_like(b), tol=tol, m=m))
+        reqs.append(dict(g=gi, tol=tol, m=m))
     arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, len(reqs)))
+
+    def rhs(k):
+        # request k's right-hand sides from its own seed, drawn when it is
+        # submitted (a long stream's b and x would not fit host memory)
+        r = reqs[k]
+        return np.random.default_rng(20220715 + 9 + k).standard_normal((r["m"],
+                                                                        pool[r["g"]]["n"]))
+
     # plain FP64 single solves of a sample of the requests' columns, on the
     # same hierarchies before they are handed to the server
     sample = reqs[:args.serve_compare]
     cols = 0
     t0 = time.perf_counter()
-    for r in sample:
+    for i, r in enumerate(sample):
         g = pool[r["g"]]
+        b = rhs(i)
         for j in range(r["m"]):
-            bd = torch.tensor(r["b"][j], dtype=torch.float64, device="cuda")
+            bd = torch.tensor(b[j], dtype=torch.float64, device="cuda")
             xd = torch.empty_like(bd)
             st, _ = lap.lap_solve(hs[r["g"]], bd.data_ptr(), xd.data_ptr(), g["n"], r["tol"],
                                   stream=sh)
@@ -277,6 +285,8 @@ def serve(args):
             log(f"  {now:6.1f}s: submitted {k}, completed {len(res)}")
         while k < len(reqs) and arrivals[k] <= now:
             r = reqs[k]
+            r["b"] = rhs(k)
+            r["x"] = np.empty_like(r["b"])
             st = lap.lap_server_submit(srv, gids[r["g"]], r["b"].ctypes.data, r["x"].ctypes.data,
                                        r["m"], r["tol"], k)
             if st != 0:
@@ -284,6 +294,9 @@ def serve(args):
             k += 1
         for o in lap.lap_server_poll(srv, 512, 1 if k == len(reqs) else 0):
             res[o["tag"]] = o
+            # the server is done with the request's buffers
+            reqs[o["tag"]].pop("b", None)
+            reqs[o["tag"]].pop("x", None)
         if k < len(reqs) and arrivals[k] > now:
             time.sleep(min(0.0005, arrivals[k] - now))
     elapsed = time.perf_counter() - t_start

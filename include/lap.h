@@ -155,6 +155,23 @@ typedef struct lap_hierarchy lap_hierarchy;
  * max_iter 1000, no flags.  Errors: LAP_EINVAL if p is NULL. */
 lap_status lap_default_params(lap_params *p);
 
+/* Device allocator for the hierarchies set up after this call (for
+ * example a framework's caching allocator, so that a hierarchy lives in the
+ * caller's memory pool).  alloc(bytes, ctx) returns device memory of the
+ * current device (at least 256-byte aligned) or NULL; free(ptr, ctx)
+ * releases a pointer alloc returned.  Both NULL restores hipMalloc /
+ * hipFree.  The library calls alloc from lap_setup (and from the first
+ * FGMRES solve of a hierarchy, for its basis) and free from lap_free, on the
+ * calling thread; a hierarchy keeps the pair it was set up with.  The
+ * request server's staging buffers and the set-up graphs built on the
+ * device (LAP_FLAG_DEVICE_SETUP) still use hipMallocAsync / hipMalloc.
+ * Process-wide; thread-safe.  Errors: LAP_EINVAL when exactly one of
+ * alloc, free is NULL.  An alloc that returns NULL makes lap_setup return
+ * LAP_ENOMEM. */
+typedef void *(*lap_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*lap_free_fn)(void *ptr, void *ctx);
+lap_status lap_set_allocator(lap_alloc_fn alloc, lap_free_fn free, void *ctx);
+
 /* Host setup (Sec. 2.2, Sec. 3.3) then upload on `stream`.
  *   1. validate and build the symmetric adjacency (parallel edges summed in
  *      input order); reject a disconnected graph (LAP_EDISCONNECTED);

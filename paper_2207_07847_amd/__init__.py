@@ -66,6 +66,10 @@ class lap_request_result(C.Structure):
                 ("total_seconds", C.c_double)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 def _load():
     # Device buffers come from torch, so the library must run on the same HIP
     # runtime instance: torch ships its own libamdhip64.so.7; importing torch
@@ -93,6 +97,8 @@ def _load():
                                         C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
     L.lap_select_mu.argtypes = [C.POINTER(lap_graph), C.POINTER(lap_params), vp, C.c_int32, vp,
                                 C.c_int32, vp, C.POINTER(C.c_int32), vp]
+    L.lap_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+    L.lap_set_allocator.restype = C.c_int
     L.lap_free.argtypes = [vp]
     L.lap_free.restype = None
     L.lap_server_create.argtypes = [C.c_int64, C.POINTER(vp)]
@@ -258,6 +264,43 @@ def lap_select_mu(n, u, v, w, mus, b_ptr: int, steps: int, params: lap_params | 
     st = _lib.lap_select_mu(C.byref(g), C.byref(p), m.ctypes.data, len(m), C.c_void_p(b_ptr),
                             int(steps), kap.ctypes.data, C.byref(best), C.c_void_p(stream or 0))
     return st, best.value, kap
+
+
+# every callback pair ever registered stays referenced: a hierarchy keeps
+# calling the pair it was set up with until lap_free
+_allocators = []
+
+
+def lap_set_allocator(alloc=None, free=None) -> int:
+    """Device allocator of later lap_setup calls: alloc(nbytes) -> device
+    pointer (int, 0 on failure), free(ptr) -> None.  No arguments restores
+    hipMalloc / hipFree."""
+    if alloc is None and free is None:
+        return _lib.lap_set_allocator(C.cast(None, ALLOC_FN), C.cast(None, FREE_FN), None)
+    if alloc is None or free is None:
+        return LAP_EINVAL
+    a = ALLOC_FN(lambda nbytes, ctx: alloc(int(nbytes)) or None)
+    f = FREE_FN(lambda ptr, ctx: free(int(ptr)))
+    _allocators.append((a, f))
+    return _lib.lap_set_allocator(a, f, None)
+
+
+def use_torch_allocator(device=None) -> int:
+    """Route the device memory of later hierarchies through torch's caching
+    allocator (on `device`, default the current one)."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else device
+
+    def alloc(nbytes):
+        try:
+            return torch.cuda.caching_allocator_alloc(nbytes, dev)
+        except RuntimeError:
+            return 0
+
+    def free(ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return lap_set_allocator(alloc, free)
 
 
 def lap_free(h) -> None:

@@ -1940,15 +1940,16 @@ __global__ __launch_bounds__(kPegpThreads) void k_pegp_bwd(PegpDev P,
 
 // PEGP by its explicit operator: z = M r on the fine level (tree order),
 // M = P(mu) L_H~^+ P(mu)^T formed at set-up (PegpPlan::op).  A dense
-// matrix-vector product bound by the stream of M: r is staged in LDS,
-// each wavefront takes two rows, every lane two adjacent columns per load
-// (coalesced 1 KB per wavefront load), four loads in flight.  z goes to zn
-// through the permutation; the partial sums of z, r z and r of the
-// workgroup's rows go to part for the finish kernel.
+// matrix-vector product bound by the stream of M: r is staged in LDS, each
+// wavefront takes one row, every lane two adjacent columns per load
+// (coalesced 1 KB per wavefront load), eight loads in flight per lane.  z
+// goes to zn through the permutation; the partial sums of z, r z and r of
+// the workgroup's rows go to part for the finish kernel.
 __global__ __launch_bounds__(kBlock) void k_pegp_op(PegpDev P, const int32_t* __restrict__ perm,
                                                     const double* __restrict__ r,
                                                     double* __restrict__ zn, const Scal* S,
                                                     double* part) {
+    static_assert(kPegpOpRows == kBlock / 64, "one row per wavefront");
     extern __shared__ __align__(16) unsigned char smem[];
     double* rs = reinterpret_cast<double*>(smem);
     const int n = P.opn, ld = P.opld, tid = threadIdx.x;
@@ -1956,32 +1957,40 @@ __global__ __launch_bounds__(kBlock) void k_pegp_op(PegpDev P, const int32_t* __
     for (int j = tid; j < ld; j += kBlock) rs[j] = j < n ? r[j] : 0.0;
     if (done) return;
     __syncthreads();
-    const int wid = tid >> 6, lane = tid & 63;
-    constexpr int RW = kPegpOpRows / (kBlock / 64);
+    const int lane = tid & 63;
+    const int i = blockIdx.x * kPegpOpRows + (tid >> 6);
     double v[3] = {0.0, 0.0, 0.0};
-    const double2* rs2 = reinterpret_cast<const double2*>(rs);
-#pragma unroll
-    for (int q = 0; q < RW; ++q) {
-        const int i = blockIdx.x * kPegpOpRows + wid * RW + q;
-        if (i >= n) break;
+    if (i < n) {
         const double2* row = reinterpret_cast<const double2*>(P.op + (size_t)i * ld);
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        const int nc2 = ld / 2;  // ld is a multiple of 256: whole rounds of 4 x 64 pairs
-        for (int c = lane; c < nc2; c += 4 * 64) {
-            const double2 m0 = row[c], m1 = row[c + 64], m2 = row[c + 128], m3 = row[c + 192];
-            const double2 x0 = rs2[c], x1 = rs2[c + 64], x2 = rs2[c + 128], x3 = rs2[c + 192];
-            a0 += m0.x * x0.x + m0.y * x0.y;
-            a1 += m1.x * x1.x + m1.y * x1.y;
-            a2 += m2.x * x2.x + m2.y * x2.y;
-            a3 += m3.x * x3.x + m3.y * x3.y;
+        const double2* rs2 = reinterpret_cast<const double2*>(rs);
+        constexpr int U = 8;
+        const int nc2 = ld / 2;  // a multiple of 64: every lane takes the same steps
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = 0.0;
+        int c = lane;
+        for (; c + (U - 1) * 64 < nc2; c += U * 64) {
+            double2 m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) m[u] = row[c + u * 64];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double2 x = rs2[c + u * 64];
+                a[u] += m[u].x * x.x + m[u].y * x.y;
+            }
         }
-        const double zi = wave_sum1((a0 + a1) + (a2 + a3));
+        for (; c < nc2; c += 64) {
+            const double2 m = row[c], x = rs2[c];
+            a[0] += m.x * x.x + m.y * x.y;
+        }
+        const double zi =
+            wave_sum1(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
         if (lane == 0) {
             const double ri = rs[i];
             zn[perm ? perm[i] : i] = zi;
-            v[0] += zi;
-            v[1] += ri * zi;
-            v[2] += ri;
+            v[0] = zi;
+            v[1] = ri * zi;
+            v[2] = ri;
         }
     }
     block_partial<3>(v, part);

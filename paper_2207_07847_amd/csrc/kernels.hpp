@@ -229,6 +229,6 @@ struct PegpDev {
     int32_t opn, opld;
     const double* op;
 };
-constexpr int kPegpOpRows = 8;           // rows of the operator per workgroup (2 per wavefront)
+constexpr int kPegpOpRows = 4;           // rows of the operator per workgroup (one per wavefront)
 
 }  // namespace lapgpu

@@ -48,6 +48,17 @@ inline int nblk(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 struct HipErr {};
 thread_local char g_last_error[256] = "";
 
+// Device allocator of hierarchies set up from now on (lap_set_allocator):
+// null functions mean hipMalloc / hipFree.  A hierarchy keeps the pair it
+// was set up with until lap_free.
+struct Allocator {
+    lap_alloc_fn alloc = nullptr;
+    lap_free_fn free = nullptr;
+    void* ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
 void record_error(const char* what, hipError_t e, int line) {
     std::snprintf(g_last_error, sizeof(g_last_error), "lap.hip:%d %s -> %s (%d)", line, what,
                   hipGetErrorString(e), (int)e);
@@ -475,11 +486,21 @@ struct lap_hierarchy {
     double reliable_drop = kReliableDrop;
     bool reliable = true;        // mixed precision by reliable updates (else restarts)
 
+    Allocator allocator;         // device memory of this hierarchy
+    void dev_free(void* ptr) {
+        if (allocator.free) allocator.free(ptr, allocator.ctx);
+        else (void)hipFree(ptr);
+    }
     template <class T>
     T* dalloc(size_t count) {
         void* ptr = nullptr;
         const size_t bytes = (count ? count : 1) * sizeof(T);
-        if (hipMalloc(&ptr, bytes) != hipSuccess) throw std::bad_alloc();
+        if (allocator.alloc) {
+            ptr = allocator.alloc(bytes, allocator.ctx);
+            if (!ptr) throw std::bad_alloc();
+        } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
+            throw std::bad_alloc();
+        }
         allocs.push_back(ptr);
         alloc_bytes.push_back(bytes);
         dev_bytes += (int64_t)bytes;
@@ -490,7 +511,7 @@ struct lap_hierarchy {
     size_t mark() const { return allocs.size(); }
     void release_to(size_t mk) {
         while (allocs.size() > mk) {
-            (void)hipFree(allocs.back());
+            dev_free(allocs.back());
             dev_bytes -= (int64_t)alloc_bytes.back();
             allocs.pop_back();
             alloc_bytes.pop_back();
@@ -511,7 +532,7 @@ struct lap_hierarchy {
         e32.release();
         m64.release();
         m32.release();
-        for (void* ptr : allocs) (void)hipFree(ptr);
+        for (void* ptr : allocs) dev_free(ptr);
         if (stage) (void)hipHostFree(stage);
         if (stagem) (void)hipHostFree(stagem);
         if (fg_hh) (void)hipHostFree(fg_hh);
@@ -2651,6 +2672,15 @@ const char* lap_status_str(lap_status s) {
     return "LAP_UNKNOWN";
 }
 
+lap_status lap_set_allocator(lap_alloc_fn alloc, lap_free_fn free_fn, void* ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return LAP_EINVAL;
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free = free_fn;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return LAP_OK;
+}
+
 lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_hierarchy** out) {
     if (!out) return LAP_EINVAL;
     *out = nullptr;
@@ -2668,6 +2698,10 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
     if (!h) return LAP_ENOMEM;
     h->params = *p;
     h->host_only = (p->flags & LAP_FLAG_HOST_ONLY) != 0;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mu);
+        h->allocator = g_alloc;
+    }
     try {
         // only the MSP solves the top level on chip (a dense pseudo-inverse)
         const bool any_top = h->host_only || p->precond != LAP_PREC_MSP;

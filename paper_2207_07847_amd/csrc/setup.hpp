@@ -146,7 +146,7 @@ constexpr int kPegpSolveThreads = 1024;      // threads of the PEGP solve workgr
 constexpr int kPegpDescInts = 4;
 constexpr int kPegpTailWidth = 24;
 constexpr int kPegpOpMax = 8192;             // largest fine level applied as an explicit operator
-constexpr int kPegpOpAlign = 512;            // row length of the operator: whole rounds of its kernel
+constexpr int kPegpOpAlign = 128;            // row length of the operator: whole wavefront loads
 constexpr int kPegpTailBlock = 192;           // rows per kernel (superblock) of the dense tail solve
 constexpr int kPegpMinDense = 64;
 constexpr int kPegpMaxDense = 4096;
