@@ -50,7 +50,16 @@ typedef enum {
                                FP64 single right-hand-side solves only, and
                                expanded graphs of at most 19,456 nodes (the
                                sum of all level sizes) in at most 64 levels */
-    LAP_PREC_NONE = 2       /* plain conjugate gradients */
+    LAP_PREC_NONE = 2,      /* plain conjugate gradients */
+    LAP_PREC_OFFTREE = 3    /* the MSP tree T~ with off-tree edges of H~ added
+                               back (Sec. 3.3, the sparsifiers after its
+                               stretch bound): the ceil(offtree_frac * count)
+                               off-tree edges of largest stretch in T~ (w_e
+                               times the effective resistance between the
+                               ends through T~; ties to the smaller pair),
+                               solved like PEGP on that subgraph of H~ (the
+                               same limits).  offtree_frac 0 gives the MSP
+                               operator, 1 the PEGP one */
 } lap_precond;
 
 typedef enum {
@@ -115,6 +124,8 @@ typedef struct {
     int32_t precision;    /* lap_precision */
     int32_t max_iter;     /* iteration cap of lap_solve (default 1000) */
     uint32_t flags;       /* LAP_FLAG_* */
+    double offtree_frac;  /* LAP_PREC_OFFTREE: fraction in [0, 1] of the
+                             off-tree edges added back (default 0.1) */
 } lap_params;
 
 typedef struct {
@@ -186,9 +197,10 @@ lap_status lap_set_allocator(lap_alloc_fn alloc, lap_free_fn free, void *ctx);
  * On success *out owns the hierarchy.  Errors: LAP_EINVAL (bad graph or
  * params: mu outside (0,1), n_top < 2, unknown precond/precision),
  * LAP_EDISCONNECTED, LAP_ENOMEM, LAP_EDEVICE, LAP_EUNSUPPORTED (top level
- * larger than the on-chip coarse solve allows; PEGP with mixed precision,
- * with LAP_FLAG_MULTI_RHS, or with an expanded graph above 19,456 nodes or
- * 64 levels).  PEGP (Sec. 3.2) factors the grounded, level-scaled
+ * larger than the on-chip coarse solve allows; PEGP or the off-tree
+ * sparsifier with mixed precision, with LAP_FLAG_MULTI_RHS, or with an
+ * expanded graph above 19,456 nodes or 64 levels).  LAP_EINVAL also for
+ * LAP_PREC_OFFTREE with offtree_frac outside [0, 1].  PEGP (Sec. 3.2) factors the grounded, level-scaled
  * L_H~ once on the host (sparse LDL^T) and applies it on the device. */
 lap_status lap_setup(const lap_graph *g, const lap_params *p, void *stream,
                      lap_hierarchy **out);
@@ -329,6 +341,16 @@ lap_status lap_select_mu(const lap_graph *g, const lap_params *p, const double *
 
 /* Sizes and memory of a hierarchy.  Errors: LAP_EINVAL on NULL. */
 lap_status lap_hierarchy_info(const lap_hierarchy *h, lap_hierarchy_desc *d);
+
+/* The off-tree edges of a LAP_PREC_OFFTREE hierarchy: *count receives
+ * their number; each array (host, count entries; any may be NULL) receives
+ * per edge its ends a < b as expanded indices (level offset, the sum of the
+ * sizes of the finer levels, plus the node's id in its level's own
+ * numbering, as lap_export_level uses), its weight in H~, its stretch in
+ * T~, and kept = 1 if it was added back.  Errors: LAP_EINVAL (NULL, or not
+ * an off-tree hierarchy). */
+lap_status lap_export_offtree(const lap_hierarchy *h, int64_t *count, int64_t *a, int64_t *b,
+                              double *w, double *stretch, int8_t *kept);
 
 /* Integer outputs of level `level` (0 = fine) for 0 <= level < nlev-1, in
  * the level's own numbering (aggregate ids in pair-creation order):

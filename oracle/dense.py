@@ -167,32 +167,20 @@ def stretch(T, H):
     return total
 
 
-def msp_apply_highprec(n, u, v, w, aggs, mu, r, dps=50):
-    """z = P(mu) pinv(L_T~) P(mu)^T r - mean(.), every step of the
-    definition carried out densely in mpmath at `dps` digits: P(mu)
-    (Sec. 2.2), L_G~ = P(mu)^T L_G P(mu), H~ its positively weighted edges
-    (Sec. 3.2), T~ the MSP edges of H~ (Sec. 3.3, same reading as
-    msp_from_h), pinv(L) = (L + J/t)^(-1) - J/t for the connected T~ with t
-    nodes (J the all-ones matrix).  For tiny graphs only (the expanded
-    graph's size cubed mpmath operations): a reference whose rounding is far
-    below FP64, for checking FP64 evaluations at any mu."""
-    import mpmath as mpm
-    ctx = mpm.mp.clone()
-    ctx.dps = dps
+def _highprec_expanded(n, u, v, w, aggs, mu, ctx):
+    """(P(mu), L_G~, T~, mask of T~'s edges) in mpmath, from the definitions
+    (the sign pattern of H~ and T~'s edge mask from the FP64 objects: which
+    entries are kept is structural)."""
     mu_ = ctx.mpf(mu)
     sizes = level_sizes(aggs, n)
     nt = sum(sizes)
-    # sign pattern of H~ and the MSP edge mask come from the FP64 objects
-    # (which entries are kept is structural, App.: ancestor links positive
-    # iff the level gap is odd); the values are recomputed in mpmath
     Pm64 = p_mu(aggs, n, float(mu))
     Gt64 = expanded(laplacian(n, u, v, w), Pm64)
     T64 = msp_from_h(positive_subgraph(Gt64), aggs, sizes)
     keep = (T64 != 0.0) & ~np.eye(nt, dtype=bool)
-    Ps = composite(aggs, n)
     Pm = ctx.zeros(n, nt)
     col = 0
-    for k, P in enumerate(Ps):
+    for k, P in enumerate(composite(aggs, n)):
         f = (-mu_) ** k
         for i, j in zip(*np.nonzero(P)):
             Pm[int(i), col + int(j)] = f
@@ -211,8 +199,44 @@ def msp_apply_highprec(n, u, v, w, aggs, mu, r, dps=50):
         T[int(i), int(j)] = Gt[int(i), int(j)]
     for i in range(nt):
         T[i, i] = -ctx.fsum(T[i, j] for j in range(nt) if j != i)
-    J = ctx.ones(nt, nt) / nt
-    Tp = ctx.inverse(T + J) - J
+    return Pm, Gt, T, keep
+
+
+def _highprec_pinv(T, ctx):
+    """pinv(L) = (L + J/t)^(-1) - J/t for a connected Laplacian of t nodes."""
+    t = T.rows
+    J = ctx.ones(t, t) / t
+    return ctx.inverse(T + J) - J
+
+
+def offtree_stretch_highprec(n, u, v, w, aggs, mu, pairs, dps=50):
+    """Stretch in T~ of the H~ edges `pairs` (expanded indices i < j): the
+    H~ weight w_ij = -L_G~(i, j) times the effective resistance
+    (e_i - e_j)^T pinv(L_T~) (e_i - e_j), all in mpmath at `dps` digits
+    (Sec. 3.3, def. stretch-edge with the resistance as the distance).  For
+    tiny graphs only."""
+    import mpmath as mpm
+    ctx = mpm.mp.clone()
+    ctx.dps = dps
+    _, Gt, T, _ = _highprec_expanded(n, u, v, w, aggs, mu, ctx)
+    Tp = _highprec_pinv(T, ctx)
+    return np.array([float(-Gt[i, j] * (Tp[i, i] + Tp[j, j] - 2 * Tp[i, j])) for i, j in pairs])
+
+
+def msp_apply_highprec(n, u, v, w, aggs, mu, r, dps=50):
+    """z = P(mu) pinv(L_T~) P(mu)^T r - mean(.), every step of the
+    definition carried out densely in mpmath at `dps` digits: P(mu)
+    (Sec. 2.2), L_G~ = P(mu)^T L_G P(mu), H~ its positively weighted edges
+    (Sec. 3.2), T~ the MSP edges of H~ (Sec. 3.3, same reading as
+    msp_from_h), pinv(L) = (L + J/t)^(-1) - J/t for the connected T~ with t
+    nodes (J the all-ones matrix).  For tiny graphs only (the expanded
+    graph's size cubed mpmath operations): a reference whose rounding is far
+    below FP64, for checking FP64 evaluations at any mu."""
+    import mpmath as mpm
+    ctx = mpm.mp.clone()
+    ctx.dps = dps
+    Pm, _, T, _ = _highprec_expanded(n, u, v, w, aggs, mu, ctx)
+    Tp = _highprec_pinv(T, ctx)
     rm = ctx.matrix([ctx.mpf(float(t)) for t in r])
     z = Pm * (Tp * (Pm.T * rm))
     mean = ctx.fsum(z[i] for i in range(n)) / n

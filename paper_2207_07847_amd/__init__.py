@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "liblapgpu.so")
 
 LAP_OK, LAP_EINVAL, LAP_EDISCONNECTED, LAP_ENOMEM, LAP_EDEVICE, LAP_ENOCONV, \
     LAP_EBREAKDOWN, LAP_EUNSUPPORTED = range(8)
-LAP_PREC_MSP, LAP_PREC_PEGP, LAP_PREC_NONE = 0, 1, 2
+LAP_PREC_MSP, LAP_PREC_PEGP, LAP_PREC_NONE, LAP_PREC_OFFTREE = 0, 1, 2, 3
 LAP_FP64 = 0
 LAP_MIXED_FP32_FP64 = 1
 LAP_FLAG_HOST_ONLY = 1
@@ -42,7 +42,7 @@ class lap_graph(C.Structure):
 class lap_params(C.Structure):
     _fields_ = [("mu", C.c_double), ("max_levels", C.c_int32), ("n_top", C.c_int32),
                 ("mwm_seed", C.c_uint64), ("precond", C.c_int32), ("precision", C.c_int32),
-                ("max_iter", C.c_int32), ("flags", C.c_uint32)]
+                ("max_iter", C.c_int32), ("flags", C.c_uint32), ("offtree_frac", C.c_double)]
 
 
 class lap_solve_info(C.Structure):
@@ -91,6 +91,7 @@ def _load():
     L.lap_hierarchy_info.argtypes = [vp, C.POINTER(lap_hierarchy_desc)]
     L.lap_export_level.argtypes = [vp, C.c_int32, vp, vp]
     L.lap_export_graph.argtypes = [vp, C.c_int32, vp, vp, vp]
+    L.lap_export_offtree.argtypes = [vp, C.POINTER(C.c_int64), vp, vp, vp, vp, vp]
     L.lap_profile_kernel.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
     L.lap_estimate_spectrum.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_double),
@@ -117,6 +118,7 @@ def _load():
     for f in ("lap_default_params", "lap_setup", "lap_solve", "lap_set_precision",
               "lap_apply_laplacian", "lap_apply_laplacian_noalloc",
               "lap_apply_precond", "lap_hierarchy_info", "lap_export_level", "lap_export_graph",
+              "lap_export_offtree",
               "lap_profile_kernel", "lap_estimate_spectrum", "lap_select_mu"):
         getattr(L, f).restype = C.c_int
     return L
@@ -232,6 +234,22 @@ def lap_export_graph(h, level: int, size: int):
     _lib.lap_export_graph(C.c_void_p(h), int(level), ptr.ctypes.data, col.ctypes.data,
                           w.ctypes.data)
     return ptr, col, w
+
+
+def lap_export_offtree(h):
+    """Off-tree edges of a LAP_PREC_OFFTREE hierarchy: dict of arrays a, b
+    (expanded indices in the levels' own numbering), w, stretch, kept."""
+    cnt = C.c_int64()
+    st = _lib.lap_export_offtree(C.c_void_p(h), C.byref(cnt), None, None, None, None, None)
+    if st != LAP_OK:
+        raise LapError(st, "lap_export_offtree")
+    k = cnt.value
+    out = dict(a=np.empty(k, np.int64), b=np.empty(k, np.int64), w=np.empty(k),
+               stretch=np.empty(k), kept=np.empty(k, np.int8))
+    _lib.lap_export_offtree(C.c_void_p(h), C.byref(cnt), out["a"].ctypes.data,
+                            out["b"].ctypes.data, out["w"].ctypes.data,
+                            out["stretch"].ctypes.data, out["kept"].ctypes.data)
+    return out
 
 
 def lap_profile_kernel(h, kernel: int, reps: int, stream=0):

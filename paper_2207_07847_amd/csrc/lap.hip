@@ -990,7 +990,8 @@ void upload_pegp(lap_hierarchy* h, hipStream_t s) {
 void upload_plan(lap_hierarchy* h, hipStream_t s) {
     const int64_t n = h->n;
     h->with_msp = (h->params.precond == LAP_PREC_MSP);
-    h->pegp = (h->params.precond == LAP_PREC_PEGP);
+    // the off-tree sparsifier is solved like PEGP, on its own subgraph
+    h->pegp = (h->params.precond == LAP_PREC_PEGP || h->params.precond == LAP_PREC_OFFTREE);
     h->mixed = (h->params.precision == LAP_MIXED_FP32_FP64);
     upload_shared(h, s);
     if (h->pegp) upload_pegp(h, s);
@@ -2652,6 +2653,7 @@ lap_status lap_default_params(lap_params* p) {
     p->n_top = 2;
     p->mwm_seed = 0;
     p->precond = LAP_PREC_MSP;
+    p->offtree_frac = 0.1;
     p->precision = LAP_FP64;
     p->max_iter = 1000;
     p->flags = 0;
@@ -2685,11 +2687,15 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
     if (!out) return LAP_EINVAL;
     *out = nullptr;
     if (!g || !p || !g->u || !g->v || !g->w) return LAP_EINVAL;
-    if (p->precond != LAP_PREC_MSP && p->precond != LAP_PREC_NONE && p->precond != LAP_PREC_PEGP)
+    if (p->precond != LAP_PREC_MSP && p->precond != LAP_PREC_NONE &&
+        p->precond != LAP_PREC_PEGP && p->precond != LAP_PREC_OFFTREE)
         return LAP_EINVAL;
     if (p->precision != LAP_FP64 && p->precision != LAP_MIXED_FP32_FP64) return LAP_EINVAL;
     // PEGP: FP64 single solves only
-    if (p->precond == LAP_PREC_PEGP &&
+    const bool pegp_like = p->precond == LAP_PREC_PEGP || p->precond == LAP_PREC_OFFTREE;
+    if (p->precond == LAP_PREC_OFFTREE && !(p->offtree_frac >= 0.0 && p->offtree_frac <= 1.0))
+        return LAP_EINVAL;
+    if (pegp_like &&
         (p->precision != LAP_FP64 || (p->flags & LAP_FLAG_MULTI_RHS)))
         return LAP_EUNSUPPORTED;
     if (p->max_iter < 0) return LAP_EINVAL;
@@ -2722,14 +2728,16 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
             return (lap_status)rc;
         }
         h->n = g->n;
-        if (p->precond == LAP_PREC_PEGP) {
+        if (pegp_like) {
             int64_t nt = 0;
             for (int k = 0; k < h->plan.nlev(); ++k) nt += h->plan.lv[k].g.n;
             if (nt > kPegpMaxNodes || h->plan.nlev() > kPegpMaxLevels) {
                 delete h;
                 return LAP_EUNSUPPORTED;
             }
-            const int prc = build_pegp(h->plan, p->mu, h->pegp_plan);
+            const int prc =
+                build_pegp(h->plan, p->mu, h->pegp_plan,
+                           p->precond == LAP_PREC_OFFTREE ? p->offtree_frac : -1.0);
             if (prc != kOk) {
                 delete h;
                 return (lap_status)prc;
@@ -2916,6 +2924,20 @@ lap_status lap_export_graph(const lap_hierarchy* h, int32_t level, int64_t* ptr,
     if (col)
         for (int64_t k = 0; k < g.nnz(); ++k) col[k] = g.col[k];
     if (w) std::memcpy(w, g.w.data(), g.w.size() * sizeof(double));
+    return LAP_OK;
+}
+
+lap_status lap_export_offtree(const lap_hierarchy* h, int64_t* count, int64_t* a, int64_t* b,
+                              double* w, double* stretch, int8_t* kept) {
+    if (!h || !count || h->params.precond != LAP_PREC_OFFTREE) return LAP_EINVAL;
+    const PegpPlan& G = h->pegp_plan;
+    const size_t c = G.ot_a.size();
+    *count = (int64_t)c;
+    if (a) std::memcpy(a, G.ot_a.data(), c * sizeof(int64_t));
+    if (b) std::memcpy(b, G.ot_b.data(), c * sizeof(int64_t));
+    if (w) std::memcpy(w, G.ot_w.data(), c * sizeof(double));
+    if (stretch) std::memcpy(stretch, G.ot_stretch.data(), c * sizeof(double));
+    if (kept) std::memcpy(kept, G.ot_kept.data(), c);
     return LAP_OK;
 }
 

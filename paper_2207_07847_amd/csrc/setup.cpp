@@ -688,7 +688,163 @@ static void pegp_operator(const HostPlan& P, const std::vector<int32_t>& off,
     for (auto& t : pool) t.join();
 }
 
-int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
+// The off-tree sparsifier of Sec. 3.3 on top of the MSP tree T~ (the
+// sparsifier of the MSP preconditioner: edges inside an aggregate on every
+// level below the top, links from a node to its own aggregate on the next
+// level, all top-level edges).  The positive edges of H~ outside T~ are
+// ranked by their stretch in T~, w_e times the effective resistance between
+// the ends through T~ (the distance of def. stretch-edge, taken as the
+// resistance, as for the total stretch of the bound after it), and the
+// ceil(frac * count) largest are kept (ties to the smaller pair in the
+// levels' own numbering).  Effective resistances come from a grounded
+// LDL^T of the tree Laplacian L_T~ (edge weights mu^(k+l) w_AB): for the
+// right-hand side e_a - e_b, w = L^-1 (e_a - e_b) touches only the
+// elimination-tree paths of a and b, and R = sum_v w_v^2 / d_v.  The
+// weights span mu^(2(l-1)), and a running diagonal would lose the small
+// pivots of coarse nodes to cancellation; every pivot is instead the sum of
+// the magnitudes of its remaining off-diagonal entries (the Schur
+// complements of a Laplacian are Laplacians; Grassmann, Taksar and
+// Heyman's elimination without subtraction), the grounded node included.
+// use[q] is cleared for every H~ edge keys[q] left out.  False: T~ is not
+// positive definite once grounded (not connected).
+static bool select_offtree(const HostPlan& P, const std::vector<int32_t>& off,
+                           const std::vector<std::vector<int32_t>>& par, double mu,
+                           const std::vector<uint64_t>& keys,
+                           const std::unordered_map<uint64_t, double>& acc, double frac,
+                           std::vector<char>& use, PegpPlan& out) {
+    const int L = P.nlev(), T = L - 1;
+    const int32_t nt = off[L], m = nt - 1;
+    std::vector<int> lev(nt);
+    std::vector<int32_t> own(nt);
+    for (int k = 0; k < L; ++k)
+        for (int32_t t = 0; t < off[k + 1] - off[k]; ++t) {
+            lev[off[k] + t] = k;
+            own[off[k] + t] = P.perm[k][t];
+        }
+    auto in_tree = [&](int32_t a, int32_t b) {  // a < b: lev(a) <= lev(b)
+        const int ka = lev[a], kb = lev[b];
+        const int32_t ta = a - off[ka], tb = b - off[kb];
+        if (ka == kb) return ka == T || par[ka][ta] == par[kb][tb];
+        return kb == ka + 1 && par[ka][ta] == tb;
+    };
+    // the tree Laplacian's off-diagonal entries (negative), rows as hash
+    // maps (fill is added as it comes)
+    std::vector<std::unordered_map<int32_t, double>> A(nt);
+    std::vector<int32_t> offq;  // off-tree edges (indices into keys)
+    for (size_t q = 0; q < keys.size(); ++q) {
+        const double w = acc.at(keys[q]);
+        if (!(w > 0.0)) continue;
+        const int32_t a = (int32_t)(keys[q] >> 32), b = (int32_t)(keys[q] & 0xffffffffu);
+        if (!in_tree(a, b)) {
+            offq.push_back((int32_t)q);
+            continue;
+        }
+        const double we = std::pow(mu, lev[a] + lev[b]) * w;
+        A[a][b] -= we;
+        A[b][a] -= we;
+    }
+    // elimination order: level by level from the finest, on each level
+    // below the top the leftovers before the matched nodes; the last top
+    // node is grounded
+    std::vector<int32_t> order, pos(nt, -1);
+    for (int k = 0; k < L; ++k)
+        for (int pass = 0; pass < 2; ++pass)
+            for (int32_t t = 0; t < off[k + 1] - off[k]; ++t) {
+                const bool matched = k < T && P.lv[k].matched[P.perm[k][t]];
+                if (k == T ? pass == 0 : (pass == 0) != matched) order.push_back(off[k] + t);
+            }
+    order.pop_back();  // nt - 1, the ground
+    for (int32_t q = 0; q < m; ++q) pos[order[q]] = q;
+    std::vector<double> piv(nt, 0.0);
+    std::vector<std::vector<std::pair<int32_t, double>>> col(nt);  // l_uv, u later
+    std::vector<int32_t> etp(nt, -1);                                // elimination-tree parent
+    for (int32_t q = 0; q < m; ++q) {
+        const int32_t v = order[q];
+        // remaining neighbours: later in the order, or the ground (pos -1)
+        auto live = [&](int32_t u) { return u != v && (pos[u] > q || u == nt - 1); };
+        double dv = 0.0;
+        for (auto& e : A[v])
+            if (live(e.first)) dv -= e.second;
+        if (!(dv > 0.0) || !std::isfinite(dv)) return false;
+        piv[v] = dv;
+        // the multipliers l_uv of the remaining neighbours (the ground's
+        // only enter the Schur updates: its column is not solved for)
+        std::vector<std::pair<int32_t, double>> c;
+        for (auto& e : A[v])
+            if (live(e.first)) c.push_back({e.first, e.second / dv});
+        std::sort(c.begin(), c.end());
+        // off-diagonal Schur updates only (they add entries of one sign)
+        for (auto& e1 : c)
+            for (auto& e2 : c)
+                if (e2.first != e1.first) A[e1.first][e2.first] -= e1.second * dv * e2.second;
+        int32_t best = -1;
+        for (auto& e : c)
+            if (e.first != nt - 1) {
+                col[v].push_back(e);
+                if (best < 0 || pos[e.first] < pos[best]) best = e.first;
+            }
+        etp[v] = best;
+        A[v].clear();
+    }
+    // stretch of every off-tree edge
+    const size_t cnt = offq.size();
+    std::vector<double> stretch(cnt);
+    std::vector<double> wv(nt, 0.0);
+    std::vector<int32_t> path;
+    for (size_t i = 0; i < cnt; ++i) {
+        const uint64_t key = keys[offq[i]];
+        const int32_t a = (int32_t)(key >> 32), b = (int32_t)(key & 0xffffffffu);
+        path.clear();
+        for (int32_t v = a; v >= 0 && v != nt - 1; v = etp[v]) path.push_back(v);
+        for (int32_t v = b; v >= 0 && v != nt - 1; v = etp[v]) path.push_back(v);
+        // (the ground's column is not part of the factor: etp stops there)
+        std::sort(path.begin(), path.end(), [&](int32_t x, int32_t y) { return pos[x] < pos[y]; });
+        path.erase(std::unique(path.begin(), path.end()), path.end());
+        if (a != nt - 1) wv[a] += 1.0;
+        if (b != nt - 1) wv[b] -= 1.0;
+        double R = 0.0;
+        for (int32_t v : path) {
+            const double x = wv[v];
+            for (auto& e : col[v]) wv[e.first] -= e.second * x;
+            R += x * x / piv[v];
+        }
+        for (int32_t v : path) wv[v] = 0.0;
+        stretch[i] = std::pow(mu, lev[a] + lev[b]) * acc.at(key) * R;
+    }
+    // ranking: stretch descending, ties to the smaller pair (own numbering)
+    auto pair_of = [&](size_t i) {
+        const uint64_t key = keys[offq[i]];
+        const int32_t a = (int32_t)(key >> 32), b = (int32_t)(key & 0xffffffffu);
+        const int64_t oa = off[lev[a]] + own[a], ob = off[lev[b]] + own[b];
+        return std::make_pair(std::min(oa, ob), std::max(oa, ob));
+    };
+    std::vector<size_t> rank(cnt);
+    std::iota(rank.begin(), rank.end(), 0);
+    std::sort(rank.begin(), rank.end(), [&](size_t x, size_t y) {
+        if (stretch[x] != stretch[y]) return stretch[x] > stretch[y];
+        return pair_of(x) < pair_of(y);
+    });
+    const size_t keep = (size_t)std::ceil(frac * (double)cnt - 1e-12);
+    std::vector<int8_t> kept(cnt, 0);
+    for (size_t r = 0; r < std::min(keep, cnt); ++r) kept[rank[r]] = 1;
+    out.ot_a.resize(cnt);
+    out.ot_b.resize(cnt);
+    out.ot_w.resize(cnt);
+    out.ot_stretch = stretch;
+    out.ot_kept = kept;
+    for (size_t i = 0; i < cnt; ++i) {
+        const auto pr = pair_of(i);
+        out.ot_a[i] = pr.first;
+        out.ot_b[i] = pr.second;
+        const uint64_t key = keys[offq[i]];
+        const int32_t a = (int32_t)(key >> 32), b = (int32_t)(key & 0xffffffffu);
+        out.ot_w[i] = std::pow(mu, lev[a] + lev[b]) * acc.at(key);
+        if (!kept[i]) use[offq[i]] = 0;
+    }
+    return true;
+}
+
+int build_pegp(const HostPlan& P, double mu, PegpPlan& out, double offtree_frac) {
     const int L = P.nlev();
     const int T = L - 1;
     out = PegpPlan();
@@ -748,7 +904,13 @@ int build_pegp(const HostPlan& P, double mu, PegpPlan& out) {
     keys.reserve(acc.size());
     for (auto& kv : acc) keys.push_back(kv.first);
     std::sort(keys.begin(), keys.end());
-    for (uint64_t key : keys) {
+    std::vector<char> use(keys.size(), 1);
+    if (offtree_frac >= 0.0 &&
+        !select_offtree(P, out.off, par, mu, keys, acc, offtree_frac, use, out))
+        return kInval;
+    for (size_t q = 0; q < keys.size(); ++q) {
+        if (!use[q]) continue;
+        const uint64_t key = keys[q];
         const double w = acc[key];
         if (!(w > 0.0)) continue;
         const int32_t a = (int32_t)(key >> 32), b = (int32_t)(key & 0xffffffffu);

@@ -1,0 +1,102 @@
+"""The off-tree sparsifier's selection (Sec. 3.3), host part of lap_setup
+(LAP_PREC_OFFTREE, host only): the off-tree edges of H~, their stretches in
+the MSP tree T~ and the edges added back.
+
+Against the oracle (oracle/offtree.py) at mu >= 0.5: the edge set must be
+identical; stretches agree to 1e-9 relative; the kept sets must agree on
+every edge whose stretch is not within 1e-9 of the selection threshold.
+Below mu = 0.5 the oracle's effective resistances, from its elimination of
+T~ with running diagonals, lose accuracy to cancellation (1.4e-8 relative
+at mu = 1/8 on an 8 x 8 grid, 0.8 % at mu = 1/16 on 16 x 16), so there the
+library's stretches are checked against the definition carried out in
+50-digit arithmetic (oracle.dense.offtree_stretch_highprec) instead."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+CASES = {
+    "grid2d_24_loguniform_mu0.5": lambda: (*W.grid2d(24), W.loguniform_weights(1104, 7), 0.5),
+    "chunglu_1500_mu0.8": lambda: (*W.chung_lu(1500, 8.0, 2.1, 5), None, 0.8),
+}
+
+
+def _case(name):
+    n, u, v, w, mu = CASES[name]()
+    if w is None:
+        w = W.uniform01_weights(len(u), 8)
+    assert len(w) == len(u)
+    return n, u, v, w, mu
+
+
+@pytest.mark.parametrize("frac", [0.0, 0.1, 0.3, 1.0])
+@pytest.mark.parametrize("name", list(CASES))
+def test_offtree_selection_matches_oracle(oracle_lib, name, frac):
+    import paper_2207_07847_amd as lap
+    from oracle import Graph, Hierarchy
+    from oracle.offtree import OffTree
+    n, u, v, w, mu = _case(name)
+    h = Hierarchy(Graph(n, u, v, w))
+    ot = OffTree(n, u, v, w, h, mu, frac)
+    H = lap.lap_setup(n, u, v, w, lap.lap_default_params(
+        mu=mu, precond=lap.LAP_PREC_OFFTREE, offtree_frac=frac, flags=lap.LAP_FLAG_HOST_ONLY))
+    try:
+        E = lap.lap_export_offtree(H)
+    finally:
+        lap.lap_free(H)
+    kept_o = set(ot.kept)
+    ora = {(i, j): (s, t in kept_o) for t, ((i, j, _), s) in enumerate(zip(ot.off, ot.stretch))}
+    gpu = {(int(a), int(b)): (s, bool(k)) for a, b, s, k in zip(E["a"], E["b"], E["stretch"],
+                                                                E["kept"])}
+    assert set(gpu) == set(ora), (len(gpu), len(ora))
+    rel = max((abs(gpu[e][0] - ora[e][0]) / ora[e][0] for e in ora), default=0.0)
+    assert rel <= 1e-9, rel
+    assert sum(k for _, k in gpu.values()) == len(kept_o)
+    if 0 < len(kept_o) < len(ora):
+        thr = min(ora[e][0] for e in ora if ora[e][1])
+        differ = [e for e in ora if ora[e][1] != gpu[e][1]]
+        assert all(abs(ora[e][0] - thr) <= 1e-9 * thr for e in differ), differ[:5]
+    # the weights are H~'s: the oracle forms H~ by the sparse products
+    # P(mu)^T L P(mu), whose cancelling sums leave up to ~1e-10 relative on
+    # small entries; the library sums the fine weights of each pair directly
+    wo = {(i, j): x for i, j, x in ot.off}
+    assert max((abs(wt - wo[(int(a), int(b))]) / wo[(int(a), int(b))]
+                for a, b, wt in zip(E["a"], E["b"], E["w"])), default=0.0) <= 1e-9
+
+
+def test_offtree_fraction_out_of_range():
+    import paper_2207_07847_amd as lap
+    n, u, v = W.grid2d(6)
+    for frac in (-0.1, 1.5, float("nan")):
+        with pytest.raises(lap.LapError):
+            lap.lap_setup(n, u, v, W.unit_weights(len(u)), lap.lap_default_params(
+                precond=lap.LAP_PREC_OFFTREE, offtree_frac=frac, flags=lap.LAP_FLAG_HOST_ONLY))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("a", [6, 8])
+def test_offtree_stretch_small_mu_highprec(oracle_lib, a):
+    """mu = 1/sqrt(n) (Tables 2-3): every off-tree edge's stretch against the
+    50-digit definition, weights log-uniform in [0.1, 10]."""
+    import paper_2207_07847_amd as lap
+    from oracle import Graph, Hierarchy, dense
+    n, u, v = W.grid2d(a)
+    w = W.loguniform_weights(len(u), 3, -1, 1)
+    mu = 1.0 / a
+    h = Hierarchy(Graph(n, u, v, w))
+    H = lap.lap_setup(n, u, v, w, lap.lap_default_params(
+        mu=mu, precond=lap.LAP_PREC_OFFTREE, offtree_frac=0.2, flags=lap.LAP_FLAG_HOST_ONLY))
+    try:
+        E = lap.lap_export_offtree(H)
+    finally:
+        lap.lap_free(H)
+    pairs = list(zip(E["a"].tolist(), E["b"].tolist()))
+    ref = dense.offtree_stretch_highprec(n, u, v, w, h.aggs(), mu, pairs, dps=50)
+    rel = np.max(np.abs(E["stretch"] - ref) / ref)
+    print(a, "edges", len(pairs), "max rel stretch error", rel)
+    assert len(pairs) > 0 and rel <= 1e-12
+    # the selection is the top ceil(0.2 count) of these values
+    k = int(np.ceil(0.2 * len(pairs) - 1e-12))
+    thr = np.sort(ref)[::-1][k - 1]
+    far = np.abs(ref - thr) > 1e-9 * thr
+    assert np.array_equal(E["kept"][far] == 1, ref[far] >= thr)
