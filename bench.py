@@ -679,14 +679,28 @@ def main():
         torch.cuda.synchronize()
         other_s = time.time() - t0
         lap.lap_free(h2)
+        # and with the matching on the device as well (the locally dominant
+        # matching: a different hierarchy, not the one timed above)
+        t0 = time.time()
+        h3 = lap.lap_setup(n, wl["u"], wl["v"], wl["w"],
+                           lap.lap_default_params(mu=wl["mu"], max_iter=args.max_iter,
+                                                  precision=prec,
+                                                  flags=flags | lap.LAP_FLAG_DEVICE_SETUP |
+                                                  lap.LAP_FLAG_PARALLEL_MATCHING,
+                                                  precond=pc), sh)
+        torch.cuda.synchronize()
+        par_s = time.time() - t0
+        lap.lap_free(h3)
         line["setup_graphs"] = {
             "host_s": other_s if args.device_setup else setup_s,
             "device_s": setup_s if args.device_setup else other_s,
+            "device_parallel_matching_s": par_s,
             "what": "lap_setup with the adjacency and coarse graphs built on the host, and on "
-                    "the device (LAP_FLAG_DEVICE_SETUP); the rest of the set-up on the host "
-                    "in both"}
+                    "the device (LAP_FLAG_DEVICE_SETUP), the rest of the set-up on the host in "
+                    "both; and with the locally dominant matching on the device too "
+                    "(LAP_FLAG_PARALLEL_MATCHING, a different hierarchy)"}
         log(f"setup: host graphs {line['setup_graphs']['host_s']:.2f}s, device graphs "
-            f"{line['setup_graphs']['device_s']:.2f}s")
+            f"{line['setup_graphs']['device_s']:.2f}s, device graphs and matching {par_s:.2f}s")
     if (not args.no_auto_mu and wl["precond"] == "msp" and args.nrhs == 1 and
             args.precision == "fp64" and args.solver == "pcg" and not capped):
         line["auto_mu"] = auto_mu(lap, wl, args, bd, xd, sh)

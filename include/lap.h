@@ -87,6 +87,21 @@ typedef enum {
                                   build.  The matching and the rest of the
                                   setup stay on the host.  Ignored with
                                   LAP_FLAG_HOST_ONLY. */
+#define LAP_FLAG_PARALLEL_MATCHING 16u /* aggregate every level by the
+                                  locally dominant matching instead of the
+                                  visit-order matching of Sec. 2.2: rounds in
+                                  which every free vertex points at its
+                                  heaviest free neighbour (ties: smaller id)
+                                  and mutual pointers pair up, until no free
+                                  vertex has a free neighbour.  The result is
+                                  the greedy matching by edge weight (ties:
+                                  smaller (i, j)), a different hierarchy from
+                                  the default: pair ids follow the smaller
+                                  end, leftovers join their heaviest
+                                  neighbour as in Sec. 2.2.  On the device
+                                  with LAP_FLAG_DEVICE_SETUP (a thread per
+                                  vertex per round), else on the host;
+                                  mwm_seed is not used. */
 #define LAP_FLAG_FGMRES 4u     /* lap_solve runs FGMRES on the expanded system
                                   L_G~ x~ = P(mu)^T b^ (Sec. 2.2, the solver of
                                   Sec. 4) instead of PCG: right-preconditioned

@@ -68,6 +68,11 @@ def lib():
     L.lr_mwm.argtypes = [vp, vp, _i64p, _i8p]
     L.lr_mwm.restype = C.c_int64
     L.lr_hier_build.argtypes = [vp, C.c_int32, C.c_int64, C.c_uint64, C.POINTER(vp)]
+    L.lr_hier_build_ex.argtypes = [vp, C.c_int32, C.c_int64, C.c_uint64, C.c_int32,
+                                   C.POINTER(vp)]
+    L.lr_hier_build_ex.restype = C.c_int
+    L.lr_greedy_match.argtypes = [vp, _i64p, _i8p]
+    L.lr_greedy_match.restype = C.c_int64
     L.lr_hier_build.restype = C.c_int
     L.lr_hier_free.argtypes = [vp]
     L.lr_hier_nlev.argtypes = [vp]
@@ -158,13 +163,18 @@ class Graph:
         return int(nc), agg, mt.astype(bool)
 
 
-class Hierarchy:
-    """MWM aggregation hierarchy (Sec. 2.2) over a Graph."""
+MATCHINGS = {"visit": 0, "greedy": 1}
 
-    def __init__(self, g: Graph, max_levels=0, n_top=2, seed=0):
+
+class Hierarchy:
+    """Aggregation hierarchy over a Graph: matching "visit" is the
+    visit-order matching of Sec. 2.2 (lr_mwm), "greedy" the greedy matching
+    by edge weight of a parallel setup (lr_greedy_match)."""
+
+    def __init__(self, g: Graph, max_levels=0, n_top=2, seed=0, matching="visit"):
         self._h = C.c_void_p()
-        rc = lib().lr_hier_build(g.handle, int(max_levels), int(n_top),
-                                 int(seed), C.byref(self._h))
+        rc = lib().lr_hier_build_ex(g.handle, int(max_levels), int(n_top),
+                                    int(seed), MATCHINGS[matching], C.byref(self._h))
         if rc != OK:
             raise OracleError(rc, "hierarchy")
         self.g = g
@@ -265,6 +275,14 @@ class MSP:
         y = np.empty(self.h.ntilde)
         lib().lr_msp_solve_expanded(self._f, np.ascontiguousarray(bt, dtype=np.float64), y)
         return y
+
+
+def greedy_match(g: Graph):
+    """(agg, matched, nc) of lr_greedy_match on the fine level of g."""
+    agg = np.empty(g.n, dtype=np.int64)
+    mt = np.empty(g.n, dtype=np.int8)
+    nc = lib().lr_greedy_match(g.handle, agg, mt)
+    return agg, mt, int(nc)
 
 
 def iteration_band(g: Graph, b, tol, maxit, precond, seeds=8, noise=4e-16):

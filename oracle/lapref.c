@@ -170,6 +170,79 @@ int64_t lr_mwm(const lr_csr *g, const int64_t *order, int64_t *agg,
     return nc;
 }
 
+/* The greedy matching by edge weight, the aggregation of a parallel
+ * setup (an alternative to the visit-order matching of Sec. 2.2; not the
+ * paper's): edges {i, j}, i < j, are taken in decreasing weight, ties to
+ * the smaller (i, j) in lexicographic order, and an edge joins the matching
+ * when both its ends are still free.  A pair's aggregate id is its rank
+ * among the pairs ordered by their smaller end.  Vertices left free (all
+ * neighbours matched: the matching is maximal) join the aggregate of their
+ * heaviest neighbour, ties to the smaller id, as in Sec. 2.2. */
+typedef struct {
+    double w;
+    int64_t i, j;
+} gedge_t;
+
+static int cmp_gedge(const void *p, const void *q)
+{
+    const gedge_t *x = (const gedge_t *)p, *y = (const gedge_t *)q;
+    if (x->w != y->w) return x->w > y->w ? -1 : 1;
+    if (x->i != y->i) return x->i < y->i ? -1 : 1;
+    if (x->j != y->j) return x->j < y->j ? -1 : 1;
+    return 0;
+}
+
+int64_t lr_greedy_match(const lr_csr *g, int64_t *agg, int8_t *matched)
+{
+    int64_t n = g->n, m = 0, nc = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = g->ptr[i]; k < g->ptr[i + 1]; ++k)
+            if (g->col[k] > i) ++m;
+    gedge_t *E = (gedge_t *)malloc(sizeof(gedge_t) * (size_t)(m + 1));
+    int64_t t = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = g->ptr[i]; k < g->ptr[i + 1]; ++k)
+            if (g->col[k] > i) {
+                E[t].w = g->w[k];
+                E[t].i = i;
+                E[t].j = g->col[k];
+                ++t;
+            }
+    qsort(E, (size_t)m, sizeof(gedge_t), cmp_gedge);
+    int64_t *mate = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) mate[i] = -1;
+    for (int64_t e = 0; e < m; ++e)
+        if (mate[E[e].i] < 0 && mate[E[e].j] < 0) {
+            mate[E[e].i] = E[e].j;
+            mate[E[e].j] = E[e].i;
+        }
+    free(E);
+    for (int64_t i = 0; i < n; ++i) agg[i] = -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (mate[i] > i) {
+            agg[i] = nc;
+            agg[mate[i]] = nc;
+            ++nc;
+        }
+    if (matched)
+        for (int64_t i = 0; i < n; ++i) matched[i] = (int8_t)(mate[i] >= 0);
+    for (int64_t v = 0; v < n; ++v) {
+        if (mate[v] >= 0) continue;
+        int64_t best = -1;
+        double bw = 0.0;
+        for (int64_t k = g->ptr[v]; k < g->ptr[v + 1]; ++k) {
+            int64_t u = g->col[k];
+            if (best < 0 || g->w[k] > bw || (g->w[k] == bw && u < best)) {
+                best = u;
+                bw = g->w[k];
+            }
+        }
+        agg[v] = agg[best];
+    }
+    free(mate);
+    return nc;
+}
+
 typedef struct {
     int64_t a, b, i, j;
     double w;
@@ -267,6 +340,12 @@ static lr_csr *csr_copy(const lr_csr *g)
 int lr_hier_build(const lr_csr *g, int32_t max_levels, int64_t n_top,
                   uint64_t seed, lr_hier **out)
 {
+    return lr_hier_build_ex(g, max_levels, n_top, seed, 0, out);
+}
+
+int lr_hier_build_ex(const lr_csr *g, int32_t max_levels, int64_t n_top,
+                     uint64_t seed, int32_t matching, lr_hier **out)
+{
     *out = NULL;
     if (!lr_connected(g)) return LR_EDISCONNECTED;
     int cap = 80;
@@ -295,7 +374,7 @@ int lr_hier_build(const lr_csr *g, int32_t max_levels, int64_t n_top,
         }
         int64_t *agg = (int64_t *)malloc(sizeof(int64_t) * (size_t)f->n);
         int8_t *mt = (int8_t *)malloc((size_t)f->n);
-        int64_t nc = lr_mwm(f, order, agg, mt);
+        int64_t nc = matching == 1 ? lr_greedy_match(f, agg, mt) : lr_mwm(f, order, agg, mt);
         free(order);
         if (nc < 2 || nc >= f->n) {
             free(agg);

@@ -65,6 +65,15 @@ int lr_coarsen(const lr_csr *f, const int64_t *agg, int64_t nc, lr_csr **out);
  * permutation seeded with seed + (1-based index of the level aggregated). */
 int lr_hier_build(const lr_csr *g, int32_t max_levels, int64_t n_top,
                   uint64_t seed, lr_hier **out);
+/* The same with the aggregation chosen: matching 0 = the visit-order
+ * matching above (lr_mwm), 1 = the greedy matching by edge weight
+ * (lr_greedy_match; seed unused). */
+int lr_hier_build_ex(const lr_csr *g, int32_t max_levels, int64_t n_top,
+                     uint64_t seed, int32_t matching, lr_hier **out);
+/* Greedy matching aggregation: edges in decreasing weight (ties: smaller
+ * (i, j) first) join while both ends are free; pair ids by the smaller end;
+ * leftovers join their heaviest neighbour's aggregate. */
+int64_t lr_greedy_match(const lr_csr *g, int64_t *agg, int8_t *matched);
 void lr_hier_free(lr_hier *h);
 int32_t lr_hier_nlev(const lr_hier *h);
 int64_t lr_hier_nk(const lr_hier *h, int32_t k);             /* k = 0-based */

@@ -28,6 +28,7 @@ LAP_MIXED_FP32_FP64 = 1
 LAP_FLAG_HOST_ONLY = 1
 LAP_FLAG_FGMRES = 4
 LAP_FLAG_DEVICE_SETUP = 8
+LAP_FLAG_PARALLEL_MATCHING = 16
 LAP_FLAG_MULTI_RHS = 2
 LAP_MAX_LEVELS = 64
 LAP_KERNEL_SPMV, LAP_KERNEL_UPDATE, LAP_KERNEL_DOWN0, LAP_KERNEL_PRECOND, LAP_KERNEL_ITER = range(5)

@@ -4,9 +4,10 @@
 // build_adjacency and coarse_graph, bit for bit.  Both are a stable radix
 // sort of (row, column) keys followed by a sum over each run of equal keys
 // in the order the host sums them (edges in input order; fine entries in
-// CSR order), so every weight is the same double.  The matching between the
-// two stays on the host: it is sequential by definition and a small part of
-// the time.
+// CSR order), so every weight is the same double.  The visit-order matching
+// of Sec. 2.2 between the two stays on the host (it is sequential by
+// definition); the locally dominant matching of the parallel setup runs
+// here, in rounds of a thread per vertex.
 //
 // Included by lap.hip inside its own namespace, after HIPCHK (and
 // hipcub at global scope).
@@ -119,6 +120,144 @@ __global__ void k_coarse_runs(int64_t N, const uint64_t* __restrict__ key,
     uw[pos[i]] = s;
 }
 
+// Locally dominant matching (the host's match_locally_dominant, bit for
+// bit).  One round: every free vertex points at its heaviest free
+// neighbour (neighbours ascending: the first maximum is the smaller id)...
+// Rows longer than this are scanned by a wavefront (k_ld_point_heavy).
+constexpr int kLdHeavy = 64;
+
+__global__ void k_ld_point(int64_t n, const int64_t* __restrict__ ptr,
+                           const int32_t* __restrict__ col, const double* __restrict__ w,
+                           const int32_t* __restrict__ mate, int32_t* __restrict__ best) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || ptr[v + 1] - ptr[v] > kLdHeavy) return;
+    int32_t pick = -1;
+    if (mate[v] < 0) {
+        double pw = -1.0;
+        for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k) {
+            const int32_t nb = col[k];
+            if (mate[nb] >= 0) continue;
+            if (w[k] > pw) {
+                pw = w[k];
+                pick = nb;
+            }
+        }
+    }
+    best[v] = pick;
+}
+
+// The heaviest (free) neighbour of heavy vertex hv[i] by a wavefront: lanes
+// stride over the row, then the (weight, id) maxima are combined, larger
+// weight first, then the smaller id.
+__device__ inline void ld_wave_best(const int64_t* __restrict__ ptr,
+                                    const int32_t* __restrict__ col,
+                                    const double* __restrict__ w,
+                                    const int32_t* __restrict__ mate, int64_t v, bool free_only,
+                                    int lane, double& pw, int32_t& pick) {
+    pw = -1.0;
+    pick = -1;
+    for (int64_t k = ptr[v] + lane; k < ptr[v + 1]; k += 64) {
+        const int32_t nb = col[k];
+        if (free_only && mate[nb] >= 0) continue;
+        if (w[k] > pw) {  // a lane's columns ascend: its first maximum is its smallest id
+            pw = w[k];
+            pick = nb;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ow = __shfl_xor(pw, off, 64);
+        const int32_t op = __shfl_xor(pick, off, 64);
+        if (ow > pw || (ow == pw && op >= 0 && (pick < 0 || op < pick))) {
+            pw = ow;
+            pick = op;
+        }
+    }
+}
+
+__global__ void k_ld_point_heavy(int64_t nh, const int32_t* __restrict__ hv,
+                                 const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                 const double* __restrict__ w, const int32_t* __restrict__ mate,
+                                 int32_t* __restrict__ best) {
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= nh) return;
+    const int64_t v = hv[i];
+    if (mate[v] >= 0) {
+        if (lane == 0) best[v] = -1;
+        return;
+    }
+    double pw;
+    int32_t pick;
+    ld_wave_best(ptr, col, w, mate, v, true, lane, pw, pick);
+    if (lane == 0) best[v] = pick;
+}
+
+// ... and two vertices pointing at each other pair up (each writes its own
+// mate); `changed` counts the vertices paired in the round.
+__global__ void k_ld_pair(int64_t n, const int32_t* __restrict__ best, int32_t* __restrict__ mate,
+                          unsigned int* __restrict__ changed) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t u = best[v];
+    if (u >= 0 && best[u] == (int32_t)v) {
+        mate[v] = u;
+        atomicAdd(changed, 1u);
+    }
+}
+
+// flag[v] = 1 where v is the smaller end of its pair
+__global__ void k_ld_first(int64_t n, const int32_t* __restrict__ mate,
+                           int32_t* __restrict__ flag) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) flag[v] = mate[v] > (int32_t)v;
+}
+
+// Aggregates: a pair's id is the rank of its smaller end (id = exclusive
+// scan of flag); a vertex left free joins its heaviest neighbour's.
+__global__ void k_ld_agg(int64_t n, const int64_t* __restrict__ ptr,
+                         const int32_t* __restrict__ col, const double* __restrict__ w,
+                         const int32_t* __restrict__ mate, const int32_t* __restrict__ id,
+                         int32_t* __restrict__ agg, int8_t* __restrict__ matched) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t m = mate[v];
+    if (m >= 0) {
+        agg[v] = id[min((int32_t)v, m)];
+        matched[v] = 1;
+        return;
+    }
+    if (ptr[v + 1] - ptr[v] > kLdHeavy) return;  // k_ld_agg_heavy
+    int32_t pick = -1;
+    double pw = -1.0;
+    for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k)
+        if (w[k] > pw) {
+            pw = w[k];
+            pick = col[k];
+        }
+    // the matching is maximal: every neighbour of a free vertex is paired
+    agg[v] = id[min(pick, mate[pick])];
+    matched[v] = 0;
+}
+
+__global__ void k_ld_agg_heavy(int64_t nh, const int32_t* __restrict__ hv,
+                               const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                               const double* __restrict__ w, const int32_t* __restrict__ mate,
+                               const int32_t* __restrict__ id, int32_t* __restrict__ agg,
+                               int8_t* __restrict__ matched) {
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= nh) return;
+    const int64_t v = hv[i];
+    if (mate[v] >= 0) return;  // paired: k_ld_agg
+    double pw;
+    int32_t pick;
+    ld_wave_best(ptr, col, w, mate, v, false, lane, pw, pick);
+    if (lane == 0) {
+        agg[v] = id[min(pick, mate[pick])];
+        matched[v] = 0;
+    }
+}
+
 class DeviceGraphBuilder : public GraphBuilder {
   public:
     explicit DeviceGraphBuilder(hipStream_t s) : s_(s) {}
@@ -190,6 +329,82 @@ class DeviceGraphBuilder : public GraphBuilder {
                                cw, cnt);
         finish_csr(nc, N, cnt, ccol, cw, c);
         release(mark);
+    }
+
+    bool match(const Adjacency& g, std::vector<int64_t>& agg, std::vector<int8_t>& matched,
+               int64_t& nc) override {
+        const int64_t n = g.n, nnz = g.nnz();
+        if (n < 2 || n > (int64_t)INT32_MAX || nnz > (int64_t)INT32_MAX) return false;
+        const size_t mark = owned_.size();
+        int64_t* dptr = up(g.ptr.data(), n + 1);
+        int32_t* dcol = up(g.col.data(), nnz);
+        double* dw = up(g.w.data(), nnz);
+        int32_t* mate = alloc<int32_t>(n);
+        int32_t* best = alloc<int32_t>(n);
+        unsigned int* changed = alloc<unsigned int>(1);
+        HIPCHK(hipMemsetAsync(mate, 0xff, (size_t)n * sizeof(int32_t), s_));  // -1: free
+        // rows above kLdHeavy neighbours: a wavefront each
+        std::vector<int32_t> heavy;
+        for (int64_t v = 0; v < n; ++v)
+            if (g.ptr[v + 1] - g.ptr[v] > kLdHeavy) heavy.push_back((int32_t)v);
+        const int64_t nh = (int64_t)heavy.size();
+        int32_t* dh = nh ? up(heavy.data(), nh) : nullptr;
+        const int64_t hblocks = std::max<int64_t>(1, (nh * 64 + kB - 1) / kB);
+        // rounds in batches of kLdBatch between checks: a round after the
+        // last pairing changes nothing
+        constexpr int kLdBatch = 4;
+        unsigned int hc = 0;
+        int rounds = 0;
+        do {
+            HIPCHK(hipMemsetAsync(changed, 0, sizeof(unsigned int), s_));
+            for (int r = 0; r < kLdBatch; ++r) {
+                hipLaunchKernelGGL(k_ld_point, dim3(blocks(n)), dim3(kB), 0, s_, n,
+                                   (const int64_t*)dptr, (const int32_t*)dcol, (const double*)dw,
+                                   (const int32_t*)mate, best);
+                if (nh)
+                    hipLaunchKernelGGL(k_ld_point_heavy, dim3(hblocks), dim3(kB), 0, s_, nh,
+                                       (const int32_t*)dh, (const int64_t*)dptr,
+                                       (const int32_t*)dcol, (const double*)dw,
+                                       (const int32_t*)mate, best);
+                hipLaunchKernelGGL(k_ld_pair, dim3(blocks(n)), dim3(kB), 0, s_, n,
+                                   (const int32_t*)best, mate, changed);
+            }
+            rounds += kLdBatch;
+            HIPCHK(hipMemcpyAsync(&hc, changed, sizeof(hc), hipMemcpyDeviceToHost, s_));
+            HIPCHK(hipStreamSynchronize(s_));
+        } while (hc != 0);
+        if (std::getenv("LAPGPU_DEBUG"))
+            std::fprintf(stderr, "[lapgpu] locally dominant matching: n %lld, %d rounds\n",
+                         (long long)n, rounds);
+        int32_t *flag = alloc<int32_t>(n), *id = alloc<int32_t>(n);
+        hipLaunchKernelGGL(k_ld_first, dim3(blocks(n)), dim3(kB), 0, s_, n, (const int32_t*)mate,
+                           flag);
+        size_t tmp = 0;
+        HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, flag, id, (int)n, s_));
+        void* t = alloc<unsigned char>((int64_t)tmp);
+        HIPCHK(hipcub::DeviceScan::ExclusiveSum(t, tmp, flag, id, (int)n, s_));
+        int32_t* dagg = alloc<int32_t>(n);
+        int8_t* dmt = alloc<int8_t>(n);
+        hipLaunchKernelGGL(k_ld_agg, dim3(blocks(n)), dim3(kB), 0, s_, n, (const int64_t*)dptr,
+                           (const int32_t*)dcol, (const double*)dw, (const int32_t*)mate,
+                           (const int32_t*)id, dagg, dmt);
+        if (nh)
+            hipLaunchKernelGGL(k_ld_agg_heavy, dim3(hblocks), dim3(kB), 0, s_, nh,
+                               (const int32_t*)dh, (const int64_t*)dptr, (const int32_t*)dcol,
+                               (const double*)dw, (const int32_t*)mate, (const int32_t*)id,
+                               dagg, dmt);
+        std::vector<int32_t> a32(n);
+        int32_t last[2];
+        matched.resize(n);
+        HIPCHK(hipMemcpyAsync(a32.data(), dagg, (size_t)n * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipMemcpyAsync(matched.data(), dmt, (size_t)n, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipMemcpyAsync(&last[0], id + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipMemcpyAsync(&last[1], flag + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s_));
+        release(mark);
+        agg.assign(a32.begin(), a32.end());
+        nc = (int64_t)last[0] + last[1];
+        return true;
     }
 
   private:

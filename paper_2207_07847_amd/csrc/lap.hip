@@ -2722,7 +2722,8 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
         }
         DeviceGraphBuilder dgb((hipStream_t)stream);
         const int rc = build_plan(g->n, g->m, g->u, g->v, g->w, p->mu, p->max_levels, p->n_top,
-                                  p->mwm_seed, any_top, h->plan, dev_setup ? &dgb : nullptr);
+                                  p->mwm_seed, any_top, h->plan, dev_setup ? &dgb : nullptr,
+                                  (p->flags & LAP_FLAG_PARALLEL_MATCHING) ? 1 : 0);
         if (rc != kOk) {
             delete h;
             return (lap_status)rc;

@@ -116,6 +116,54 @@ int64_t match_aggregate(const Adjacency& g, const std::vector<int64_t>* order,
     return next;
 }
 
+// Aggregation of the parallel setup: the matching by rounds of locally
+// dominant pairs.  In every round each free vertex points at its heaviest
+// free neighbour (ties: smaller id), and two vertices pointing at each other
+// pair up; rounds go on until no free vertex has a free neighbour.  With
+// that tie rule an edge's rank (weight descending, then the smaller (i, j))
+// is a strict total order, and the result is the greedy matching in that
+// order: the heaviest edge left is always mutual.  Pair ids follow the
+// smaller end; each vertex left free joins its heaviest neighbour's
+// aggregate (ties: smaller id), as in the second pass above.  The device
+// runs the same rounds with a thread per vertex (devsetup.hpp).
+int64_t match_locally_dominant(const Adjacency& g, std::vector<int64_t>& agg,
+                               std::vector<int8_t>& matched) {
+    const int64_t n = g.n;
+    std::vector<int64_t> mate(n, -1), ptr(n, -1);
+    auto heaviest = [&](int64_t v, bool free_only) {
+        int64_t pick = -1;
+        double pw = -1.0;
+        for (int64_t k = g.ptr[v]; k < g.ptr[v + 1]; ++k) {
+            const int32_t nb = g.col[k];
+            if (free_only && mate[nb] >= 0) continue;
+            if (g.w[k] > pw) { pw = g.w[k]; pick = nb; }   // ascending nb: first max wins
+        }
+        return pick;
+    };
+    for (bool changed = true; changed;) {
+        for (int64_t v = 0; v < n; ++v) ptr[v] = mate[v] < 0 ? heaviest(v, true) : -1;
+        changed = false;
+        for (int64_t v = 0; v < n; ++v) {
+            const int64_t u = ptr[v];
+            if (u >= 0 && ptr[u] == v) {
+                mate[v] = u;
+                changed = true;
+            }
+        }
+    }
+    agg.assign(n, -1);
+    matched.assign(n, 0);
+    int64_t next = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (mate[v] > v) {
+            agg[v] = agg[mate[v]] = next++;
+            matched[v] = matched[mate[v]] = 1;
+        }
+    for (int64_t v = 0; v < n; ++v)
+        if (mate[v] < 0) agg[v] = agg[heaviest(v, false)];
+    return next;
+}
+
 // Coarse graph of P^T L P: edges between different aggregates, weights
 // accumulated per unordered aggregate pair in ascending fine (i, j), i < j.
 // Contributions are bucketed by the smaller aggregate id in scan order (a
@@ -267,7 +315,7 @@ static double level_theta(double mu, int k) {
 
 int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                const double* w, double mu, int max_levels, int64_t n_top,
-               uint64_t seed, bool any_top, HostPlan& plan, GraphBuilder* gb) {
+               uint64_t seed, bool any_top, HostPlan& plan, GraphBuilder* gb, int matching) {
     if (!(mu > 0.0 && mu < 1.0) || n_top < 2 || max_levels < 0) return kInval;
     plan = HostPlan();
     plan.mu = mu;
@@ -284,7 +332,9 @@ int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
         std::vector<int64_t> agg;
         std::vector<int8_t> mt;
         int64_t nc;
-        if (seed != 0) {
+        if (matching == 1) {
+            nc = (gb && gb->match(f.g, agg, mt, nc)) ? nc : match_locally_dominant(f.g, agg, mt);
+        } else if (seed != 0) {
             std::vector<int64_t> ord = visit_order(f.g.n, seed + (uint64_t)plan.lv.size());
             nc = match_aggregate(f.g, &ord, agg, mt);
         } else {

@@ -179,11 +179,23 @@ struct GraphBuilder {
                           const double* w, Adjacency& out) = 0;
     virtual void coarse(const Adjacency& f, const std::vector<int64_t>& agg, int64_t nc,
                         Adjacency& c) = 0;
+    // The locally dominant matching of match_locally_dominant, bit for bit;
+    // false: not available here (the host computes it).
+    virtual bool match(const Adjacency& g, std::vector<int64_t>& agg,
+                       std::vector<int8_t>& matched, int64_t& nc) {
+        (void)g; (void)agg; (void)matched; (void)nc;
+        return false;
+    }
     virtual ~GraphBuilder() = default;
 };
+// matching: 0 the visit-order matching of Sec. 2.2 (seed: the order), 1 the
+// locally dominant (greedy) matching of a parallel setup.
 int build_plan(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                const double* w, double mu, int max_levels, int64_t n_top,
-               uint64_t seed, bool any_top, HostPlan& plan, GraphBuilder* gb = nullptr);
+               uint64_t seed, bool any_top, HostPlan& plan, GraphBuilder* gb = nullptr,
+               int matching = 0);
+int64_t match_locally_dominant(const Adjacency& g, std::vector<int64_t>& agg,
+                               std::vector<int8_t>& matched);
 // kOk when the edge list is a valid input: n >= 2, 0 <= u, v < n, u != v,
 // w > 0 finite; kInval otherwise.
 int validate_edges(int64_t n, int64_t m, const int64_t* u, const int64_t* v, const double* w);

@@ -249,3 +249,33 @@ def test_spectrum_and_mu_choice_errors_without_device():
                                 kap.ctypes.data, C.byref(bi), None)
     assert st == lap.LAP_EINVAL and bi.value == -1
     assert np.all(np.isinf(kap))
+
+
+@pytest.mark.parametrize("case", range(9))
+def test_parallel_matching_hierarchy_bit_exact_vs_oracle(oracle_lib, case):
+    """LAP_FLAG_PARALLEL_MATCHING on the host: the locally dominant rounds
+    give the oracle's greedy matching (a global sort by edge weight), level
+    by level, bit for bit, with the same coarse graphs."""
+    from oracle import Graph, Hierarchy
+    lap = _lap()
+    name, (n, u, v), kind = _graphs()[case]
+    w = _weights(kind, len(u), 100 + case)
+    p = lap.lap_default_params(flags=lap.LAP_FLAG_HOST_ONLY | lap.LAP_FLAG_PARALLEL_MATCHING)
+    h = lap.lap_setup(n, u, v, w, p)
+    try:
+        info = lap.lap_hierarchy_info(h)
+        H = Hierarchy(Graph(n, u, v, w), matching="greedy")
+        assert info["sizes"] == H.sizes, name
+        for k in range(info["nlev"] - 1):
+            a, m = lap.lap_export_level(h, k, info["sizes"][k])
+            a2, m2 = H.agg(k)
+            np.testing.assert_array_equal(a, a2)
+            np.testing.assert_array_equal(m, m2)
+        for k in range(info["nlev"]):
+            pt, c, ww = lap.lap_export_graph(h, k, info["sizes"][k])
+            pt2, c2, w2 = H.level_csr(k)
+            np.testing.assert_array_equal(pt, pt2)
+            np.testing.assert_array_equal(c, c2)
+            np.testing.assert_array_equal(ww, w2)
+    finally:
+        lap.lap_free(h)
