@@ -63,14 +63,15 @@ def workload(name, scale, nrhs=1):
     return dict(n=n, u=u, v=v, w=w, b=b, mu=0.8, tol=1e-8, precond="msp")
 
 
-def pmc_traffic(workload_name, scale):
-    """HBM bytes per launch of k_spmv_p from the committed rocprofv3 counter
-    summary, when it was taken on this workload and on the kernel sources
-    as they are now; None otherwise."""
+def pmc_traffic(workload_name, scale, kernel):
+    """HBM bytes per launch of `kernel` (names joined by '+' are summed)
+    from the committed rocprofv3 counter summary of that kernel on this
+    workload (profiles/<first kernel>_<workload>_pmc.txt), when it was taken
+    on the kernel sources as they are now; None otherwise."""
     import hashlib
-    if workload_name != "grid3d_128" or scale != 1.0:
+    if scale != 1.0:
         return None
-    path = os.path.join(ROOT, "profiles", "k_spmv_p_grid3d_128_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('+')[0]}_{workload_name}_pmc.txt")
     csrc = os.path.join(ROOT, "paper_2207_07847_amd", "csrc")
     try:
         text = open(path).read()
@@ -81,13 +82,17 @@ def pmc_traffic(workload_name, scale):
                     h.update(fh.read())
     except OSError:
         return None
-    traffic, sha = None, None
+    per, sha = {}, None
     for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch k_spmv_p:"):
-            traffic = float(line.split(":")[1])
+        if line.startswith("traffic_bytes_per_launch "):
+            k, v = line[len("traffic_bytes_per_launch "):].split(":")
+            per[k.strip()] = float(v)
         elif line.startswith("kernel source sha256[:16]"):
             sha = line.split(":")[-1].strip()
-    return traffic if sha == h.hexdigest()[:16] else None
+    names = kernel.split("+")
+    if sha != h.hexdigest()[:16] or any(k not in per for k in names):
+        return None
+    return sum(per[k] for k in names)
 
 
 def cpu_baseline_fgmres(wl, budget_s):
@@ -581,9 +586,12 @@ def main():
     parts = [(lap.LAP_KERNEL_SPMV, "spmv_p"), (lap.LAP_KERNEL_UPDATE, "update_up0"),
              (lap.LAP_KERNEL_DOWN0, "down0"), (lap.LAP_KERNEL_PRECOND, "update_precond"),
              (lap.LAP_KERNEL_ITER, "iteration")]
+    pegp_op = wl["precond"] == "pegp" and info["pegp_operator_n"] > 0
     if wl["precond"] == "pegp":
-        # the PEGP application has no MSP level parts to time
-        parts = [parts[0], parts[-1]]
+        # the PEGP application has no MSP level parts to time; with the
+        # explicit operator, its matrix-vector product is the dominant kernel
+        parts = [parts[0]] + ([(lap.LAP_KERNEL_PEGP_OP, "pegp_op")] if pegp_op else []) + \
+            [parts[-1]]
     for kid, name in parts:
         ms, by = lap.lap_profile_kernel(h, kid, args.profile_reps, sh)
         kern[name] = {"avg_us": ms * 1e3, "alg_bytes": by, "gbs": by / (ms * 1e-3) / 1e9}
@@ -598,6 +606,9 @@ def main():
     lap.lap_free(h)
 
     spmv = kern["spmv_p"] if args.nrhs == 1 else kern["block_spmm"]
+    dom, dom_name = (kern["pegp_op"], "k_pegp_op") if pegp_op else \
+        (spmv, "k_mm_spmm" if args.nrhs > 1 else
+         "k_spmv_p" if info["spmv_fused"] else "k_pupd+k_spmv_q")
     steps = args.steps * args.nrhs       # right-hand sides solved
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
     line = {
@@ -634,20 +645,24 @@ def main():
         "setup_s": setup_s,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_spmv_p" if args.nrhs == 1 else "k_mm_spmm",
-            "achieved": spmv["gbs"],
+            "kernel": dom_name,
+            "achieved": dom["gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": spmv["gbs"] / HBM_PEAK_GBS,
-            "traffic": pmc_traffic(args.workload, args.scale) if args.precision == "fp64" else None,
+            "frac": dom["gbs"] / HBM_PEAK_GBS,
+            "traffic": pmc_traffic(args.workload, args.scale, dom_name)
+            if args.precision == "fp64" else None,
         },
     }
-    if wl["precond"] == "pegp":
+    if pegp_op:
         line["roofline"]["note"] = (
-            "the SpMV is a small part of a PEGP iteration: its time is in the "
-            "preconditioner's level and dense-tail solves, chains of dependent "
-            "steps bound by latency (per-kernel times in "
-            "profiles/k_pegp_grid2d_64_kernel_trace.txt)")
+            "the operator (opn^2 FP64 entries) fits the 256 MB last-level cache, "
+            "so repeated applications can read it from there rather than HBM")
+    elif wl["precond"] == "pegp":
+        line["roofline"]["note"] = (
+            "the SpMV is a small part of a PEGP iteration applied by the factor: its "
+            "time is in the preconditioner's level and dense-tail solves, chains of "
+            "dependent steps bound by latency")
     if args.nrhs > 1:
         k = 1 if args.precision != "fp64" else 0
         line["autotuned"] = {"spmm_entries_per_item": info["mm_chunk"][k],

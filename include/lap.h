@@ -173,6 +173,12 @@ typedef struct {
     int32_t mm_grid[2];
     int32_t mm_seg[2];
     double mm_tune_seconds;       /* host time of the autotuner in lap_setup */
+    /* 1 if the SpMV of an iteration forms p itself (one kernel, k_spmv_p),
+     * 0 if a separate p pass runs first (k_pupd, then k_spmv_q) */
+    int32_t spmv_fused;
+    /* the fine-node count of the explicit PEGP operator (0: none; PEGP
+     * then runs through its factor) */
+    int32_t pegp_operator_n;
 } lap_hierarchy_desc;
 
 typedef struct lap_hierarchy lap_hierarchy;
@@ -312,12 +318,16 @@ lap_status lap_apply_precond(lap_hierarchy *h, const double *r, double *z,
  *   LAP_KERNEL_BLOCK_SPMM  block solve (LAP_FLAG_MULTI_RHS): Q = L P over 64
  *                       columns (2 n 64 v + (4 + v) nnz bytes, v = value size)
  *   LAP_KERNEL_BLOCK_ITER  one whole iteration of the block solve
+ *   LAP_KERNEL_PEGP_OP  PEGP hierarchy applied by its explicit operator: the
+ *                       matrix-vector product z = M r (8 opn^2 + 20 n bytes:
+ *                       the operator's entries as stored, r and its index
+ *                       read, z written)
  * Errors: LAP_EINVAL (bad id, reps < 1), LAP_EUNSUPPORTED (host-only or a
  * part the hierarchy does not have), LAP_EBREAKDOWN (the iterations hit a
  * breakdown, so the timing is not representative), LAP_EDEVICE. */
 enum { LAP_KERNEL_SPMV = 0, LAP_KERNEL_UPDATE = 1, LAP_KERNEL_DOWN0 = 2,
        LAP_KERNEL_PRECOND = 3, LAP_KERNEL_ITER = 4,
-       LAP_KERNEL_BLOCK_SPMM = 5, LAP_KERNEL_BLOCK_ITER = 6 };
+       LAP_KERNEL_BLOCK_SPMM = 5, LAP_KERNEL_BLOCK_ITER = 6, LAP_KERNEL_PEGP_OP = 7 };
 lap_status lap_profile_kernel(lap_hierarchy *h, int32_t kernel, int32_t reps,
                               void *stream, double *avg_ms, double *alg_bytes);
 

@@ -32,7 +32,7 @@ LAP_FLAG_PARALLEL_MATCHING = 16
 LAP_FLAG_MULTI_RHS = 2
 LAP_MAX_LEVELS = 64
 LAP_KERNEL_SPMV, LAP_KERNEL_UPDATE, LAP_KERNEL_DOWN0, LAP_KERNEL_PRECOND, LAP_KERNEL_ITER = range(5)
-LAP_KERNEL_BLOCK_SPMM, LAP_KERNEL_BLOCK_ITER = 5, 6
+LAP_KERNEL_BLOCK_SPMM, LAP_KERNEL_BLOCK_ITER, LAP_KERNEL_PEGP_OP = 5, 6, 7
 
 
 class lap_graph(C.Structure):
@@ -57,7 +57,8 @@ class lap_hierarchy_desc(C.Structure):
                 ("sizes", C.c_int64 * LAP_MAX_LEVELS), ("ntilde", C.c_int64),
                 ("nnz", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double),
                 ("mm_chunk", C.c_int32 * 2), ("mm_grid", C.c_int32 * 2),
-                ("mm_seg", C.c_int32 * 2), ("mm_tune_seconds", C.c_double)]
+                ("mm_seg", C.c_int32 * 2), ("mm_tune_seconds", C.c_double),
+                ("spmv_fused", C.c_int32), ("pegp_operator_n", C.c_int32)]
 
 
 class lap_request_result(C.Structure):
@@ -213,7 +214,8 @@ def lap_hierarchy_info(h) -> dict:
                 ntilde=d.ntilde, nnz=d.nnz, device_bytes=d.device_bytes,
                 setup_seconds=d.setup_seconds, mm_chunk=list(d.mm_chunk),
                 mm_grid=list(d.mm_grid), mm_seg=list(d.mm_seg),
-                mm_tune_seconds=d.mm_tune_seconds)
+                mm_tune_seconds=d.mm_tune_seconds, spmv_fused=bool(d.spmv_fused),
+                pegp_operator_n=d.pegp_operator_n)
 
 
 def lap_export_level(h, level: int, size: int):

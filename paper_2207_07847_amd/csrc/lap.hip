@@ -601,9 +601,10 @@ void enqueue_precond(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int do_updat
             if (P.opn > 0) {
                 // the explicit operator: one matrix-vector product
                 const int grid = (P.opn + kPegpOpRows - 1) / kPegpOpRows;
-                hipLaunchKernelGGL(k_pegp_op, dim3(grid), dim3(kBlock),
-                                   (uint32_t)(P.opld * sizeof(double)), s, P, h->t2s,
-                                   (const double*)e.r, e.zn, (const Scal*)S, h->part);
+                launch_timed(k_pegp_op, dim3(grid), dim3(kBlock),
+                             (uint32_t)(P.opld * sizeof(double)), s,
+                             mk.start(LAP_KERNEL_PEGP_OP), mk.stop(LAP_KERNEL_PEGP_OP), P,
+                             h->t2s, (const double*)e.r, e.zn, (const Scal*)S, h->part);
                 finish<kFinRho>(h, s, S, grid);
                 return;
             }
@@ -2190,7 +2191,14 @@ lap_status profile(lap_hierarchy* h, Engine<T>& e, int32_t kernel, int32_t reps,
     if ((kernel == LAP_KERNEL_UPDATE || kernel == LAP_KERNEL_DOWN0 ||
          kernel == LAP_KERNEL_PRECOND) && !levels)
         return LAP_EUNSUPPORTED;
-    const double bytes = part_bytes(h, kernel, (double)sizeof(T), levels, e.fuse01);
+    const PegpDev& G = h->pegp_dev;
+    if (kernel == LAP_KERNEL_PEGP_OP && !(h->pegp && G.opn > 0)) return LAP_EUNSUPPORTED;
+    // the explicit PEGP operator: its opn x opn entries as stored, r gathered
+    // through t2s (value and index), z written
+    const double bytes =
+        kernel == LAP_KERNEL_PEGP_OP
+            ? 8.0 * (double)G.opn * (double)G.opn + 20.0 * (double)h->n
+            : part_bytes(h, kernel, (double)sizeof(T), levels, e.fuse01);
     // ITER: two events around all timed iterations; a part: its own kernels'
     // timestamps in every timed iteration
     const bool whole = kernel == LAP_KERNEL_ITER;
@@ -2870,9 +2878,9 @@ lap_status lap_apply_precond(lap_hierarchy* h, const double* r, double* z, void*
 
 lap_status lap_profile_kernel(lap_hierarchy* h, int32_t kernel, int32_t reps, void* stream,
                               double* avg_ms, double* alg_bytes) {
-    if (!h || reps < 1 || kernel < 0 || kernel > LAP_KERNEL_BLOCK_ITER) return LAP_EINVAL;
+    if (!h || reps < 1 || kernel < 0 || kernel > LAP_KERNEL_PEGP_OP) return LAP_EINVAL;
     if (h->host_only) return LAP_EUNSUPPORTED;
-    if (kernel >= LAP_KERNEL_BLOCK_SPMM) {
+    if (kernel == LAP_KERNEL_BLOCK_SPMM || kernel == LAP_KERNEL_BLOCK_ITER) {
         if (!h->has_block) return LAP_EUNSUPPORTED;
         return h->mixed ? profile_block(h, h->m32, kernel, reps, (hipStream_t)stream, avg_ms,
                                         alg_bytes)
@@ -2895,6 +2903,8 @@ lap_status lap_hierarchy_info(const lap_hierarchy* h, lap_hierarchy_desc* d) {
     d->nnz = h->plan.lv[0].g.nnz();
     d->device_bytes = h->dev_bytes;
     d->setup_seconds = h->setup_seconds;
+    d->spmv_fused = h->fuse_p ? 1 : 0;
+    d->pegp_operator_n = h->pegp ? h->pegp_dev.opn : 0;
     if (h->has_block) {
         d->mm_chunk[0] = h->m64.chunk;
         d->mm_grid[0] = h->m64.grid;

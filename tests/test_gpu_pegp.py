@@ -187,3 +187,28 @@ def test_pegp_c1_solve(oracle_lib, mode):
     say(msg)
     assert st == 0 and info["iterations"] == ref.iterations, msg
     assert host <= 1.01e-8 and diff <= 1e-7, msg
+
+
+def test_pegp_operator_profile_part(oracle_lib):
+    """The operator's matrix-vector product is timed on its own
+    (LAP_KERNEL_PEGP_OP), with 8 n^2 + 20 n algorithmic bytes; a hierarchy
+    that runs through the factor has no such part."""
+    import paper_2207_07847_amd as lap
+    n, u, v = W.grid2d(32)
+    w = W.unit_weights(len(u))
+    for mode in MODES:
+        with _mode(mode):
+            G = GpuLap(n, u, v, w, mu=1 / 32.0, precond=lap.LAP_PREC_PEGP)
+        try:
+            opn = G.info["pegp_operator_n"]
+            if mode == "operator":
+                assert opn == n
+                ms, by = lap.lap_profile_kernel(G.h, lap.LAP_KERNEL_PEGP_OP, 10, G.stream())
+                say(f"pegp operator n {n}: {ms * 1e3:.1f} us, {by / 1e6:.2f} MB")
+                assert by == 8.0 * n * n + 20.0 * n and 0.0 < ms < 10.0
+            else:
+                assert opn == 0
+                with pytest.raises(lap.LapError):
+                    lap.lap_profile_kernel(G.h, lap.LAP_KERNEL_PEGP_OP, 10, G.stream())
+        finally:
+            G.close()
