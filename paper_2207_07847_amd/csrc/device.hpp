@@ -31,6 +31,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace lapgpu {
@@ -348,20 +350,42 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(int nlb, Sell<T> A, const T* 
     block_partial<1>(v, part);
 }
 
+// One entry of the new search direction, p = (zn - zbar) + beta p_old, as
+// one fused multiply-add, so that every kernel that forms it gets the same
+// bits.
+template <class T>
+__device__ inline T p_next(T zn, T zbar, T beta, T po) {
+    if constexpr (std::is_same<T, double>::value) return __builtin_fma(beta, po, zn - zbar);
+    else return __builtin_fmaf(beta, po, zn - zbar);
+}
+
 // p = zn - zbar + beta p_old (solve order), for the SpMV below, and the
-// previous step x += alpha p_old.
+// previous step x += alpha p_old.  The blocks past the first ceil(n/kBlock)
+// also form the compact copy of p's hot columns, ph[k] = p[hot[k]], from
+// the same inputs (p_old is not written here, so the two agree bit for bit).
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_pupd(int n, const T* __restrict__ zn,
                                                  const T* __restrict__ pold, T* __restrict__ pnew,
-                                                 T* __restrict__ x, const Scal* S) {
+                                                 T* __restrict__ x, const Scal* S, int nhot,
+                                                 const int32_t* __restrict__ hot,
+                                                 T* __restrict__ ph) {
     const int done = S->done;
     const T beta = (T)S->beta, zbar = (T)S->zbar, alpha = (T)S->alpha;
     if (done) return;
-    const int t = xcd_block() * kBlock + threadIdx.x;
-    if (t < n) {
-        const T po = pold[t];
-        pnew[t] = (zn[t] - zbar) + beta * po;
-        x[t] += alpha * po;
+    const int b = xcd_block(), nbm = (n + kBlock - 1) / kBlock;
+    if (b < nbm) {
+        const int t = b * kBlock + threadIdx.x;
+        if (t < n) {
+            const T po = pold[t];
+            pnew[t] = p_next(zn[t], zbar, beta, po);
+            x[t] += alpha * po;
+        }
+    } else {
+        const int k = (b - nbm) * kBlock + threadIdx.x;
+        if (k < nhot) {
+            const int c = hot[k];
+            ph[k] = p_next(zn[c], zbar, beta, pold[c]);
+        }
     }
 }
 
@@ -385,8 +409,19 @@ __global__ __launch_bounds__(kBlock) void k_last_step(int n, T* __restrict__ x,
 
 // q = L p with p already formed (one gathered vector per neighbour instead
 // of two: the choice for graphs whose gathers are scattered); partial p^T q.
+//
+// With hot columns (ph non-null), A's column arrays name a hot column c as
+// ~rank(c) and its value is read from the compact copy ph[rank]: the most
+// referenced columns of a graph without locality then share cache lines,
+// which stay in the L2 of every XCD, instead of one line each.
+template <class T>
+__device__ inline T gather_hot(const T* __restrict__ p, const T* __restrict__ ph, int j) {
+    return j >= 0 ? p[j] : ph[~j];
+}
+
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_spmv_q(int nlb, Sell<T> A, const T* __restrict__ p,
+                                                   const T* __restrict__ ph,
                                                    T* __restrict__ q, Scal* S, double* part) {
     if (S->done) return;
     const int lb = spmv_block(A.nheavyblk);
@@ -396,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_q(int nlb, Sell<T> A, const T* 
         if (slot < A.nlight) {
             const int row = A.row ? A.row[slot] : slot;
             const T pi = p[row];
-            const T acc = light_row(A, slot, [&](int j) { return pi - p[j]; });
+            const T acc = light_row(A, slot, [&](int j) { return pi - gather_hot(p, ph, j); });
             q[row] = acc;
             v[0] = (double)pi * (double)acc;
         }
@@ -405,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_q(int nlb, Sell<T> A, const T* 
             A, -1 - lb,
             [&](int row) {
                 const T pi = p[row];
-                return [=](int j) { return pi - p[j]; };
+                return [=](int j) { return pi - gather_hot(p, ph, j); };
             },
             [&](int row, T acc) {
                 q[row] = acc;

@@ -336,6 +336,7 @@ struct Engine {
     int nb01 = 0;
     // workspace: input order
     T *x = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *zn = nullptr;
+    T* ph = nullptr;             // compact copy of p's hot columns (nhot)
     // workspace: tree order
     T *r = nullptr, *z = nullptr;
     hipStream_t cap = nullptr;   // private capture stream
@@ -444,6 +445,10 @@ struct lap_hierarchy {
     const int32_t* t2s = nullptr;   // tree position -> solve position (null: same)
     const int32_t* sperm = nullptr; // solve position -> input vertex (null: same)
     bool fuse_p = true;             // SpMV forms p on the fly (else a p pass first)
+    // hot columns of the separate-p SpMV (k_spmv_q): nhot most referenced
+    // columns, their list and the column arrays that name them by rank
+    int32_t nhot = 0;
+    const int32_t *hot = nullptr, *hot_col = nullptr, *hot_hcol = nullptr;
     std::vector<const int32_t*> cptr, bst;
     std::vector<int32_t> nb;
     Sell<double> Ai{};           // the index arrays of the SpMV matrix (weights unset)
@@ -713,12 +718,18 @@ void enqueue_iteration(lap_hierarchy* h, Engine<T>& e, hipStream_t s, int par,
                      h->part);
     } else {
         const int n = (int)h->n;
-        launch_timed(k_pupd<T>, dim3(nblk(n)), dim3(kBlock), 0, s, mk.start(LAP_KERNEL_SPMV),
-                     (hipEvent_t) nullptr, n, (const T*)e.zn, (const T*)e.p[par], e.p[1 - par],
-                     e.x, (const Scal*)h->S);
+        launch_timed(k_pupd<T>, dim3(nblk(n) + nblk(h->nhot)), dim3(kBlock), 0, s,
+                     mk.start(LAP_KERNEL_SPMV), (hipEvent_t) nullptr, n, (const T*)e.zn,
+                     (const T*)e.p[par], e.p[1 - par], e.x, (const Scal*)h->S, h->nhot, h->hot,
+                     e.ph);
+        Sell<T> A = e.A;
+        if (h->nhot > 0) {
+            A.col = h->hot_col;
+            A.hcol = h->hot_hcol;
+        }
         launch_timed(k_spmv_q<T>, dim3(e.spmv_grid()), dim3(kBlock), 0, s, (hipEvent_t) nullptr,
-                     mk.stop(LAP_KERNEL_SPMV), e.nlb, e.A, (const T*)e.p[1 - par], e.q, h->S,
-                     h->part);
+                     mk.stop(LAP_KERNEL_SPMV), e.nlb, A, (const T*)e.p[1 - par],
+                     (const T*)e.ph, e.q, h->S, h->part);
     }
     finish<kFinPq>(h, s, h->S, e.spmv_grid());
     enqueue_precond(h, e, s, 1, mk);
@@ -763,6 +774,20 @@ void upload_shared(lap_hierarchy* h, hipStream_t s) {
     A.hrow = h->upload(P.heavy_row, s);
     A.hptr = h->upload(P.heavy_ptr, s);
     A.hcol = h->upload(P.heavy_col, s);
+    // hot columns: only for the separate-p SpMV over a vector well beyond
+    // what the L2 of one XCD holds (4 MB); a copy of 2^16 values (512 KB)
+    // took the SpMV of a 3.9M-vertex Chung-Lu graph from 846 to 707 us
+    // (2^18: 714 us, 2^20: 757 us)
+    int64_t nh = h->fuse_p || h->n < (int64_t)1 << 19 ? 0 : std::min<int64_t>(h->n / 8, 1 << 16);
+    nh = env_int("LAPGPU_HOT_COLS", (int)nh);
+    if (!h->fuse_p && nh > 0) {
+        std::vector<int32_t> hot, col, hcol;
+        hot_columns(P, h->n, nh, hot, col, hcol);
+        h->nhot = (int32_t)hot.size();
+        h->hot = h->upload(hot, s);
+        h->hot_col = h->upload(col, s);
+        h->hot_hcol = h->upload(hcol, s);
+    }
 }
 
 // The SpMV matrix, the preconditioner and the workspace of one value type.
@@ -796,6 +821,7 @@ void upload_engine(lap_hierarchy* h, Engine<T>& e, hipStream_t s, bool with_leve
     e.p[1] = h->dalloc<T>(n);
     e.r = h->dalloc<T>(n);
     e.z = h->dalloc<T>(n);
+    if (h->nhot > 0) e.ph = h->dalloc<T>(h->nhot);
     if (!with_levels) return;
     // the tail: the lowest level from which all coarser levels fit in LDS
     const int tail_max = env_int("LAPGPU_TAIL_MAX", 1 << 30);

@@ -586,6 +586,31 @@ void build_sell(const Adjacency& g, HostPlan& plan) {
     if (in_blk > 0) plan.heavy_blk.push_back((int32_t)heavy.size());
 }
 
+void hot_columns(const HostPlan& plan, int64_t n, int64_t count, std::vector<int32_t>& hot,
+                 std::vector<int32_t>& sell_col, std::vector<int32_t>& heavy_col) {
+    std::vector<int64_t> refs(n, 0);
+    // light slots: only the real entries (a padding slot holds its own row
+    // with weight 0)
+    for (size_t t = 0; t < plan.sell_col.size(); ++t)
+        if (plan.sell_w[t] != 0.0) ++refs[plan.sell_col[t]];
+    for (int32_t c : plan.heavy_col) ++refs[c];
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    count = std::min<int64_t>(count, n);
+    std::partial_sort(order.begin(), order.begin() + count, order.end(), [&](int32_t a, int32_t b) {
+        return refs[a] != refs[b] ? refs[a] > refs[b] : a < b;
+    });
+    hot.assign(order.begin(), order.begin() + count);
+    std::vector<int32_t> rank(n, -1);
+    for (int64_t k = 0; k < count; ++k) rank[hot[k]] = (int32_t)k;
+    sell_col = plan.sell_col;
+    for (size_t t = 0; t < sell_col.size(); ++t)
+        if (plan.sell_w[t] != 0.0 && rank[sell_col[t]] >= 0) sell_col[t] = ~rank[sell_col[t]];
+    heavy_col = plan.heavy_col;
+    for (int32_t& c : heavy_col)
+        if (rank[c] >= 0) c = ~rank[c];
+}
+
 // ------------------------------------------------------------------ PEGP
 
 // How many lanes share a row in the rows [r0, r1) of a PEGP solve level

@@ -204,6 +204,13 @@ void build_sell(const Adjacency& g, HostPlan& plan);
 // Whether g is mesh-like for the SpMV: no row above kHeavyDeg and slices of
 // consecutive rows padded by at most 15 %.
 bool mesh_like(const Adjacency& g);
+// The hot columns of the SpMV matrix: the `count` columns referenced most
+// often (ties to the smaller column), hot[k] = column of rank k, and copies
+// of the matrix's column arrays in which every reference to a hot column c
+// reads ~rank(c) (negative), so a kernel can gather those values from a
+// compact copy of the vector.  Padding slots keep their own row.
+void hot_columns(const HostPlan& plan, int64_t n, int64_t count, std::vector<int32_t>& hot,
+                 std::vector<int32_t>& sell_col, std::vector<int32_t>& heavy_col);
 // g renumbered: new id of old vertex i is inv[i], rows ascending.
 void permute_graph(const Adjacency& g, const std::vector<int32_t>& perm,
                    const std::vector<int32_t>& inv, Adjacency& out);
