@@ -66,12 +66,12 @@ def workload(name, scale, nrhs=1):
 def pmc_traffic(workload_name, scale, kernel):
     """HBM bytes per launch of `kernel` (names joined by '+' are summed)
     from the committed rocprofv3 counter summary of that kernel on this
-    workload (profiles/<first kernel>_<workload>_pmc.txt), when it was taken
+    workload (profiles/<last kernel>_<workload>_pmc.txt), when it was taken
     on the kernel sources as they are now; None otherwise."""
     import hashlib
     if scale != 1.0:
         return None
-    path = os.path.join(ROOT, "profiles", f"{kernel.split('+')[0]}_{workload_name}_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel.split('+')[-1]}_{workload_name}_pmc.txt")
     csrc = os.path.join(ROOT, "paper_2207_07847_amd", "csrc")
     try:
         text = open(path).read()

@@ -309,7 +309,8 @@ lap_status lap_apply_precond(lap_hierarchy *h, const double *r, double *z,
  *   LAP_KERNEL_SPMV     p update + q = L p + p^T q, with the previous
  *                       iteration's x step riding along (48 n + 12 nnz
  *                       bytes: z, p_old, x read, p, q, x written, and col,
- *                       w of the matrix)
+ *                       w of the matrix; 56 n + 12 nnz where p is formed
+ *                       in a pass of its own, for graphs without locality)
  *   LAP_KERNEL_UPDATE   x, r update + level-0 restriction and pair solves
  *   LAP_KERNEL_DOWN0    level-0 prolongation + z, r^T z reductions
  *   LAP_KERNEL_PRECOND  update through down0: the x, r update and the
