@@ -656,8 +656,9 @@ def main():
     }
     if pegp_op:
         line["roofline"]["note"] = (
-            "the operator (opn^2 FP64 entries) fits the 256 MB last-level cache, "
-            "so repeated applications can read it from there rather than HBM")
+            "the operator (opn^2 FP64 entries, 134 MB here) is smaller than the 256 MB "
+            "last-level cache, so part of each read may be served there: the L2 fetches "
+            "it once per launch either way")
     elif wl["precond"] == "pegp":
         line["roofline"]["note"] = (
             "the SpMV is a small part of a PEGP iteration applied by the factor: its "
