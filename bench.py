@@ -124,10 +124,25 @@ def cpu_baseline_fgmres(wl, budget_s):
     }
 
 
-def cpu_baseline(wl, gpu_iters, budget_s):
+def oracle_iterations(name, scale, mu):
+    """The oracle's own iteration count for the whole solve, where a
+    committed script under tests/golden/ (calling only oracle/) has stored
+    it; None elsewhere."""
+    if name != "grid3d_128" or scale != 1.0 or mu != 0.8:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", "grid3d_128_mu08.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return int(d["iterations"]) if d.get("status") == 0 else None
+
+
+def cpu_baseline(wl, iters, budget_s, whose):
     """The oracle (single thread) on a bounded number of PCG iterations of
     the same solve, scaled to solves/s by the iteration count the solve
-    needs."""
+    needs (`whose`: where that count comes from)."""
     from oracle import MSP, Graph, Hierarchy, pcg
     t0 = time.time()
     g = Graph(wl["n"], wl["u"], wl["v"], wl["w"])
@@ -142,13 +157,58 @@ def cpu_baseline(wl, gpu_iters, budget_s):
     dt = time.time() - t0
     per_it = dt / res.iterations
     return {
-        "value": 1.0 / (per_it * gpu_iters),
+        "value": 1.0 / (per_it * iters),
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
         "sample": (f"{res.iterations} PCG iterations of the same solve in {dt:.1f} s "
                    f"({per_it * 1e3:.1f} ms/iteration, setup {setup_s:.1f} s untimed), "
-                   f"scaled by the {gpu_iters} iterations the solve takes"),
+                   f"scaled by the {iters} iterations the solve takes ({whose})"),
+    }, per_it
+
+
+def _cpu_worker(name, scale, mu, k, barrier, out):
+    """One single-threaded oracle process of the all-cores baseline: its
+    own hierarchy (untimed), then k PCG iterations once every process is
+    ready."""
+    from oracle import MSP, Graph, Hierarchy, pcg
+    wl = workload(name, scale)
+    g = Graph(wl["n"], wl["u"], wl["v"], wl["w"])
+    M = MSP(Hierarchy(g), mu)
+    barrier.wait()
+    t0 = time.time()
+    res = pcg(g, wl["b"], 0.0, k, M)
+    out.put((time.time() - t0) / res.iterations)
+
+
+def cpu_baseline_all_cores(name, scale, mu, iters, per_it1, budget_s, whose):
+    """The oracle on all host cores the run may use (at most 16, the host
+    share of one GPU): one single-threaded oracle process per core, each on
+    the same bounded sample, started together; whole-host throughput is the
+    sum of the processes' rates.  Spawned interpreters that never touch the
+    GPU."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    k = max(3, int(budget_s / per_it1))
+    ctx = mp.get_context("spawn")
+    barrier, out = ctx.Barrier(cores), ctx.Queue()
+    procs = [ctx.Process(target=_cpu_worker, args=(name, scale, mu, k, barrier, out))
+             for _ in range(cores)]
+    for p in procs:
+        p.start()
+    per = [out.get() for _ in procs]
+    for p in procs:
+        p.join()
+    rate = sum(1.0 / (t * iters) for t in per)
+    return {
+        "value": rate,
+        "unit": "solves/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{cores} single-threaded oracle processes, {k} PCG iterations of the same "
+                   f"solve each, started together ({min(per) * 1e3:.1f}-{max(per) * 1e3:.1f} "
+                   f"ms/iteration; setup untimed), each scaled by the {iters} iterations the "
+                   f"solve takes ({whose})"),
     }
 
 
@@ -468,6 +528,8 @@ def main():
                     help="with --nrhs > 1: columns timed as single FP64 solves beside it")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-all-cores", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the oracle in one process per host core (at most 16)")
     ap.add_argument("--profile-reps", type=int, default=100)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -723,7 +785,15 @@ def main():
     if not args.no_cpu:
         if args.workload == "grid3d_128" and args.scale == 1.0 and args.solver == "pcg":
             log("cpu baseline (oracle) ...")
-            line["cpu_baseline"] = cpu_baseline(wl, inf["iterations"], args.cpu_seconds)
+            it = oracle_iterations(args.workload, args.scale, wl["mu"])
+            whose = "the oracle's own count, tests/golden/grid3d_128_mu08.json" if it else \
+                "the GPU's count; the oracle's is not stored for this setting"
+            it = it or inf["iterations"]
+            line["cpu_baseline"], per_it = cpu_baseline(wl, it, args.cpu_seconds, whose)
+            if args.cpu_all_cores:
+                log("cpu baseline (oracle) on all host cores ...")
+                line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(
+                    args.workload, args.scale, wl["mu"], it, per_it, args.cpu_seconds, whose)
         elif args.workload == "grid2d_64" and args.solver == "fgmres":
             log("cpu baseline (oracle FGMRES) ...")
             line["cpu_baseline"] = cpu_baseline_fgmres(wl, args.cpu_seconds)
