@@ -4,8 +4,10 @@ The GPU runs FGMRES in the original space with expanded inner products
 (every basis vector lies in the range of P(mu)^T); the oracle runs it on
 expanded vectors with the grounded expanded solve.  Both minimise the same
 residual over the same Krylov spaces, so the step counts must agree up to
-rounding (one step), and both solutions must meet the residual they stop
-on.
+rounding (one step), both solutions must meet the residual they stop on,
+and the GPU's solution must equal the oracle's FGMRES iterate after the
+same number of steps within 1e-7 relative (the solution bar of the PCG
+parity tests; what is left is rounding).
 """
 import numpy as np
 import pytest
@@ -16,12 +18,17 @@ from gpu_util import GpuLap, say
 pytestmark = pytest.mark.gpu
 
 
-def _oracle_fgmres(n, u, v, w, b, precond, mu, max_levels=0):
+def _oracle_fgmres(n, u, v, w, b, precond, mu, max_levels=0, same_steps=None):
+    """The oracle's FGMRES to tol 1e-8, and (same_steps) its iterate after
+    exactly that many steps (tol 0)."""
     from oracle import MSP, Graph, Hierarchy
     from oracle.fgmres import fgmres_expanded
     from oracle.pegp import PEGP
     h = Hierarchy(Graph(n, u, v, w), max_levels=max_levels)
     M = MSP(h, mu) if precond == "msp" else PEGP(n, u, v, w, h.aggs(), mu)
+    if same_steps is not None:
+        return fgmres_expanded(n, u, v, w, h.aggs(), mu, b, M.solve_expanded, tol=0.0,
+                               maxit=same_steps)
     return fgmres_expanded(n, u, v, w, h.aggs(), mu, b, M.solve_expanded)
 
 
@@ -51,13 +58,17 @@ def test_fgmres_table3_grids(oracle_lib, a, precond, mu, ml):
         st, x, info = G.solve(b, 1e-8)
     finally:
         G.close()
-    say("fgmres", n, precond, "mu", mu, "level", ml or "max", "gpu", info["iterations"],
-        "oracle", ref.iterations, "est", info["relres_recursive"], "true", info["relres_true"])
-    assert st == 0 and abs(info["iterations"] - ref.iterations) <= 1
-    assert info["relres_recursive"] <= 1e-8
+    same = _oracle_fgmres(n, u, v, w, b, precond, mu, ml, same_steps=info["iterations"])
+    d_same = np.linalg.norm(x - same.x) / np.linalg.norm(same.x)
+    msg = (f"fgmres {n} {precond} mu {mu:.4g} level {ml or 'max'}: gpu {info['iterations']} "
+           f"oracle {ref.iterations} steps; est {info['relres_recursive']:.3e} true "
+           f"{info['relres_true']:.3e}; x vs oracle at the same step count {d_same:.2e}")
+    say(msg)
+    assert st == 0 and abs(info["iterations"] - ref.iterations) <= 1, msg
+    assert info["relres_recursive"] <= 1e-8, msg
     # the original residual is the expanded one's image: same order
-    assert _host_relres(n, u, v, w, b, x) <= 3e-8
-    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-5
+    assert _host_relres(n, u, v, w, b, x) <= 3e-8, msg
+    assert d_same <= 1e-7, msg
 
 
 def test_fgmres_weighted_powerlaw(oracle_lib):
