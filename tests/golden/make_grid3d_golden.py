@@ -16,8 +16,12 @@ For each size this records, from the oracle only:
     relative noise 4e-16 on L p and M r).
 
 Run from the repository root:  python tests/golden/make_grid3d_golden.py [a ...]
-(default 40 48 128; 128 takes about 70 minutes of one core for the
+(default 40 48 128; 128 takes about 3.5 hours of one core for the
 converged solve).  Output: tests/golden/grid3d_<a>_mu08.json.
+
+    python tests/golden/make_grid3d_golden.py --band a
+adds the rounding band (the eight noise runs, one process each) to an
+existing grid3d_<a>_mu08.json (128: about 4 hours on eight cores).
 """
 import json
 import multiprocessing as mp
@@ -111,5 +115,22 @@ def main(sizes):
         print("wrote", path, flush=True)
 
 
+def add_band(a):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"grid3d_{a}_mu08.json")
+    with open(path) as f:
+        d = json.load(f)
+    jobs = [(a, "band", s) for s in range(1, SEEDS + 1)]
+    with mp.get_context("fork").Pool(len(jobs)) as pool:
+        d["band_runs"] = sorted(out["iterations"] for _, _, _, out in pool.imap_unordered(task, jobs))
+    its = [d["iterations"]] + d["band_runs"]
+    d["band"] = [min(its), max(its)]
+    with open(path, "w") as f:
+        json.dump(d, f, indent=0)
+    print("wrote", path, flush=True)
+
+
 if __name__ == "__main__":
-    main([int(t) for t in sys.argv[1:]] or [40, 48, 128])
+    if sys.argv[1:2] == ["--band"]:
+        add_band(int(sys.argv[2]))
+    else:
+        main([int(t) for t in sys.argv[1:]] or [40, 48, 128])
