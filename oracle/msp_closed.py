@@ -72,15 +72,24 @@ def closed_form(h, mu):
     return apply
 
 
-def pcg_exact_sums(g, M, b, tol, maxit):
+def pcg_exact_sums(g, M, b, tol, maxit, noise=0.0, seed=0):
     """The oracle's PCG steps (x0 = 0, z = M r - mean, stop at ||r|| <=
     tol ||b^||) with every inner product and mean summed by math.fsum.
-    Returns (iterations, x)."""
+    noise > 0 applies the oracle's rounding model on top: every L p and
+    every M r multiplied entrywise by (1 + noise u), u uniform in [-1, 1)
+    (numpy's generator seeded with `seed`).  Returns (iterations, x)."""
+    rng = np.random.default_rng(seed)
+
     def dot(a, c):
         return math.fsum(a * c)
 
     def mean(a):
         return math.fsum(a) / len(a)
+
+    def perturb(a):
+        if noise > 0.0:
+            a = a * (1.0 + noise * (2.0 * rng.random(len(a)) - 1.0))
+        return a
 
     bh = b - mean(b)
     nb = math.sqrt(dot(bh, bh))
@@ -88,20 +97,20 @@ def pcg_exact_sums(g, M, b, tol, maxit):
     if nb == 0.0:
         return 0, x
     r = bh.copy()
-    z = M(r)
+    z = perturb(M(r))
     z = z - mean(z)
     p = z.copy()
     rho = dot(r, z)
     it = 0
     while it < maxit:
-        q = g.apply(p)
+        q = perturb(g.apply(p))
         a = rho / dot(p, q)
         x += a * p
         r -= a * q
         it += 1
         if math.sqrt(dot(r, r)) <= tol * nb:
             break
-        z = M(r)
+        z = perturb(M(r))
         z = z - mean(z)
         rho2 = dot(r, z)
         p = z + (rho2 / rho) * p

@@ -19,9 +19,18 @@ Run from the repository root:  python tests/golden/make_grid3d_golden.py [a ...]
 (default 40 48 128; 128 takes about 3.5 hours of one core for the
 converged solve).  Output: tests/golden/grid3d_<a>_mu08.json.
 
-    python tests/golden/make_grid3d_golden.py --band a
-adds the rounding band (the eight noise runs, one process each) to an
-existing grid3d_<a>_mu08.json (128: about 4 hours on eight cores).
+    python tests/golden/make_grid3d_golden.py --band a [seeds]
+adds the rounding band (noise runs 1..seeds, default 8, one process each)
+to an existing grid3d_<a>_mu08.json (128: about 4 hours a run).
+
+    python tests/golden/make_grid3d_golden.py --exact seeds a [a ...]
+adds to grid3d_<a>_mu08_exact.json the same solve with every inner product
+and mean summed exactly (math.fsum, oracle.msp_closed.pcg_exact_sums),
+with the oracle's elimination of T~ and with the MSP's closed form, each
+unperturbed (seed 0) and with the noise model for seeds 1..seeds:
+iterations and x at the sample.  On these grids the oracle's sequential
+sums over n terms of widely spread magnitude are the largest rounding in
+the solve, so these runs show how far the count moves with it.
 """
 import json
 import multiprocessing as mp
@@ -115,11 +124,47 @@ def main(sizes):
         print("wrote", path, flush=True)
 
 
-def add_band(a):
+def exact_task(job):
+    from oracle.msp_closed import closed_form, pcg_exact_sums
+    a, kind, seed = job
+    t0 = time.time()
+    n, b, g, h, M = _problem(a)
+    idx = sample_index(n)
+    apply = M.apply if kind == "elimination" else closed_form(h, MU)
+    it, x = pcg_exact_sums(g, apply, b, TOL, MAXIT, noise=NOISE if seed else 0.0, seed=seed)
+    print(f"grid3d {a}: exact sums, {kind}, seed {seed}: {it} iterations in "
+          f"{time.time() - t0:.0f} s", flush=True)
+    return a, dict(precond=kind, seed=seed, iterations=it, xnorm=float(np.linalg.norm(x)),
+                   x=[float(t) for t in x[idx]])
+
+
+def add_exact(seeds, sizes, procs, first=0):
+    jobs = [(a, kind, s) for a in sizes for kind in ("elimination", "closed_form")
+            for s in range(first, seeds + 1)]
+    res = {a: [] for a in sizes}
+    with mp.get_context("fork").Pool(min(procs, len(jobs))) as pool:
+        for a, out in pool.imap_unordered(exact_task, jobs):
+            res[a].append(out)
+    for a in sizes:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"grid3d_{a}_mu08_exact.json")
+        runs = res[a]
+        if os.path.exists(path):
+            with open(path) as f:
+                old = json.load(f)["runs"]
+            have = {(r["precond"], r.get("seed", 0)) for r in runs}
+            runs += [r for r in old if (r["precond"], r.get("seed", 0)) not in have]
+        runs.sort(key=lambda r: (r["precond"], r.get("seed", 0)))
+        with open(path, "w") as f:
+            json.dump(dict(workload=f"grid3d {a}^3, as grid3d_{a}_mu08.json", mu=MU, tol=TOL,
+                           noise=NOISE, sample_seed=W.MASTER_SEED + 77, runs=runs), f, indent=0)
+        print("wrote", path, flush=True)
+
+
+def add_band(a, seeds=SEEDS):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"grid3d_{a}_mu08.json")
     with open(path) as f:
         d = json.load(f)
-    jobs = [(a, "band", s) for s in range(1, SEEDS + 1)]
+    jobs = [(a, "band", s) for s in range(1, seeds + 1)]
     with mp.get_context("fork").Pool(len(jobs)) as pool:
         d["band_runs"] = sorted(out["iterations"] for _, _, _, out in pool.imap_unordered(task, jobs))
     its = [d["iterations"]] + d["band_runs"]
@@ -131,6 +176,10 @@ def add_band(a):
 
 if __name__ == "__main__":
     if sys.argv[1:2] == ["--band"]:
-        add_band(int(sys.argv[2]))
+        add_band(int(sys.argv[2]), int(sys.argv[3]) if len(sys.argv) > 3 else SEEDS)
+    elif sys.argv[1:2] == ["--exact"]:
+        add_exact(int(sys.argv[2]), [int(t) for t in sys.argv[3:]],
+                  int(os.environ.get("GOLDEN_PROCS", "8")),
+                  int(os.environ.get("GOLDEN_FIRST_SEED", "0")))
     else:
         main([int(t) for t in sys.argv[1:]] or [40, 48, 128])

@@ -1,9 +1,12 @@
 """GPU checks at the benchmark's full size: 3D 7-point grid 128^3 with
 weights 10^U(-3,3), MSP mu = 0.8, in the launch configuration bench.py
-times.  The oracle cannot afford a whole solve at this size (tens of
-thousands of iterations), so every step is checked on its own instead:
-hierarchy outputs bit for bit, L x and M r element by element, and the
-solve by its FP64 residual recomputed on the host with the oracle's L."""
+times.  Every step is checked on its own (hierarchy outputs bit for bit,
+L x and M r element by element), and the whole solve against the
+oracle's own full solve, stored by tests/golden/make_grid3d_golden.py
+(about 3.5 hours of one host core): the iteration count within the band
+of the oracle's FP64 variants (test_gpu_grid3d_family.py says why a band),
+the converged solution at a sample of 4096 vertices within 1e-7, and the
+FP64 residual recomputed on the host with the oracle's L."""
 import numpy as np
 import pytest
 
@@ -66,11 +69,13 @@ def test_fullsize_precond(oracle_lib, full):
 
 
 def test_fullsize_solve(oracle_lib, full):
+    from test_gpu_grid3d_family import check_solve
     say("fullsize: gpu solve")
     b, g, G = full["b"], full["g"], full["G"]
     st, x, info = G.solve(b, 1e-8)
     say("  ", info)
     assert st == 0 and info["relres_true"] <= 1e-8
+    check_solve(128, st, x, info)
     bh = b - b.mean()
     rel = np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh)
     say("  host relres", rel)

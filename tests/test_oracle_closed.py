@@ -104,6 +104,33 @@ def test_pcg_exact_sums_solves(oracle_lib):
     assert pcg_exact_sums(g, closed_form(h, 0.8), np.full(n, 2.0), 1e-8, 10)[0] == 0
 
 
+def test_pcg_exact_sums_noise_model(oracle_lib):
+    """The rounding model of the exact-sum PCG: noise 0 is the unperturbed
+    run bit for bit; relative noise 4e-16 on L p and M r moves the solution
+    only at rounding level (the converged x agrees with the unperturbed one
+    and with pinv(L) b^), different seeds perturb differently, and a large
+    noise visibly changes the iteration count's path (the model is live)."""
+    from oracle import dense
+    from oracle.msp_closed import closed_form, pcg_exact_sums
+    n, u, v = W.grid2d(7, 6)
+    w = W.loguniform_weights(len(u), 9, -1, 1)
+    g, h = _setup(n, u, v, w)
+    b = W.gaussian_rhs(n, 10)
+    M = closed_form(h, 0.8)
+    xs = np.linalg.pinv(dense.laplacian(n, u, v, w)) @ (b - b.mean())
+    k0, x0 = pcg_exact_sums(g, M, b, 1e-12, 500)
+    k0b, x0b = pcg_exact_sums(g, M, b, 1e-12, 500, noise=0.0, seed=5)
+    assert k0 == k0b and np.array_equal(x0, x0b)
+    k1, x1 = pcg_exact_sums(g, M, b, 1e-12, 500, noise=4e-16, seed=1)
+    k2, x2 = pcg_exact_sums(g, M, b, 1e-12, 500, noise=4e-16, seed=2)
+    assert abs(k1 - k0) <= 2 and abs(k2 - k0) <= 2
+    for x in (x1, x2):
+        assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    assert not np.array_equal(x1, x0) and not np.array_equal(x1, x2)
+    k3, _ = pcg_exact_sums(g, M, b, 1e-12, 500, noise=0.3, seed=1)
+    assert k3 != k0
+
+
 def test_band_and_the_cause_of_lower_counts(oracle_lib):
     """The rounding band holds the oracle's own count, and on these two
     workloads the more accurate evaluations (closed form, correctly rounded
