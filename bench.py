@@ -215,6 +215,27 @@ def cpu_baseline_all_cores(name, scale, mu, iters, per_it1, budget_s, whose):
     }
 
 
+def device_copy_rate(torch, nbytes=2 * 2**30, reps=20):
+    """GB/s (bytes read plus written) of a plain device-to-device copy moving
+    nbytes per launch, 2 GiB by default: far beyond the 256 MB Infinity
+    Cache, so it measures what HBM gives a read-write stream on this GPU,
+    beside the kernels' rates (a copy that fits the cache runs faster)."""
+    half = max(1, int(nbytes // 16))
+    src = torch.ones(half, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 16.0 * half / dt / 1e9
+
+
 def measure(lap, h, bd, xd, n, tol, steps, warmup, sh, stream, capped, nrhs=1):
     """Warm-up solves, then `steps` timed solves (of nrhs columns each);
     per-solve latency from HIP events on the solve stream."""
@@ -718,6 +739,14 @@ def main():
             "traffic": pmc_traffic(args.workload, args.scale, dom_name, args.precision),
         },
     }
+    copy = device_copy_rate(torch)
+    line["device_copy"] = {
+        "gbs": copy, "bytes": 2 * 2**30,
+        "kernel_over_copy": dom["gbs"] / copy,
+        "what": "torch device-to-device copy of 1 GiB into 1 GiB (2 GiB read plus written "
+                "per launch, beyond the 256 MB Infinity Cache), back to back: the rate HBM "
+                "gives a plain read-write stream on this GPU, beside the dominant kernel's"}
+    log(f"device copy (2 GiB moved): {copy:.0f} GB/s; kernel / copy {dom['gbs'] / copy:.3f}")
     if pegp_op:
         line["roofline"]["note"] = (
             "the operator (opn^2 FP64 entries, 134 MB here) is smaller than the 256 MB "
