@@ -63,6 +63,114 @@ def select(edges, stretch, frac):
     return sorted(order[:k])
 
 
+def h_edges(Ht):
+    """Every positive edge of H~ as (i, j, w), i < j, in (i, j) order (the
+    same rounding-size filter as offtree_edges)."""
+    return offtree_edges(Ht, np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64))
+
+
+def max_weight_spanning_tree(nt, edges):
+    """Kruskal's algorithm on H~'s edges (i, j, w): the heaviest first, ties
+    to the smaller pair; an edge joining two components is kept.  Returns
+    the indices of the nt - 1 tree edges, in (i, j) order."""
+    parent = list(range(nt))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    tree = []
+    for t in sorted(range(len(edges)), key=lambda t: (-edges[t][2], edges[t][0], edges[t][1])):
+        i, j, _ = edges[t]
+        ri, rj = find(i), find(j)
+        if ri != rj:
+            parent[ri] = rj
+            tree.append(t)
+    if len(tree) != nt - 1:
+        raise ValueError("H~ is not connected")
+    return sorted(tree)
+
+
+def subgraph_laplacian(nt, edges):
+    """L of the subgraph with the given (i, j, w) edges on nt nodes."""
+    eu = [e[0] for e in edges]
+    ev = [e[1] for e in edges]
+    ew = [e[2] for e in edges]
+    A = sp.coo_matrix((ew, (eu, ev)), shape=(nt, nt)).tocsr()
+    A = A + A.T
+    return (sp.diags(np.asarray(A.sum(axis=1)).ravel()) - A).tocsr()
+
+
+def grounded_solver(Lsub):
+    """y with Lsub y = e (grounded at the last node); differences y_i - y_j
+    do not depend on the grounding."""
+    nt = Lsub.shape[0]
+    lu = spla.splu(Lsub[:-1, :-1].tocsc())
+
+    def solve(e):
+        y = np.zeros(nt)
+        y[:-1] = lu.solve(np.asarray(e, dtype=np.float64)[:-1])
+        return y
+
+    return solve
+
+
+class _SubgraphPreconditioner:
+    """z = P(mu) pinv(L_S) P(mu)^T r (mean-free) for a subgraph S of H~
+    given by its edges, solved like PEGP: the grounded, scaled system
+    D L_S D by a sparse LU."""
+
+    def _factor(self, n, aggs, mu, edges, permc_spec):
+        self.Hk = subgraph_laplacian(self.nt, edges)
+        sizes = [n] + [int(np.max(a)) + 1 for a in aggs]
+        self.d = np.concatenate([np.full(s, mu ** (-k)) for k, s in enumerate(sizes)])
+        S = (sp.diags(self.d) @ self.Hk @ sp.diags(self.d)).tocsc()
+        self._lu = spla.splu(S[:-1, :-1].tocsc(), permc_spec=permc_spec)
+
+    def solve_expanded(self, bt):
+        """Grounded solve of L_S y~ = b~ (the last node grounded)."""
+        y = np.zeros(self.nt)
+        y[:-1] = self._lu.solve((self.d * np.asarray(bt, dtype=np.float64))[:-1])
+        return y * self.d
+
+    def apply(self, r):
+        y = self.solve_expanded(self.Pmu.T @ np.asarray(r, dtype=np.float64))
+        z = self.Pmu @ y
+        return z - z.mean()
+
+    __call__ = apply
+
+
+class SpanningOffTree(_SubgraphPreconditioner):
+    """The other tree of Sec. 3.3's remark: a maximum-weight spanning tree
+    of H~ (Kruskal), with its off-tree edges of largest stretch added back
+    (stretch = w_e times the effective resistance between the ends through
+    the tree, ranked and selected as for the MSP tree), solved like PEGP.
+    frac = 1 gives PEGP."""
+
+    def __init__(self, n, u, v, w, h, mu, frac, permc_spec="COLAMD"):
+        self.n = int(n)
+        self.mu = float(mu)
+        aggs = h.aggs()
+        L = laplacian_sparse(n, np.asarray(u), np.asarray(v), np.asarray(w, dtype=np.float64))
+        self.Pmu = p_mu_sparse(aggs, n, mu)
+        Ht = positive_part((self.Pmu.T @ L @ self.Pmu).tocsr())
+        self.nt = Ht.shape[0]
+        edges = h_edges(Ht)
+        tree_idx = max_weight_spanning_tree(self.nt, edges)
+        in_tree = np.zeros(len(edges), dtype=bool)
+        in_tree[tree_idx] = True
+        self.tree_edges = [edges[t] for t in tree_idx]
+        self.off = [e for e, t in zip(edges, in_tree) if not t]
+        solve_tree = grounded_solver(subgraph_laplacian(self.nt, self.tree_edges))
+        self.stretch = stretch_in_tree(self.off, solve_tree, self.nt)
+        self.kept = select(self.off, self.stretch, frac)
+        self._factor(n, aggs, mu, self.tree_edges + [self.off[t] for t in self.kept],
+                     permc_spec)
+
+
 class OffTree:
     """z = P(mu) pinv(L_Hk~) P(mu)^T r (mean-free), H_k~ = T~ plus the
     selected off-tree edges of H~."""

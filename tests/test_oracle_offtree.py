@@ -109,3 +109,90 @@ def test_nested_sparsifier_pencils(oracle_lib, case):
             assert nz.max() <= total * (1 + 1e-9)
         prev = nz.max()
     assert abs(prev - 1.0) <= 1e-9                      # frac = 1: H_k~ = H~
+
+
+# The other tree: a maximum-weight spanning tree of H~ (oracle.offtree.SpanningOffTree).
+
+@pytest.mark.parametrize("case", range(4))
+def test_spanning_tree_is_a_maximum_weight_spanning_tree(oracle_lib, case):
+    """nt - 1 edges of H~ that connect every node, and the largest total
+    weight: against scipy's minimum spanning tree of the order-reversed
+    weights (every spanning tree has nt - 1 edges, so maximising sum w is
+    minimising sum (c - w))."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components, minimum_spanning_tree
+    from oracle.offtree import SpanningOffTree, h_edges
+    n, u, v, w, h, mu = _setup(case)
+    M = SpanningOffTree(n, u, v, w, h, mu, 0.0)
+    nt = M.nt
+    assert len(M.tree_edges) == nt - 1
+    T = sp.coo_matrix(([1.0] * (nt - 1), ([e[0] for e in M.tree_edges],
+                                          [e[1] for e in M.tree_edges])), shape=(nt, nt))
+    assert connected_components(T, directed=False)[0] == 1
+    H, _ = _dense(n, u, v, w, h, mu)
+    edges = h_edges(sp.csr_matrix(H))
+    c = 1.0 + max(e[2] for e in edges)
+    G = sp.coo_matrix(([c - e[2] for e in edges], ([e[0] for e in edges], [e[1] for e in edges])),
+                      shape=(nt, nt)).tocsr()
+    best = (nt - 1) * c - minimum_spanning_tree(G).sum()
+    mine = sum(e[2] for e in M.tree_edges)
+    assert abs(mine - best) <= 1e-12 * best
+    # every tree edge is an edge of H~ with its weight
+    for (i, j, x) in M.tree_edges:
+        assert abs(x + H[i, j]) <= 1e-13 * x
+
+
+@pytest.mark.parametrize("case", [1, 3])
+def test_spanning_stretch_is_the_tree_path_resistance(oracle_lib, case):
+    """Stretch w_e * R_tree(i, j): R summed along the tree path (1 / weight
+    per edge), found by a breadth-first search, not by solves."""
+    from collections import deque
+    from oracle.offtree import SpanningOffTree
+    n, u, v, w, h, mu = _setup(case)
+    M = SpanningOffTree(n, u, v, w, h, mu, 0.3)
+    adj = {k: [] for k in range(M.nt)}
+    for (i, j, x) in M.tree_edges:
+        adj[i].append((j, x))
+        adj[j].append((i, x))
+    for t, (i, j, x) in enumerate(M.off):
+        res = {i: 0.0}
+        q = deque([i])
+        while q:
+            a = q.popleft()
+            for b, y in adj[a]:
+                if b not in res:
+                    res[b] = res[a] + 1.0 / y
+                    q.append(b)
+        assert abs(M.stretch[t] - x * res[j]) <= 1e-12 * x * res[j]
+    # the kept edges are the largest stretches
+    k = len(M.kept)
+    assert k == int(np.ceil(0.3 * len(M.off) - 1e-12))
+    thr = min(M.stretch[t] for t in M.kept)
+    assert all(M.stretch[t] <= thr for t in range(len(M.off)) if t not in set(M.kept))
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_spanning_ends_tree_alone_and_pegp(oracle_lib, case):
+    """frac = 0: P(mu) pinv(L_tree) P(mu)^T r against a dense pseudo-inverse
+    of the tree's Laplacian; frac = 1: every edge of H~ is back, PEGP."""
+    from oracle import dense
+    from oracle.offtree import SpanningOffTree
+    from oracle.pegp import PEGP
+    n, u, v, w, h, mu = _setup(case)
+    r = _rhs(n, 40 + case)
+    M0 = SpanningOffTree(n, u, v, w, h, mu, 0.0)
+    Lt = np.zeros((M0.nt, M0.nt))
+    for (i, j, x) in M0.tree_edges:
+        Lt[i, j] -= x
+        Lt[j, i] -= x
+        Lt[i, i] += x
+        Lt[j, j] += x
+    Pm = dense.p_mu(h.aggs(), n, mu)
+    z0 = Pm @ np.linalg.pinv(Lt) @ Pm.T @ r
+    z0 -= z0.mean()
+    z = M0.apply(r)
+    assert np.linalg.norm(z - z0) <= 1e-9 * np.linalg.norm(z0)
+    M1 = SpanningOffTree(n, u, v, w, h, mu, 1.0)
+    assert len(M1.kept) == len(M1.off)
+    z1 = PEGP(n, u, v, w, h.aggs(), mu).apply(r)
+    assert np.linalg.norm(M1.apply(r) - z1) <= 1e-10 * np.linalg.norm(z1)
