@@ -51,7 +51,7 @@ typedef enum {
                                expanded graphs of at most 19,456 nodes (the
                                sum of all level sizes) in at most 64 levels */
     LAP_PREC_NONE = 2,      /* plain conjugate gradients */
-    LAP_PREC_OFFTREE = 3    /* the MSP tree T~ with off-tree edges of H~ added
+    LAP_PREC_OFFTREE = 3,   /* the MSP tree T~ with off-tree edges of H~ added
                                back (Sec. 3.3, the sparsifiers after its
                                stretch bound): the ceil(offtree_frac * count)
                                off-tree edges of largest stretch in T~ (w_e
@@ -60,6 +60,15 @@ typedef enum {
                                solved like PEGP on that subgraph of H~ (the
                                same limits).  offtree_frac 0 gives the MSP
                                operator, 1 the PEGP one */
+    LAP_PREC_SPANNING = 4   /* the same with the other tree of Sec. 3.3's
+                               remark: a maximum-weight spanning tree of H~
+                               (Kruskal: heaviest edge first, ties to the
+                               smaller pair), its off-tree edges ranked by
+                               stretch (w_e times the resistance of the tree
+                               path between the ends) and the largest
+                               ceil(offtree_frac * count) added back, solved
+                               like PEGP (the same limits).  offtree_frac 1
+                               gives the PEGP operator */
 } lap_precond;
 
 typedef enum {
@@ -139,7 +148,7 @@ typedef struct {
     int32_t precision;    /* lap_precision */
     int32_t max_iter;     /* iteration cap of lap_solve (default 1000) */
     uint32_t flags;       /* LAP_FLAG_* */
-    double offtree_frac;  /* LAP_PREC_OFFTREE: fraction in [0, 1] of the
+    double offtree_frac;  /* LAP_PREC_OFFTREE, LAP_PREC_SPANNING: fraction in [0, 1] of the
                              off-tree edges added back (default 0.1) */
 } lap_params;
 
@@ -221,8 +230,9 @@ lap_status lap_set_allocator(lap_alloc_fn alloc, lap_free_fn free, void *ctx);
  * larger than the on-chip coarse solve allows; PEGP or the off-tree
  * sparsifier with mixed precision, with LAP_FLAG_MULTI_RHS, or with an
  * expanded graph above 19,456 nodes or 64 levels).  LAP_EINVAL also for
- * LAP_PREC_OFFTREE with offtree_frac outside [0, 1].  PEGP (Sec. 3.2) factors the grounded, level-scaled
- * L_H~ once on the host (sparse LDL^T) and applies it on the device. */
+ * LAP_PREC_OFFTREE or LAP_PREC_SPANNING with offtree_frac outside [0, 1].
+ * PEGP (Sec. 3.2) factors the grounded, level-scaled L_H~ once on the host
+ * (sparse LDL^T) and applies it on the device. */
 lap_status lap_setup(const lap_graph *g, const lap_params *p, void *stream,
                      lap_hierarchy **out);
 
@@ -368,13 +378,14 @@ lap_status lap_select_mu(const lap_graph *g, const lap_params *p, const double *
 /* Sizes and memory of a hierarchy.  Errors: LAP_EINVAL on NULL. */
 lap_status lap_hierarchy_info(const lap_hierarchy *h, lap_hierarchy_desc *d);
 
-/* The off-tree edges of a LAP_PREC_OFFTREE hierarchy: *count receives
+/* The off-tree edges of a LAP_PREC_OFFTREE or LAP_PREC_SPANNING hierarchy
+ * (outside T~, or outside the spanning tree): *count receives
  * their number; each array (host, count entries; any may be NULL) receives
  * per edge its ends a < b as expanded indices (level offset, the sum of the
  * sizes of the finer levels, plus the node's id in its level's own
  * numbering, as lap_export_level uses), its weight in H~, its stretch in
- * T~, and kept = 1 if it was added back.  Errors: LAP_EINVAL (NULL, or not
- * an off-tree hierarchy). */
+ * its tree, and kept = 1 if it was added back.  Errors: LAP_EINVAL (NULL,
+ * or not an off-tree hierarchy). */
 lap_status lap_export_offtree(const lap_hierarchy *h, int64_t *count, int64_t *a, int64_t *b,
                               double *w, double *stretch, int8_t *kept);
 

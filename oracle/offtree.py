@@ -69,10 +69,30 @@ def h_edges(Ht):
     return offtree_edges(Ht, np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64))
 
 
+TIE_REL = 1e-9
+
+
+def kruskal_order(edges):
+    """The order Kruskal takes H~'s edges (i, j, w) in: heaviest first, and
+    weights that agree to TIE_REL relative taken as equal (runs of sorted
+    weights whose consecutive gaps are all within it), ordered by the
+    smaller pair.  H~ has structurally equal weights (the pairs (i,
+    parent(j)) and (j, parent(i)) of one fine edge, for one), which
+    evaluations of H~ in FP64 may round apart by far less than that."""
+    by_w = sorted(range(len(edges)), key=lambda t: -edges[t][2])
+    group = {}
+    g = 0
+    for r, t in enumerate(by_w):
+        if r and edges[by_w[r - 1]][2] - edges[t][2] > TIE_REL * edges[by_w[r - 1]][2]:
+            g += 1
+        group[t] = g
+    return sorted(range(len(edges)), key=lambda t: (group[t], edges[t][0], edges[t][1]))
+
+
 def max_weight_spanning_tree(nt, edges):
-    """Kruskal's algorithm on H~'s edges (i, j, w): the heaviest first, ties
-    to the smaller pair; an edge joining two components is kept.  Returns
-    the indices of the nt - 1 tree edges, in (i, j) order."""
+    """Kruskal's algorithm on H~'s edges (i, j, w) in kruskal_order; an
+    edge joining two components is kept.  Returns the indices of the
+    nt - 1 tree edges, in (i, j) order."""
     parent = list(range(nt))
 
     def find(a):
@@ -82,7 +102,7 @@ def max_weight_spanning_tree(nt, edges):
         return a
 
     tree = []
-    for t in sorted(range(len(edges)), key=lambda t: (-edges[t][2], edges[t][0], edges[t][1])):
+    for t in kruskal_order(edges):
         i, j, _ = edges[t]
         ri, rj = find(i), find(j)
         if ri != rj:

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "liblapgpu.so")
 
 LAP_OK, LAP_EINVAL, LAP_EDISCONNECTED, LAP_ENOMEM, LAP_EDEVICE, LAP_ENOCONV, \
     LAP_EBREAKDOWN, LAP_EUNSUPPORTED = range(8)
-LAP_PREC_MSP, LAP_PREC_PEGP, LAP_PREC_NONE, LAP_PREC_OFFTREE = 0, 1, 2, 3
+LAP_PREC_MSP, LAP_PREC_PEGP, LAP_PREC_NONE, LAP_PREC_OFFTREE, LAP_PREC_SPANNING = 0, 1, 2, 3, 4
 LAP_FP64 = 0
 LAP_MIXED_FP32_FP64 = 1
 LAP_FLAG_HOST_ONLY = 1
@@ -240,7 +240,7 @@ def lap_export_graph(h, level: int, size: int):
 
 
 def lap_export_offtree(h):
-    """Off-tree edges of a LAP_PREC_OFFTREE hierarchy: dict of arrays a, b
+    """Off-tree edges of a LAP_PREC_OFFTREE or LAP_PREC_SPANNING hierarchy: dict of arrays a, b
     (expanded indices in the levels' own numbering), w, stretch, kept."""
     cnt = C.c_int64()
     st = _lib.lap_export_offtree(C.c_void_p(h), C.byref(cnt), None, None, None, None, None)

@@ -1018,7 +1018,8 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     const int64_t n = h->n;
     h->with_msp = (h->params.precond == LAP_PREC_MSP);
     // the off-tree sparsifier is solved like PEGP, on its own subgraph
-    h->pegp = (h->params.precond == LAP_PREC_PEGP || h->params.precond == LAP_PREC_OFFTREE);
+    h->pegp = (h->params.precond == LAP_PREC_PEGP || h->params.precond == LAP_PREC_OFFTREE ||
+               h->params.precond == LAP_PREC_SPANNING);
     h->mixed = (h->params.precision == LAP_MIXED_FP32_FP64);
     upload_shared(h, s);
     if (h->pegp) upload_pegp(h, s);
@@ -2722,13 +2723,14 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
     *out = nullptr;
     if (!g || !p || !g->u || !g->v || !g->w) return LAP_EINVAL;
     if (p->precond != LAP_PREC_MSP && p->precond != LAP_PREC_NONE &&
-        p->precond != LAP_PREC_PEGP && p->precond != LAP_PREC_OFFTREE)
+        p->precond != LAP_PREC_PEGP && p->precond != LAP_PREC_OFFTREE &&
+        p->precond != LAP_PREC_SPANNING)
         return LAP_EINVAL;
     if (p->precision != LAP_FP64 && p->precision != LAP_MIXED_FP32_FP64) return LAP_EINVAL;
     // PEGP: FP64 single solves only
-    const bool pegp_like = p->precond == LAP_PREC_PEGP || p->precond == LAP_PREC_OFFTREE;
-    if (p->precond == LAP_PREC_OFFTREE && !(p->offtree_frac >= 0.0 && p->offtree_frac <= 1.0))
-        return LAP_EINVAL;
+    const bool offtree = p->precond == LAP_PREC_OFFTREE || p->precond == LAP_PREC_SPANNING;
+    const bool pegp_like = p->precond == LAP_PREC_PEGP || offtree;
+    if (offtree && !(p->offtree_frac >= 0.0 && p->offtree_frac <= 1.0)) return LAP_EINVAL;
     if (pegp_like &&
         (p->precision != LAP_FP64 || (p->flags & LAP_FLAG_MULTI_RHS)))
         return LAP_EUNSUPPORTED;
@@ -2771,8 +2773,8 @@ lap_status lap_setup(const lap_graph* g, const lap_params* p, void* stream, lap_
                 return LAP_EUNSUPPORTED;
             }
             const int prc =
-                build_pegp(h->plan, p->mu, h->pegp_plan,
-                           p->precond == LAP_PREC_OFFTREE ? p->offtree_frac : -1.0);
+                build_pegp(h->plan, p->mu, h->pegp_plan, offtree ? p->offtree_frac : -1.0,
+                           p->precond == LAP_PREC_SPANNING ? 1 : 0);
             if (prc != kOk) {
                 delete h;
                 return (lap_status)prc;
@@ -2966,7 +2968,9 @@ lap_status lap_export_graph(const lap_hierarchy* h, int32_t level, int64_t* ptr,
 
 lap_status lap_export_offtree(const lap_hierarchy* h, int64_t* count, int64_t* a, int64_t* b,
                               double* w, double* stretch, int8_t* kept) {
-    if (!h || !count || h->params.precond != LAP_PREC_OFFTREE) return LAP_EINVAL;
+    if (!h || !count ||
+        (h->params.precond != LAP_PREC_OFFTREE && h->params.precond != LAP_PREC_SPANNING))
+        return LAP_EINVAL;
     const PegpPlan& G = h->pegp_plan;
     const size_t c = G.ot_a.size();
     *count = (int64_t)c;

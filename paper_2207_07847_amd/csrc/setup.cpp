@@ -919,7 +919,149 @@ static bool select_offtree(const HostPlan& P, const std::vector<int32_t>& off,
     return true;
 }
 
-int build_pegp(const HostPlan& P, double mu, PegpPlan& out, double offtree_frac) {
+// The other tree: a maximum-weight spanning tree of H~ (Kruskal: heaviest
+// edge first, weights within kTieRel of each other, runs of sorted
+// weights with every consecutive gap inside it, taken as equal and
+// ordered by the smaller pair in the levels' own numbering; an edge
+// joining two components is taken), and its off-tree edges ranked by
+// stretch, w_e times the resistance of the tree path between the ends
+// (the sum of 1 / w along it), as select_offtree ranks them for T~.  H~
+// has structurally equal weights (the pairs (i, parent(j)) and (j,
+// parent(i)) of one fine edge, for one), which FP64 evaluations of H~ may
+// round apart by far less than kTieRel.
+constexpr double kTieRel = 1e-9;
+static bool select_spanning(const HostPlan& P, const std::vector<int32_t>& off, double mu,
+                            const std::vector<uint64_t>& keys,
+                            const std::unordered_map<uint64_t, double>& acc, double frac,
+                            std::vector<char>& use, PegpPlan& out) {
+    const int L = P.nlev();
+    const int32_t nt = off[L];
+    std::vector<int> lev(nt);
+    std::vector<int32_t> own(nt);
+    for (int k = 0; k < L; ++k)
+        for (int32_t t = 0; t < off[k + 1] - off[k]; ++t) {
+            lev[off[k] + t] = k;
+            own[off[k] + t] = P.perm[k][t];
+        }
+    const size_t ne = keys.size();
+    std::vector<double> we(ne, 0.0);
+    std::vector<std::pair<int64_t, int64_t>> pr(ne);
+    std::vector<size_t> cand;
+    for (size_t q = 0; q < ne; ++q) {
+        const double w = acc.at(keys[q]);
+        const int32_t a = (int32_t)(keys[q] >> 32), b = (int32_t)(keys[q] & 0xffffffffu);
+        const int64_t oa = off[lev[a]] + own[a], ob = off[lev[b]] + own[b];
+        pr[q] = {std::min(oa, ob), std::max(oa, ob)};
+        if (!(w > 0.0)) continue;
+        we[q] = std::pow(mu, lev[a] + lev[b]) * w;
+        cand.push_back(q);
+    }
+    std::sort(cand.begin(), cand.end(), [&](size_t x, size_t y) { return we[x] > we[y]; });
+    std::vector<int32_t> group(ne, 0);
+    for (size_t r = 1; r < cand.size(); ++r) {
+        const double a = we[cand[r - 1]], b = we[cand[r]];
+        group[cand[r]] = group[cand[r - 1]] + (a - b > kTieRel * a ? 1 : 0);
+    }
+    std::sort(cand.begin(), cand.end(), [&](size_t x, size_t y) {
+        if (group[x] != group[y]) return group[x] < group[y];
+        return pr[x] < pr[y];
+    });
+    std::vector<int32_t> dsu(nt);
+    std::iota(dsu.begin(), dsu.end(), 0);
+    auto find = [&](int32_t a) {
+        while (dsu[a] != a) a = dsu[a] = dsu[dsu[a]];
+        return a;
+    };
+    std::vector<char> in_tree(ne, 0);
+    std::vector<std::vector<std::pair<int32_t, double>>> tadj(nt);
+    int32_t taken = 0;
+    for (size_t q : cand) {
+        const int32_t a = (int32_t)(keys[q] >> 32), b = (int32_t)(keys[q] & 0xffffffffu);
+        const int32_t ra = find(a), rb = find(b);
+        if (ra == rb) continue;
+        dsu[ra] = rb;
+        in_tree[q] = 1;
+        tadj[a].push_back({b, we[q]});
+        tadj[b].push_back({a, we[q]});
+        ++taken;
+    }
+    if (taken != nt - 1) return false;  // H~ not connected
+    // the tree rooted at the ground: parents, depths, edge weights upward,
+    // and ancestor tables for the meeting points of paths
+    std::vector<int32_t> parent(nt, -1), depth(nt, 0), bfs;
+    std::vector<double> up_w(nt, 0.0);
+    bfs.reserve(nt);
+    bfs.push_back(nt - 1);
+    parent[nt - 1] = nt - 1;
+    for (size_t i = 0; i < bfs.size(); ++i) {
+        const int32_t a = bfs[i];
+        for (auto& e : tadj[a])
+            if (parent[e.first] < 0) {
+                parent[e.first] = a;
+                depth[e.first] = depth[a] + 1;
+                up_w[e.first] = e.second;
+                bfs.push_back(e.first);
+            }
+    }
+    int LOG = 1;
+    while ((1 << LOG) < nt) ++LOG;
+    std::vector<std::vector<int32_t>> anc(LOG, std::vector<int32_t>(nt));
+    anc[0] = parent;
+    for (int k = 1; k < LOG; ++k)
+        for (int32_t v = 0; v < nt; ++v) anc[k][v] = anc[k - 1][anc[k - 1][v]];
+    auto meet = [&](int32_t a, int32_t b) {
+        if (depth[a] < depth[b]) std::swap(a, b);
+        for (int k = LOG - 1; k >= 0; --k)
+            if (depth[a] - (1 << k) >= depth[b]) a = anc[k][a];
+        if (a == b) return a;
+        for (int k = LOG - 1; k >= 0; --k)
+            if (anc[k][a] != anc[k][b]) {
+                a = anc[k][a];
+                b = anc[k][b];
+            }
+        return parent[a];
+    };
+    std::vector<size_t> offq;
+    for (size_t q : cand)
+        if (!in_tree[q]) offq.push_back(q);
+    std::sort(offq.begin(), offq.end());
+    const size_t cnt = offq.size();
+    std::vector<double> stretch(cnt);
+    for (size_t i = 0; i < cnt; ++i) {
+        const uint64_t key = keys[offq[i]];
+        const int32_t a = (int32_t)(key >> 32), b = (int32_t)(key & 0xffffffffu);
+        const int32_t c = meet(a, b);
+        double R = 0.0;
+        for (int32_t v = a; v != c; v = parent[v]) R += 1.0 / up_w[v];
+        for (int32_t v = b; v != c; v = parent[v]) R += 1.0 / up_w[v];
+        stretch[i] = we[offq[i]] * R;
+    }
+    std::vector<size_t> rank(cnt);
+    std::iota(rank.begin(), rank.end(), 0);
+    std::sort(rank.begin(), rank.end(), [&](size_t x, size_t y) {
+        if (stretch[x] != stretch[y]) return stretch[x] > stretch[y];
+        return pr[offq[x]] < pr[offq[y]];
+    });
+    const size_t keep = (size_t)std::ceil(frac * (double)cnt - 1e-12);
+    std::vector<int8_t> kept(cnt, 0);
+    for (size_t r = 0; r < std::min(keep, cnt); ++r) kept[rank[r]] = 1;
+    out.ot_a.resize(cnt);
+    out.ot_b.resize(cnt);
+    out.ot_w.resize(cnt);
+    out.ot_stretch = stretch;
+    out.ot_kept = kept;
+    for (size_t i = 0; i < cnt; ++i) {
+        out.ot_a[i] = pr[offq[i]].first;
+        out.ot_b[i] = pr[offq[i]].second;
+        out.ot_w[i] = we[offq[i]];
+    }
+    for (size_t q = 0; q < ne; ++q) use[q] = in_tree[q];
+    for (size_t i = 0; i < cnt; ++i)
+        if (kept[i]) use[offq[i]] = 1;
+    return true;
+}
+
+int build_pegp(const HostPlan& P, double mu, PegpPlan& out, double offtree_frac, int tree) {
     const int L = P.nlev();
     const int T = L - 1;
     out = PegpPlan();
@@ -981,7 +1123,8 @@ int build_pegp(const HostPlan& P, double mu, PegpPlan& out, double offtree_frac)
     std::sort(keys.begin(), keys.end());
     std::vector<char> use(keys.size(), 1);
     if (offtree_frac >= 0.0 &&
-        !select_offtree(P, out.off, par, mu, keys, acc, offtree_frac, use, out))
+        !(tree == 1 ? select_spanning(P, out.off, mu, keys, acc, offtree_frac, use, out)
+                    : select_offtree(P, out.off, par, mu, keys, acc, offtree_frac, use, out)))
         return kInval;
     for (size_t q = 0; q < keys.size(); ++q) {
         if (!use[q]) continue;

@@ -142,7 +142,7 @@ struct PegpPlan {
     int32_t opn = 0, opld = 0;
     std::vector<double> op;
     // Off-tree sparsifier (build_pegp with offtree_frac >= 0): the positive
-    // edges of H~ outside the MSP tree T~, each with its expanded ends in
+    // edges of H~ outside the tree (T~ or the spanning tree), each with its expanded ends in
     // the levels' own numbering (level offset + node id), weight (of H~),
     // stretch in T~ and whether it was added back.
     std::vector<int64_t> ot_a, ot_b;
@@ -158,9 +158,11 @@ constexpr int kPegpTailBlock = 192;           // rows per kernel (superblock) of
 constexpr int kPegpMinDense = 64;
 constexpr int kPegpMaxDense = 4096;
 // The factored grounded system of PEGP (offtree_frac < 0: all of H~), or,
-// with 0 <= offtree_frac <= 1, of the MSP tree T~ plus the ceil(frac *
-// count) off-tree edges of H~ of largest stretch in T~ (Sec. 3.3).
-int build_pegp(const HostPlan& plan, double mu, PegpPlan& out, double offtree_frac = -1.0);
+// with 0 <= offtree_frac <= 1, of a tree plus the ceil(frac * count)
+// off-tree edges of H~ of largest stretch in it (Sec. 3.3): the MSP tree T~
+// (tree 0) or a maximum-weight spanning tree of H~ (tree 1).
+int build_pegp(const HostPlan& plan, double mu, PegpPlan& out, double offtree_frac = -1.0,
+               int tree = 0);
 
 int build_adjacency(int64_t n, int64_t m, const int64_t* u, const int64_t* v,
                     const double* w, Adjacency& out);

@@ -1,6 +1,10 @@
 """The off-tree sparsifier's selection (Sec. 3.3), host part of lap_setup
-(LAP_PREC_OFFTREE, host only): the off-tree edges of H~, their stretches in
-the MSP tree T~ and the edges added back.
+(LAP_PREC_OFFTREE and LAP_PREC_SPANNING, host only): the off-tree edges of
+H~, their stretches in the tree (the MSP tree T~, or a maximum-weight
+spanning tree of H~) and the edges added back.  For the spanning tree an
+identical off-tree edge set also means an identical tree, and the unit-
+weight grid (every weight a power of two at mu = 0.5, so no rounding in
+either H~) has many equal weights, which the tie rule must order alike.
 
 Against the oracle (oracle/offtree.py) at mu >= 0.5: the edge set must be
 identical; stretches agree to 1e-9 relative; the kept sets must agree on
@@ -18,7 +22,9 @@ import workloads as W
 CASES = {
     "grid2d_24_loguniform_mu0.5": lambda: (*W.grid2d(24), W.loguniform_weights(1104, 7), 0.5),
     "chunglu_1500_mu0.8": lambda: (*W.chung_lu(1500, 8.0, 2.1, 5), None, 0.8),
+    "grid2d_16_unit_mu0.5": lambda: (*W.grid2d(16), W.unit_weights(480), 0.5),
 }
+TREES = ["msp", "spanning"]
 
 
 def _case(name):
@@ -29,17 +35,19 @@ def _case(name):
     return n, u, v, w, mu
 
 
+@pytest.mark.parametrize("tree", TREES)
 @pytest.mark.parametrize("frac", [0.0, 0.1, 0.3, 1.0])
 @pytest.mark.parametrize("name", list(CASES))
-def test_offtree_selection_matches_oracle(oracle_lib, name, frac):
+def test_offtree_selection_matches_oracle(oracle_lib, name, frac, tree):
     import paper_2207_07847_amd as lap
     from oracle import Graph, Hierarchy
-    from oracle.offtree import OffTree
+    from oracle.offtree import OffTree, SpanningOffTree
     n, u, v, w, mu = _case(name)
     h = Hierarchy(Graph(n, u, v, w))
-    ot = OffTree(n, u, v, w, h, mu, frac)
+    ot = (OffTree if tree == "msp" else SpanningOffTree)(n, u, v, w, h, mu, frac)
+    pc = lap.LAP_PREC_OFFTREE if tree == "msp" else lap.LAP_PREC_SPANNING
     H = lap.lap_setup(n, u, v, w, lap.lap_default_params(
-        mu=mu, precond=lap.LAP_PREC_OFFTREE, offtree_frac=frac, flags=lap.LAP_FLAG_HOST_ONLY))
+        mu=mu, precond=pc, offtree_frac=frac, flags=lap.LAP_FLAG_HOST_ONLY))
     try:
         E = lap.lap_export_offtree(H)
     finally:
@@ -67,10 +75,11 @@ def test_offtree_selection_matches_oracle(oracle_lib, name, frac):
 def test_offtree_fraction_out_of_range():
     import paper_2207_07847_amd as lap
     n, u, v = W.grid2d(6)
-    for frac in (-0.1, 1.5, float("nan")):
-        with pytest.raises(lap.LapError):
-            lap.lap_setup(n, u, v, W.unit_weights(len(u)), lap.lap_default_params(
-                precond=lap.LAP_PREC_OFFTREE, offtree_frac=frac, flags=lap.LAP_FLAG_HOST_ONLY))
+    for pc in (lap.LAP_PREC_OFFTREE, lap.LAP_PREC_SPANNING):
+        for frac in (-0.1, 1.5, float("nan")):
+            with pytest.raises(lap.LapError):
+                lap.lap_setup(n, u, v, W.unit_weights(len(u)), lap.lap_default_params(
+                    precond=pc, offtree_frac=frac, flags=lap.LAP_FLAG_HOST_ONLY))
 
 
 @pytest.mark.slow

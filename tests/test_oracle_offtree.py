@@ -196,3 +196,13 @@ def test_spanning_ends_tree_alone_and_pegp(oracle_lib, case):
     assert len(M1.kept) == len(M1.off)
     z1 = PEGP(n, u, v, w, h.aggs(), mu).apply(r)
     assert np.linalg.norm(M1.apply(r) - z1) <= 1e-10 * np.linalg.norm(z1)
+
+
+def test_kruskal_order_takes_near_equal_weights_as_ties():
+    """Weights within 1e-9 relative are one run, ordered by pair; a larger
+    gap starts a new run; heavier runs first."""
+    from oracle.offtree import kruskal_order
+    edges = [(0, 5, 1.0), (1, 2, 1.0 + 1e-13), (0, 3, 2.0), (2, 4, 1.0 - 3e-10),
+             (3, 4, 1.0 - 5e-8)]
+    order = kruskal_order(edges)
+    assert [edges[t][:2] for t in order] == [(0, 3), (0, 5), (1, 2), (2, 4), (3, 4)]
