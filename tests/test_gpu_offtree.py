@@ -1,7 +1,9 @@
-"""GPU checks of the off-tree sparsifier (LAP_PREC_OFFTREE, Sec. 3.3): the
-MSP tree T~ with the off-tree edges of H~ of largest stretch added back,
-solved like PEGP on that subgraph (explicit operator or factor, both
-tested) and applied through the lifting of Sec. 3.1.
+"""GPU checks of the off-tree sparsifiers (Sec. 3.3): a tree with the
+off-tree edges of H~ of largest stretch added back, solved like PEGP on
+that subgraph (explicit operator or factor, both tested) and applied
+through the lifting of Sec. 3.1; the tree is the MSP tree T~
+(LAP_PREC_OFFTREE) or a maximum-weight spanning tree of H~
+(LAP_PREC_SPANNING).
 
 Against the oracle (oracle/offtree.py), at mu where its stretches are
 accurate (the host tests check the selection itself): the applied
@@ -50,46 +52,55 @@ def _mode(mode):
             os.environ["LAPGPU_PEGP_OPERATOR"] = old
 
 
-def _gpu(n, u, v, w, mu, frac, mode, **kw):
+TREES = ["msp", "spanning"]
+
+
+def _oracle_cls(tree):
+    from oracle.offtree import OffTree, SpanningOffTree
+    return OffTree if tree == "msp" else SpanningOffTree
+
+
+def _gpu(n, u, v, w, mu, frac, mode, tree="msp", **kw):
     import paper_2207_07847_amd as lap
+    pc = lap.LAP_PREC_OFFTREE if tree == "msp" else lap.LAP_PREC_SPANNING
     with _mode(mode):
-        return GpuLap(n, u, v, w, mu=mu, precond=lap.LAP_PREC_OFFTREE, offtree_frac=frac, **kw)
+        return GpuLap(n, u, v, w, mu=mu, precond=pc, offtree_frac=frac, **kw)
 
 
+@pytest.mark.parametrize("tree", TREES)
 @pytest.mark.parametrize("mode", ["operator", "factor"])
 @pytest.mark.parametrize("frac", [0.0, 0.1, 0.3, 1.0])
 @pytest.mark.parametrize("name", list(CASES))
-def test_offtree_apply_parity(oracle_lib, name, frac, mode):
+def test_offtree_apply_parity(oracle_lib, name, frac, mode, tree):
     from oracle import Graph, Hierarchy
-    from oracle.offtree import OffTree
     n, u, v, w, mu = _case(name)
     h = Hierarchy(Graph(n, u, v, w))
-    M = OffTree(n, u, v, w, h, mu, frac)
-    M2 = OffTree(n, u, v, w, h, mu, frac, permc_spec="MMD_AT_PLUS_A")
+    M = _oracle_cls(tree)(n, u, v, w, h, mu, frac)
+    M2 = _oracle_cls(tree)(n, u, v, w, h, mu, frac, permc_spec="MMD_AT_PLUS_A")
     r = np.random.default_rng(13).standard_normal(n)
     r -= r.mean()
     z0 = M.apply(r)
     spread = np.linalg.norm(M2.apply(r) - z0) / np.linalg.norm(z0)
-    G = _gpu(n, u, v, w, mu, frac, mode)
+    G = _gpu(n, u, v, w, mu, frac, mode, tree)
     try:
         z = G.apply_precond(r)
     finally:
         G.close()
     err = np.linalg.norm(z - z0) / np.linalg.norm(z0)
-    msg = (f"{name} frac {frac} ({mode}): kept {len(M.kept)} of {len(M.off)} off-tree edges, "
+    msg = (f"{name} {tree} frac {frac} ({mode}): kept {len(M.kept)} of {len(M.off)} off-tree edges, "
            f"rel err {err:.3e}, oracle ordering spread {spread:.3e}")
     say(msg)
     assert err <= max(100 * spread, 1e-14), msg
 
 
+@pytest.mark.parametrize("tree", TREES)
 @pytest.mark.parametrize("name,frac", [("grid2d_24_loguniform_mu0.5", 0.1),
                                        ("chunglu_1500_mu0.8", 0.3)])
-def test_offtree_solve(oracle_lib, name, frac):
+def test_offtree_solve(oracle_lib, name, frac, tree):
     from oracle import Graph, Hierarchy, iteration_band, pcg
-    from oracle.offtree import OffTree
     n, u, v, w, mu = _case(name)
     g = Graph(n, u, v, w)
-    M = OffTree(n, u, v, w, Hierarchy(g), mu, frac)
+    M = _oracle_cls(tree)(n, u, v, w, Hierarchy(g), mu, frac)
     b = W.gaussian_rhs(n, 44)
     ref = pcg(g, b, 1e-8, 2000, M)
     D = np.empty((n, n))
@@ -104,7 +115,7 @@ def test_offtree_solve(oracle_lib, name, frac):
         its += list(iteration_band(g, b, 1e-8, 2000, op))
         its.append(pcg_exact_sums(g, op, b, 1e-8, 2000)[0])
     lo, hi = min(its), max(its)
-    G = _gpu(n, u, v, w, mu, frac, "operator", max_iter=2000)
+    G = _gpu(n, u, v, w, mu, frac, "operator", tree, max_iter=2000)
     try:
         st, x, info = G.solve(b, 1e-8)
     finally:
@@ -114,7 +125,7 @@ def test_offtree_solve(oracle_lib, name, frac):
     d = np.linalg.norm(x - same.x) / np.linalg.norm(same.x)
     bh = b - b.mean()
     host = np.linalg.norm(bh - g.apply(x)) / np.linalg.norm(bh)
-    msg = (f"{name} frac {frac}: gpu status {st} iterations {k}, oracle {ref.iterations}, "
+    msg = (f"{name} {tree} frac {frac}: gpu status {st} iterations {k}, oracle {ref.iterations}, "
            f"band [{lo - 1}, {hi + 1}]; relres {info['relres_true']:.3e} host {host:.3e}; "
            f"iterate diff at the same count {d:.2e}")
     say(msg)
