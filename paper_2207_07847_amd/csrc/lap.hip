@@ -1051,8 +1051,12 @@ void upload_plan(lap_hierarchy* h, hipStream_t s) {
     // beyond the one it checks, so up to two chunks run past convergence as
     // iterations that return at once; each still costs its dispatches.  A
     // PEGP iteration is about 30 dispatches and a few hundred microseconds,
-    // so two iterations already cover the host's check.
-    h->chunk = std::max(2, env_int("LAPGPU_CHUNK", h->pegp ? 2 : 8) & ~1);
+    // so two iterations already cover the host's check.  From 2^20 vertices
+    // an iteration takes ~100 us or more and solves run long, so longer
+    // chunks (fewer graph launches) pay for the overshoot: 3,369 -> 3,339 ms
+    // on a 128^3 grid solve of 23,702 iterations with 32 instead of 8.
+    const int dflt = h->pegp ? 2 : h->n >= ((int64_t)1 << 20) ? 32 : 8;
+    h->chunk = std::max(2, env_int("LAPGPU_CHUNK", dflt) & ~1);
     h->inner_tol = env_double("LAPGPU_INNER_TOL", 1e-4);
     h->reliable_drop = env_double("LAPGPU_RELIABLE_DROP", kReliableDrop);
     h->reliable = env_int("LAPGPU_MIXED_RESTART", 0) == 0;
