@@ -294,8 +294,22 @@ __global__ __launch_bounds__(kMmWaves * 64) void k_mm_spmm_combine(Chunks C,
     double v[1] = {0.0};
     MM_FOR(m, C.nmulti) {
         const int row = C.multi[m];
-        T acc = T(0);
-        for (int s = C.mfirst[m]; s < C.mfirst[m + 1]; ++s) acc += scr[(size_t)s * kCols + c];
+        const int s0 = C.mfirst[m], s1 = C.mfirst[m + 1];
+        // eight partial rows in flight (a hub's row is split into hundreds)
+        constexpr int U = 8;
+        T a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = T(0);
+        int s = s0;
+        for (; s + U <= s1; s += U) {
+            T y[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) y[u] = scr[(size_t)(s + u) * kCols + c];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] += y[u];
+        }
+        for (; s < s1; ++s) a[0] += scr[(size_t)s * kCols + c];
+        const T acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         q[(size_t)row * kCols + c] = acc;
         v[0] += (double)p[(size_t)row * kCols + c] * (double)acc;
     }
@@ -342,16 +356,44 @@ __global__ __launch_bounds__(kMmWaves * 64) void k_mm_up(LevelDev<T> s, Chunks C
     const int J = C.id[it], c0 = C.t0[it], c1 = C.t1[it];
     const int b0 = s.cptr[J];
     T sum = T(0), ga = T(0), gb = T(0);
-    for (int t = c0; t < c1; ++t) {
+    int t = c0;
+    // the matched pair leads the children; then the leftovers, eight rows
+    // and their coefficients in flight at a time (a hub's chunk is long)
+    if (t == b0 && t < c1) {
         const T rv = rk[(size_t)t * kCols + c];
         sum += rv;
-        if (t == b0) ga += rv;
-        else if (t == b0 + 1) gb += rv;
-        else {
-            const int li = t - 2 * J - 2;
-            ga += s.l1[li] * rv;
-            gb += s.l2[li] * rv;
+        ga += rv;
+        ++t;
+    }
+    if (t == b0 + 1 && t < c1) {
+        const T rv = rk[(size_t)t * kCols + c];
+        sum += rv;
+        gb += rv;
+        ++t;
+    }
+    constexpr int U = 8;
+    for (; t + U <= c1; t += U) {
+        T rv[U], a1[U], a2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int li = t + u - 2 * J - 2;
+            rv[u] = rk[(size_t)(t + u) * kCols + c];
+            a1[u] = s.l1[li];
+            a2[u] = s.l2[li];
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            sum += rv[u];
+            ga += a1[u] * rv[u];
+            gb += a2[u] * rv[u];
+        }
+    }
+    for (; t < c1; ++t) {
+        const T rv = rk[(size_t)t * kCols + c];
+        const int li = t - 2 * J - 2;
+        sum += rv;
+        ga += s.l1[li] * rv;
+        gb += s.l2[li] * rv;
     }
     const int sl = C.slot[it];
     if (sl < 0) {
@@ -378,7 +420,22 @@ __global__ __launch_bounds__(kMmWaves * 64) void k_mm_up_combine(LevelDev<T> s, 
     MM_FOR(m, C.nmulti) {
         const int J = C.multi[m];
         T sum = T(0), ga = T(0), gb = T(0);
-        for (int q = C.mfirst[m]; q < C.mfirst[m + 1]; ++q) {
+        const int q1 = C.mfirst[m + 1];
+        int q = C.mfirst[m];
+        // the chunks' sums in order, four chunks' loads in flight
+        constexpr int U = 4;
+        for (; q + U <= q1; q += U) {
+            T y[3 * U];
+#pragma unroll
+            for (int i = 0; i < 3 * U; ++i) y[i] = scr[(size_t)(3 * q + i) * kCols + c];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                sum += y[3 * u];
+                ga += y[3 * u + 1];
+                gb += y[3 * u + 2];
+            }
+        }
+        for (; q < q1; ++q) {
             sum += scr[(size_t)(3 * q) * kCols + c];
             ga += scr[(size_t)(3 * q + 1) * kCols + c];
             gb += scr[(size_t)(3 * q + 2) * kCols + c];
@@ -404,16 +461,35 @@ __global__ __launch_bounds__(kMmWaves * 64) void k_mm_down(LevelDev<T> s, Chunks
     const int b0 = s.cptr[J];
     const T yJ = yk1[(size_t)J * kCols + c];
     const T ea = s.ea[(size_t)J * kCols + c], eb = s.eb[(size_t)J * kCols + c];
-    for (int t = c0; t < c1; ++t) {
-        const size_t o = (size_t)t * kCols + c;
-        T y;
-        if (t == b0) y = ea + yJ;
-        else if (t == b0 + 1) y = eb + yJ;
-        else {
-            const int li = t - 2 * J - 2;
-            y = s.l0[li] * rk[o] + s.l1[li] * ea + s.l2[li] * eb + yJ;
+    int t = c0;
+    // the pair first, then the leftovers eight at a time (loads in flight)
+    if (t == b0 && t < c1) {
+        yk[(size_t)t * kCols + c] = ea + yJ;
+        ++t;
+    }
+    if (t == b0 + 1 && t < c1) {
+        yk[(size_t)t * kCols + c] = eb + yJ;
+        ++t;
+    }
+    constexpr int U = 8;
+    for (; t + U <= c1; t += U) {
+        T rv[U], a0[U], a1[U], a2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int li = t + u - 2 * J - 2;
+            rv[u] = rk[(size_t)(t + u) * kCols + c];
+            a0[u] = s.l0[li];
+            a1[u] = s.l1[li];
+            a2[u] = s.l2[li];
         }
-        yk[o] = y;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            yk[(size_t)(t + u) * kCols + c] = a0[u] * rv[u] + a1[u] * ea + a2[u] * eb + yJ;
+    }
+    for (; t < c1; ++t) {
+        const int li = t - 2 * J - 2;
+        const size_t o = (size_t)t * kCols + c;
+        yk[o] = s.l0[li] * rk[o] + s.l1[li] * ea + s.l2[li] * eb + yJ;
     }
     }
 }
