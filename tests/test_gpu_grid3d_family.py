@@ -14,7 +14,7 @@ oracle/ only:
     unperturbed and under the same noise model.
 
 On this family the iteration count moves with FP64 rounding by far more
-than one step: at 40^3 the oracle's own variants take 3,557 to 3,630
+than one step: at 40^3 the oracle's own variants take 3,518 to 3,630
 iterations, the exactly summed ones fewest, since the sequential sums over
 n products of widely spread magnitude are the largest rounding in the
 solve.  The bar is therefore the oracle's band over all its variants,
