@@ -739,14 +739,17 @@ def main():
             "traffic": pmc_traffic(args.workload, args.scale, dom_name, args.precision),
         },
     }
-    copy = device_copy_rate(torch)
+    copy = device_copy_rate(torch) if not capped else float("nan")
     line["device_copy"] = {
         "gbs": copy, "bytes": 2 * 2**30,
         "kernel_over_copy": dom["gbs"] / copy,
         "what": "torch device-to-device copy of 1 GiB into 1 GiB (2 GiB read plus written "
                 "per launch, beyond the 256 MB Infinity Cache), back to back: the rate HBM "
                 "gives a plain read-write stream on this GPU, beside the dominant kernel's"}
-    log(f"device copy (2 GiB moved): {copy:.0f} GB/s; kernel / copy {dom['gbs'] / copy:.3f}")
+    if capped:
+        del line["device_copy"]     # capped runs (counter passes) time no copy
+    else:
+        log(f"device copy (2 GiB moved): {copy:.0f} GB/s; kernel / copy {dom['gbs'] / copy:.3f}")
     if pegp_op:
         line["roofline"]["note"] = (
             "the operator (opn^2 FP64 entries, 134 MB here) is smaller than the 256 MB "
